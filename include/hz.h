@@ -1,0 +1,162 @@
+/*
+ * hz.h -- C ABI of the MI355X twogrid-preconditioned FGMRES Helmholtz solver.
+ *
+ * Method (Drzisga, Koeppl, Wohlmuth, arXiv 2104.01439):
+ *   * problem (Sec. 2, the impedance boundary value problem and its variational form):
+ *       -Laplace u - k^2 u = f in the unit square,  du/dn - i k u = g on its boundary,
+ *     discretised with P_p Lagrange elements (p = 1, 2, 3) on the uniform mesh whose square
+ *     cells are split by their "/" diagonal; system matrix A(k, eps) = K - M(k, eps) - i B(k)
+ *     (Sec. 2, definition of the system matrix).
+ *   * preconditioner (Sec. 4, Algorithm 1 with two levels): one V(nu, nu)-cycle on the shifted
+ *     operator A_eps with damped Jacobi smoothing, FE prolongation P, restriction P^T and an
+ *     exact coarse solve on the 2h mesh. The shift is passed as a complex multiplier s of the
+ *     k^2 mass term: A_eps = K - s k^2 M - i k B, i.e. eps = Im(s) k^2 when Re(s) = 1; the
+ *     boundary term is not shifted (the shifted problem of Sec. 2 keeps the impedance
+ *     condition). The fine level is matrix-free; the coarse operator is assembled as a
+ *     block-tridiagonal matrix and factored on the device.
+ *   * outer solver (Sec. 4, after Saad 1993): right-preconditioned flexible GMRES(restart)
+ *     on A_0 = A(k, 0), zero initial guess, stopping on the relative residual (Sec. 5, the
+ *     residual of the unpreconditioned system).
+ *
+ * Conventions shared by every entry point
+ *   * Vectors are complex, interleaved (re, im), hz_c64 == std::complex<double> ==
+ *     torch.complex128. A fine vector holds N = M*M values, M = p*n + 1, n = 1/h; the value of
+ *     lattice point (a, b), located at (a h/p, b h/p), sits at index b*M + a. A coarse vector
+ *     has the same layout with n/2 cells (Mc = p*n/2 + 1).
+ *   * Pointers named d_* are DEVICE pointers owned by the caller; h_* are host pointers.
+ *     The library owns everything inside hz_problem / hz_engine and frees it on destroy.
+ *   * hip_stream is a hipStream_t (NULL = the default stream). Calls are asynchronous with
+ *     respect to the host unless stated; hz_solve* synchronise the stream before returning.
+ *   * No exception crosses the ABI. Every call returns a status; hz_last_error() gives a
+ *     human-readable message for the calling thread. Non-convergence is not an error.
+ *   * One problem must not be used by two threads at once; a concurrent call returns HZ_EBUSY.
+ */
+#ifndef HZ_H
+#define HZ_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hz_problem hz_problem;
+typedef struct hz_engine hz_engine;
+
+typedef struct { double re, im; } hz_c64;
+
+typedef enum {
+  HZ_OK = 0,
+  HZ_EINVAL = 1,      /* invalid argument (bad sizes, NaN input, Im(s) <= 0, ...) */
+  HZ_ENOMEM = 2,      /* device allocation failed or a budget would be exceeded   */
+  HZ_EDEVICE = 3,     /* HIP runtime error                                        */
+  HZ_ESINGULAR = 4,   /* zero or non-finite pivot in the coarse factorisation     */
+  HZ_EBUSY = 5        /* the object is in use by another call                     */
+} hz_status;
+
+typedef enum {
+  HZ_FP64 = 0,        /* everything in complex FP64                                        */
+  HZ_MIXED = 1        /* preconditioner (fine stencils, smoother, transfers, coarse
+                         triangular solves) in complex FP32 with FP32 accumulation; outer
+                         FGMRES, A_0, Arnoldi and Givens in FP64; coarse factor computed in
+                         FP64 and stored in FP32 for the solves                              */
+} hz_precision;
+
+typedef struct {
+  int nu;             /* pre- and post-smoothing sweeps (Algorithm 1); default 2          */
+  double omega;       /* Jacobi damping; default 0.6                                      */
+  int restart;        /* FGMRES restart length m (1..64); default 50                      */
+  int maxit;          /* cap on the total number of preconditioner applications; 5000    */
+  double tol;         /* relative residual tolerance; default 1e-8                        */
+  int prec;           /* hz_precision; default HZ_FP64                                    */
+} hz_options;
+
+typedef struct {
+  int iterations;       /* preconditioner applications, summed over restart cycles          */
+  int converged;        /* 1 if the true relative residual reached tol, else 0              */
+  double rel_res_true;  /* ||F - A_0 u|| / ||F|| recomputed at exit                          */
+  double rel_res_est;   /* last Givens estimate |g_{j+1}| / ||F||                            */
+  double setup_s;       /* wall seconds spent in hz_create_problem (coarse factor included) */
+  double solve_s;       /* wall seconds of this solve                                        */
+} hz_result;
+
+/* Operators exposed by hz_apply (parity hooks; all act on the problem's own data). */
+typedef enum {
+  HZ_OP_A0 = 0,             /* y = A_0 x                               (fine -> fine)     */
+  HZ_OP_AEPS = 1,           /* y = A_eps x                             (fine -> fine)     */
+  HZ_OP_JACOBI = 2,         /* y = x + omega D^-1 (f - A_eps x), D = diag(A_eps)           */
+  HZ_OP_RESTRICT = 3,       /* y = P^T x                               (fine -> coarse)   */
+  HZ_OP_PROLONG = 4,        /* y = P x                                 (coarse -> fine)   */
+  HZ_OP_VCYCLE = 5,         /* y = V-cycle(x) from a zero initial guess (fine -> fine)    */
+  HZ_OP_COARSE_SOLVE = 6,   /* y = (A_eps^{2h})^-1 x                   (coarse -> coarse) */
+  HZ_OP_COARSE_A = 7,       /* y = A_eps^{2h} x                        (coarse -> coarse) */
+  HZ_OP_RESID_RESTRICT = 8  /* y = P^T (f - A_eps x)                   (fine -> coarse)   */
+} hz_op;
+
+/* Fills the defaults listed in hz_options. */
+hz_status hz_default_options(hz_options* o);
+
+/* Creates a problem for wavenumber k > 0 on n = 1/h cells per side (1/h must be an even
+ * integer >= 2, up to 4096), element order p in {1,2,3} and shift multiplier s with
+ * Im(s) > 0 (required: the coarse block LU runs without pivoting, which is safe because the
+ * Hermitian part of i*A_eps is Im(s) k^2 M + k B, positive definite). Builds the stencil
+ * tables, assembles and factors the coarse operator on the device and allocates the Krylov
+ * workspace for o->restart (and an FP32 factor copy when o->prec == HZ_MIXED). On success
+ * *out owns all of it. Synchronises hip_stream. Errors: HZ_EINVAL, HZ_ENOMEM, HZ_ESINGULAR,
+ * HZ_EDEVICE; *out is left NULL. */
+hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_options* o,
+                            void* hip_stream, hz_problem** out);
+
+/* Sizes of a created problem: fine dofs, coarse dofs, device bytes held. */
+hz_status hz_problem_info(const hz_problem* pr, long* n_dofs, long* n_coarse,
+                          size_t* footprint_bytes);
+
+/* Device bytes hz_create_problem would hold for these parameters (no allocation);
+ * 0 for invalid parameters. Used for admission by footprint. */
+size_t hz_footprint_estimate(double k, double h, int p, const hz_options* o);
+
+/* Writes the load vector of the plane-wave impedance data into d_F (fine vector):
+ * F_i = integral over the boundary of g phi_i (Sec. 2, the linear form with f = 0),
+ * g = du/dn - i k u for u = exp(i k (x cos(theta) + y sin(theta))); each boundary edge is
+ * integrated with 10-point Gauss-Legendre. Asynchronous on hip_stream. */
+hz_status hz_planewave_rhs(const hz_problem* pr, double theta, hz_c64* d_F, void* hip_stream);
+
+/* Solves A_0 u = F by FGMRES(o->restart) preconditioned with the twogrid V-cycle; zero
+ * initial guess; stops when the relative residual is <= o->tol (the rotation estimate inside
+ * a cycle, confirmed by the recomputed true residual), or after o->maxit preconditioner
+ * applications (then converged = 0, status HZ_OK). o->nu and o->omega are those given at
+ * creation. d_F, d_u: fine vectors (d_u is overwritten). h_res_hist (nullable) receives one
+ * relative residual estimate per iteration and must hold o->maxit doubles. A zero F gives
+ * u = 0 after 0 iterations; a non-finite ||F|| returns HZ_EINVAL. Synchronises hip_stream. */
+hz_status hz_solve(hz_problem* pr, const hz_c64* d_F, hz_c64* d_u, const hz_options* o,
+                   hz_result* res, double* h_res_hist, void* hip_stream);
+
+/* Applies one building block of the method (see hz_op). d_x, d_y: device vectors of the
+ * op's input and output spaces; d_f: the second input of HZ_OP_JACOBI and
+ * HZ_OP_RESID_RESTRICT (ignored otherwise, may be NULL). prec selects the FP64 or FP32
+ * kernels; I/O is always complex FP64 (converted on the device for FP32). d_y must not alias
+ * d_x or d_f. Asynchronous on hip_stream. */
+hz_status hz_apply(const hz_problem* pr, int op, const hz_c64* d_x, const hz_c64* d_f,
+                   hz_c64* d_y, int prec, void* hip_stream);
+
+/* Runs nprob * nrhs_per_prob independent FGMRES solves in lockstep: solve (i, r) uses
+ * problem probs[i] and right-hand side d_F[i*nrhs_per_prob + r], writing
+ * d_u[i*nrhs_per_prob + r] and res[i*nrhs_per_prob + r]. All problems must share (k, h, p)
+ * and were created with restart >= o->restart. Per-step kernels are launched once for all
+ * active solves; the coarse triangular solves of the right-hand sides of one problem share
+ * each read of its factor. Every result equals what hz_solve gives for that solve alone
+ * (same arithmetic, same order). h_res_hist may be NULL. Synchronises hip_stream. */
+hz_status hz_solve_batched(hz_problem* const* probs, int nprob, const hz_c64* const* d_F,
+                           int nrhs_per_prob, hz_c64* const* d_u, const hz_options* o,
+                           hz_result* res, void* hip_stream);
+
+/* Frees everything the problem owns (NULL is a no-op). */
+void hz_destroy_problem(hz_problem* pr);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* hz_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HZ_H */

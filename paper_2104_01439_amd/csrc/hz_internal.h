@@ -1,0 +1,153 @@
+// Internal declarations of the HIP Helmholtz solver (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hz.h"
+
+namespace hz {
+
+using cd = std::complex<double>;
+
+// ------------------------------------------------------------------------------------------
+// Host tables (hz_tables.cpp)
+// ------------------------------------------------------------------------------------------
+
+struct RefElement {
+  int p, nloc;
+  int ni[10], nj[10];     // local node (i, j) sits at (i/p, j/p) of the reference triangle
+  int ma[10], mb[10];     // monomials x^ma y^mb
+  double C[10][10];       // phi_k = sum_m C[m][k] x^ma[m] y^mb[m]
+  explicit RefElement(int p);
+  double phi(int k, double x, double y) const;
+};
+
+// Stencil tables of one level (fine or coarse), real parts of K, M and the unit-weight
+// boundary mass, indexed [cls * 9 + reg][(dy + p) * (2p+1) + (dx + p)], with
+// cls = (b mod p) * p + (a mod p) and reg = ry * 3 + rx (0: first line, 1: interior,
+// 2: last line of the lattice along that axis). RW holds the prolongation weights
+// [cls][(dy + 2p) * (4p+1) + (dx + 2p)] (coarse class, fine offsets).
+struct LevelTables {
+  int p = 1, n = 0, M = 0;
+  double h = 0;
+  std::vector<double> K, Mm, B, RW;
+};
+
+LevelTables build_level_tables(int p, int n, double h);
+std::vector<cd> combine_operator(const LevelTables& t, double k, cd s);
+
+// ------------------------------------------------------------------------------------------
+// Device-side views
+// ------------------------------------------------------------------------------------------
+
+template <typename T> struct vec2;
+template <> struct vec2<double> { using type = double2; };
+template <> struct vec2<float> { using type = float2; };
+template <typename T> using V2 = typename vec2<T>::type;
+
+// One level's operator on the device: complex stencil coefficients and the Jacobi
+// multiplier omega / diag(A) per (class, region).
+template <typename T> struct DevOp {
+  const V2<T>* coef = nullptr;   // [p*p*9][(2p+1)^2]
+  const V2<T>* wdinv = nullptr;  // [p*p*9]
+  int M = 0;                     // lattice points per side
+};
+
+// Coarse block-tridiagonal factor: block j (j < nc) holds lattice rows p j .. p j + p - 1,
+// the last block (j = nc) holds the final lattice row alone. Block j stores the dense
+// inverse S_j of the Schur complement D_j, row-major, at element offset off(j).
+struct CoarseLayout {
+  int p = 1, nc = 0, Mc = 0;     // coarse cells per side, coarse lattice points per side
+  int nblocks() const { return nc + 1; }
+  int rows(int j) const { return j < nc ? p : 1; }
+  long size(int j) const { return long(rows(j)) * Mc; }
+  long first_dof(int j) const { return long(p) * j * Mc; }
+  size_t off(int j) const { return size_t(j) * size_t(p * Mc) * size_t(p * Mc); }
+  size_t total() const { return off(nc) + size_t(Mc) * size_t(Mc); }
+};
+
+// ------------------------------------------------------------------------------------------
+// Launchers (hz_fine.hip, hz_coarse.hip, hz_krylov.hip)
+// ------------------------------------------------------------------------------------------
+
+enum StencilMode { ST_APPLY = 0, ST_RESID = 1, ST_SMOOTH = 2 };
+
+// y = A x  |  y = f - A x  |  y = x + wdinv (f - A x)   on one level, lattice M x M.
+template <typename T, typename TX, typename TF, typename TY>
+void launch_stencil(int p, int mode, const DevOp<T>& op, const V2<TX>* x, const V2<TF>* f,
+                    V2<TY>* y, int nbatch, long bstride, hipStream_t st);
+// y = wdinv * f (the first sweep from a zero guess).
+template <typename T, typename TF>
+void launch_jacobi0(int p, const DevOp<T>& op, const V2<TF>* f, V2<T>* y, int nbatch,
+                    long bstride, hipStream_t st);
+// yc = P^T r (fine -> coarse), yf (+)= P xc (coarse -> fine).
+template <typename T>
+void launch_restrict(int p, int Mf, int Mc, const T* rw, const V2<T>* r, V2<T>* yc, int nbatch,
+                     long fstride, long cstride, hipStream_t st);
+template <typename T>
+void launch_prolong(int p, int Mf, int Mc, const T* rw, const V2<T>* xc, V2<T>* yf, bool add,
+                    int nbatch, long fstride, long cstride, hipStream_t st);
+// Plane-wave impedance load vector.
+void launch_planewave(int p, int n, double k, double theta, const double* gl_t,
+                      const double* gl_w, const double* lag, double2* F, hipStream_t st);
+// Conversions.
+void launch_d2f(const double2* x, float2* y, long n, hipStream_t st);
+void launch_f2d(const float2* x, double2* y, long n, hipStream_t st);
+
+// Coarse factorisation: assembles and inverts every block in sequence. Returns HZ_OK or
+// HZ_ESINGULAR (pivot check on device, read back at the end).
+struct CoarseFactorWork {
+  double2* T = nullptr;      // temp block (max block size ^2)
+  double2* W = nullptr;      // GJ panel buffers
+  double2* R = nullptr;
+  int* flag = nullptr;       // device error flag
+};
+hz_status coarse_factor(const CoarseLayout& L, const DevOp<double>& cop, double2* S,
+                        const CoarseFactorWork& w, hipStream_t st);
+// Solves A_c y = b with the stored inverses; nrhs right-hand sides with stride cstride.
+template <typename T>
+void coarse_solve(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b,
+                  V2<T>* y, int nrhs, long cstride, hipStream_t st);
+void launch_factor_to_f32(const double2* S, float2* Sf, size_t n, hipStream_t st);
+
+// Krylov kernels. Vectors of length N; V is row-major [nv][ldv].
+int mdot_blocks(long N);
+template <typename TV>
+void launch_mdot(const V2<TV>* V, long ldv, int nv, const double2* w, long N, double2* partial,
+                 int nblk, hipStream_t st);
+void launch_reduce(const double2* partial, int nblk, int nv, double2* out, hipStream_t st);
+// w -= V h (h on device, nv entries); optionally accumulates |w|^2 partials (nv index 0).
+void launch_maxpy(const double2* V, long ldv, int nv, const double2* h, double2* w, long N,
+                  double2* norm_partial, int nblk, hipStream_t st);
+void launch_scale_dev(const double2* w, const double* s_dev, double2* v, long N, hipStream_t st);
+void launch_scale(const double2* w, double s, double2* v, long N, hipStream_t st);
+void launch_fill_zero(double2* y, long N, hipStream_t st);
+void launch_fill_zero(float2* y, long N, hipStream_t st);
+template <typename TZ>
+void launch_update(const V2<TZ>* Z, long ldz, int nz, const double2* y, double2* u, long N,
+                   hipStream_t st);
+void launch_axpby_copy(const double2* x, double2* y, long N, hipStream_t st);
+
+// ------------------------------------------------------------------------------------------
+// Errors
+// ------------------------------------------------------------------------------------------
+
+void set_error(const std::string& msg);
+
+struct HipError {
+  hipError_t e;
+  std::string where;
+};
+
+#define HZ_HIP(call)                                                           \
+  do {                                                                         \
+    hipError_t _e = (call);                                                    \
+    if (_e != hipSuccess) throw ::hz::HipError{_e, #call};                     \
+  } while (0)
+
+}  // namespace hz

@@ -1,0 +1,210 @@
+"""ctypes binding of libhz.so (C ABI in include/hz.h); argument marshalling only.
+
+Every computation runs in the library's HIP kernels. torch provides device memory and
+streams: vectors are complex128 CUDA tensors, the stream is torch's current stream.
+torch is imported before the library so that both share one HIP runtime.
+"""
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhz.so")
+
+HZ_OK, HZ_EINVAL, HZ_ENOMEM, HZ_EDEVICE, HZ_ESINGULAR, HZ_EBUSY = range(6)
+HZ_FP64, HZ_MIXED = 0, 1
+OPS = {"A0": 0, "AEPS": 1, "JACOBI": 2, "RESTRICT": 3, "PROLONG": 4, "VCYCLE": 5,
+       "COARSE_SOLVE": 6, "COARSE_A": 7, "RESID_RESTRICT": 8}
+_PREC = {"fp64": HZ_FP64, "mixed": HZ_MIXED, HZ_FP64: HZ_FP64, HZ_MIXED: HZ_MIXED}
+
+
+class HZError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hz status {status}: {msg}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_int), ("omega", ctypes.c_double), ("restart", ctypes.c_int),
+                ("maxit", ctypes.c_int), ("tol", ctypes.c_double), ("prec", ctypes.c_int)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int),
+                ("rel_res_true", ctypes.c_double), ("rel_res_est", ctypes.c_double),
+                ("setup_s", ctypes.c_double), ("solve_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class C64(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "hz_default_options": (ctypes.c_int, [ctypes.POINTER(Options)]),
+    "hz_create_problem": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_int, C64,
+                                         ctypes.POINTER(Options), _P, ctypes.POINTER(_P)]),
+    "hz_problem_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_long),
+                                       ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_size_t)]),
+    "hz_footprint_estimate": (ctypes.c_size_t, [ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                                ctypes.POINTER(Options)]),
+    "hz_planewave_rhs": (ctypes.c_int, [_P, ctypes.c_double, _P, _P]),
+    "hz_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(Options), ctypes.POINTER(Result),
+                                ctypes.POINTER(ctypes.c_double), _P]),
+    "hz_apply": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_int, _P]),
+    "hz_solve_batched": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_P),
+                                        ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(Options),
+                                        ctypes.POINTER(Result), _P]),
+    "hz_destroy_problem": (None, [_P]),
+    "hz_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Loads libhz.so; raises if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2104_01439_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != HZ_OK:
+        raise HZError(status, lib().hz_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def options(nu=2, omega=0.6, restart=50, maxit=5000, tol=1e-8, prec="fp64"):
+    o = Options()
+    _check(lib().hz_default_options(ctypes.byref(o)))
+    o.nu, o.omega, o.restart, o.maxit, o.tol, o.prec = nu, omega, restart, maxit, tol, _PREC[prec]
+    return o
+
+
+def footprint_estimate(k, h, p, **kw):
+    o = options(**kw)
+    return int(lib().hz_footprint_estimate(k, h, p, ctypes.byref(o)))
+
+
+def sizes(n, p):
+    """(fine lattice M, fine dofs, coarse lattice Mc, coarse dofs) for n cells per side."""
+    M, Mc = p * n + 1, p * (n // 2) + 1
+    return M, M * M, Mc, Mc * Mc
+
+
+class Problem:
+    """create_problem(k, h, p, s): tables, coarse factor and Krylov workspace on the GPU."""
+
+    def __init__(self, k, h, p, s, nu=2, omega=0.6, restart=50, maxit=5000, tol=1e-8,
+                 prec="fp64"):
+        self.k, self.h, self.p, self.s = float(k), float(h), int(p), complex(s)
+        self.n = int(round(1.0 / h))
+        self.opts = options(nu, omega, restart, maxit, tol, prec)
+        self._h = ctypes.c_void_p()
+        _check(lib().hz_create_problem(self.k, self.h, self.p, C64(self.s.real, self.s.imag),
+                                       ctypes.byref(self.opts), _stream(), ctypes.byref(self._h)))
+        self.M, self.N, self.Mc, self.Nc = sizes(self.n, self.p)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        n, nc, fp = ctypes.c_long(), ctypes.c_long(), ctypes.c_size_t()
+        _check(lib().hz_problem_info(self._h, ctypes.byref(n), ctypes.byref(nc), ctypes.byref(fp)))
+        return {"n_dofs": n.value, "n_coarse": nc.value, "footprint_bytes": fp.value}
+
+    def empty(self, coarse=False):
+        return torch.empty(self.Nc if coarse else self.N, dtype=torch.complex128, device="cuda")
+
+    def planewave_rhs(self, theta, out=None):
+        F = self.empty() if out is None else out
+        _check(lib().hz_planewave_rhs(self._h, float(theta), _ptr(F), _stream()))
+        return F
+
+    def solve(self, F, u=None, tol=None, restart=None, maxit=None, prec=None, history=True):
+        o = Options.from_buffer_copy(self.opts)
+        if tol is not None:
+            o.tol = tol
+        if restart is not None:
+            o.restart = restart
+        if maxit is not None:
+            o.maxit = maxit
+        if prec is not None:
+            o.prec = _PREC[prec]
+        u = self.empty() if u is None else u
+        res = Result()
+        hist = (ctypes.c_double * o.maxit)() if history else None
+        _check(lib().hz_solve(self._h, _ptr(F), _ptr(u), ctypes.byref(o), ctypes.byref(res),
+                              hist, _stream()))
+        out = res.as_dict()
+        if history:
+            out["hist"] = list(hist[: res.iterations])
+        return u, out
+
+    def apply(self, op, x, f=None, prec="fp64"):
+        op_id = OPS[op]
+        coarse_out = op in ("RESTRICT", "COARSE_SOLVE", "COARSE_A", "RESID_RESTRICT")
+        y = self.empty(coarse=coarse_out)
+        _check(lib().hz_apply(self._h, op_id, _ptr(x), _ptr(f), _ptr(y), _PREC[prec], _stream()))
+        return y
+
+    def close(self):
+        if self._h:
+            lib().hz_destroy_problem(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batched(problems, Fs, nrhs_per_prob, us=None, tol=None, restart=None, maxit=None,
+                  prec=None):
+    """Lockstep solves: Fs[i*nrhs + r] with problems[i]; returns (us, [result dict])."""
+    o = Options.from_buffer_copy(problems[0].opts)
+    if tol is not None:
+        o.tol = tol
+    if restart is not None:
+        o.restart = restart
+    if maxit is not None:
+        o.maxit = maxit
+    if prec is not None:
+        o.prec = _PREC[prec]
+    nsol = len(problems) * nrhs_per_prob
+    assert len(Fs) == nsol
+    us = [problems[i // nrhs_per_prob].empty() for i in range(nsol)] if us is None else us
+    P = (ctypes.c_void_p * len(problems))(*[p.handle.value for p in problems])
+    FF = (ctypes.c_void_p * nsol)(*[F.data_ptr() for F in Fs])
+    UU = (ctypes.c_void_p * nsol)(*[u.data_ptr() for u in us])
+    res = (Result * nsol)()
+    _check(lib().hz_solve_batched(P, len(problems), FF, nrhs_per_prob, UU, ctypes.byref(o), res,
+                                  _stream()))
+    return us, [r.as_dict() for r in res]

@@ -1,0 +1,60 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke check.
+
+Holds none of the method's arithmetic: only random draws and the workload recipes
+(parameters of each benchmark configuration). NumPy only; callers move data to a device.
+"""
+
+import math
+
+import numpy as np
+
+
+def random_complex(n, seed=1234):
+    """U[-1,1] + i U[-1,1], complex128."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1, 1, n) + 1j * rng.uniform(-1, 1, n)
+
+
+# Workloads: the plane-wave impedance problem on the unit square, zero initial guess.
+CFG_SMALL = dict(name="p1_k16_n64", k=16.0, n=64, p=1, s=1 + 0.5j, theta=math.pi / 7,
+                 nu=2, omega=0.6, restart=50, tol=1e-8)
+CFG_P1_LARGE = dict(name="p1_k400_n2048", k=400.0, n=2048, p=1, s=1 + 0.5j,
+                    theta=math.pi / 7, nu=2, omega=0.6, restart=50, tol=1e-10)
+CFG_SWEEP = dict(name="p2_k150_n512_sweep", k=150.0, n=512, p=2, nu=2, omega=0.6,
+                 restart=50, tol=1e-8)
+CFG_MIXED = dict(name="p3_k200_n256", k=200.0, n=256, p=3, s=1 + 0.5j, theta=math.pi / 7,
+                 nu=2, omega=0.6, restart=50, tol=1e-10)
+
+
+def sweep_betas(count=64, lo=0.05, hi=1.5):
+    """beta_i evenly spaced in [lo, hi]."""
+    return [lo + i * (hi - lo) / (count - 1) for i in range(count)]
+
+
+def sweep_thetas(count=4, seed=0):
+    """Incidence angles shared by every shift of the sweep."""
+    return list(np.random.default_rng(seed).uniform(0.0, 2 * math.pi, count))
+
+
+def serving_requests(count=2000, seed=1, rate=None, kmin=10.0, kmax=300.0, bmin=0.1, bmax=1.5,
+                     khp_max=0.3, nmax=2048):
+    """Request stream: per request draw (gap, log k, p, beta, theta) in that order.
+
+    n = 2^m is the smallest power of two with k / (n p) <= khp_max, capped at nmax;
+    gaps are exponential with mean 1/rate (all zero when rate is None).
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(count):
+        gap = rng.exponential(1.0 / rate) if rate else 0.0
+        k = math.exp(rng.uniform(math.log(kmin), math.log(kmax)))
+        p = int(rng.integers(1, 4))
+        beta = rng.uniform(bmin, bmax)
+        theta = rng.uniform(0.0, 2 * math.pi)
+        n = 2
+        while k / (n * p) > khp_max and n < nmax:
+            n *= 2
+        t += gap
+        out.append(dict(id=i, t=t, k=k, p=p, n=n, beta=beta, theta=theta))
+    return out

@@ -1,0 +1,235 @@
+"""GPU parity: every building block and whole solves through the C ABI against the oracle.
+
+Inputs are seeded U[-1,1] + iU[-1,1] vectors; tolerances: 1e-12 relative for operator
+applies and transfers, 1e-10 for the coarse solve and the V-cycle (bounded by the
+conditioning of the coarse operator, measured values printed), FGMRES iterations within
++-1 and solutions within 1e-8 at tolerance 1e-10.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import Problem as OProblem
+from oracle.fem import Discretisation, prolongation
+from oracle.twogrid import BandedLU, TwoGrid, jacobi_sweep
+from paper_2104_01439_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+# (k, n, p, s): sizes span several lattice tiles with a ragged tail, several Gauss-Jordan
+# panels with a ragged last panel, and the degenerate smallest meshes.
+CASES = [
+    (3.0, 2, 1, 1 + 0.5j),
+    (7.0, 4, 1, 1 + 0.5j),
+    (30.0, 130, 1, 1 + 0.5j),
+    (5.0, 2, 2, 1 + 0.8j),
+    (35.0, 70, 2, 1 + 0.5j),
+    (4.0, 2, 3, 1 + 0.3j),
+    (45.0, 66, 3, 1 + 0.5j),
+]
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def hz(torch):
+    from paper_2104_01439_amd import hz as h
+    h.lib()
+    return h
+
+
+class _Case:
+    def __init__(self, hz, torch, k, n, p, s):
+        _log(f"[case] k={k} n={n} p={p} s={s}")
+        self.torch = torch
+        self.k, self.n, self.p, self.s = k, n, p, s
+        self.gp = hz.Problem(k, 1.0 / n, p, s, nu=2, omega=0.6)
+        self.tg = TwoGrid(k, n, p, s, nu=2, omega=0.6)
+        self.fine, self.coarse = self.tg.fine, self.tg.coarse
+        self.A0 = self.fine.operator(k, 1.0)
+
+    def dev(self, x):
+        return self.torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).cuda()
+
+    def host(self, t):
+        self.torch.cuda.synchronize()
+        return t.cpu().numpy()
+
+
+_cache = {}
+
+
+def case(hz, torch, c):
+    if c not in _cache:
+        _cache[c] = _Case(hz, torch, *c)
+    return _cache[c]
+
+
+@pytest.mark.parametrize("c", CASES)
+def test_operator_applies(hz, torch, c):
+    C = case(hz, torch, c)
+    x = inputs.random_complex(C.fine.N, seed=1234)
+    f = inputs.random_complex(C.fine.N, seed=99)
+    xc = inputs.random_complex(C.coarse.N, seed=4321)
+    dx, df, dxc = C.dev(x), C.dev(f), C.dev(xc)
+    checks = {
+        "A0": (C.gp.apply("A0", dx), C.A0 @ x),
+        "AEPS": (C.gp.apply("AEPS", dx), C.tg.Aeps @ x),
+        "JACOBI": (C.gp.apply("JACOBI", dx, df), jacobi_sweep(C.tg.Aeps, C.tg.dinv, 0.6, x, f)),
+        "RESTRICT": (C.gp.apply("RESTRICT", dx), C.tg.P.T @ x),
+        "PROLONG": (C.gp.apply("PROLONG", dxc), C.tg.P @ xc),
+        "COARSE_A": (C.gp.apply("COARSE_A", dxc), C.tg.Ac @ xc),
+        "RESID_RESTRICT": (C.gp.apply("RESID_RESTRICT", dx, df), C.tg.P.T @ (f - C.tg.Aeps @ x)),
+    }
+    for name, (g, o) in checks.items():
+        e = rel(C.host(g), o)
+        _log(f"  {name}: rel err {e:.2e}")
+        assert e <= 1e-12, (name, e)
+
+
+@pytest.mark.parametrize("c", CASES)
+def test_coarse_solve_and_vcycle(hz, torch, c):
+    C = case(hz, torch, c)
+    rc = inputs.random_complex(C.coarse.N, seed=7)
+    ec = C.host(C.gp.apply("COARSE_SOLVE", C.dev(rc)))
+    ec_o = C.tg.coarse_solve(rc)
+    e1 = rel(ec, ec_o)
+    res = np.linalg.norm(C.tg.Ac @ ec - rc) / np.linalg.norm(rc)
+    f = inputs.random_complex(C.fine.N, seed=8)
+    z = C.host(C.gp.apply("VCYCLE", C.dev(f)))
+    e2 = rel(z, C.tg.vcycle(f))
+    _log(f"  coarse solve rel err {e1:.2e} (residual {res:.2e}), vcycle rel err {e2:.2e}")
+    assert e1 <= 1e-10 and res <= 1e-12
+    assert e2 <= 1e-10
+
+
+@pytest.mark.parametrize("c", CASES)
+def test_planewave_rhs(hz, torch, c):
+    C = case(hz, torch, c)
+    for th in (math.pi / 7, 2.5, 5.9):
+        F = C.host(C.gp.planewave_rhs(th))
+        e = rel(F, C.fine.planewave_rhs(C.k, th))
+        assert e <= 1e-12, e
+
+
+@pytest.mark.parametrize("c", CASES)
+def test_mixed_precision_blocks(hz, torch, c):
+    """FP32 preconditioner kernels agree with the FP64 oracle to single precision."""
+    C = case(hz, torch, c)
+    x = inputs.random_complex(C.fine.N, seed=11)
+    f = inputs.random_complex(C.fine.N, seed=12)
+    dx, df = C.dev(x), C.dev(f)
+    for name, g, o in [
+        ("AEPS", C.gp.apply("AEPS", dx, prec="mixed"), C.tg.Aeps @ x),
+        ("JACOBI", C.gp.apply("JACOBI", dx, df, prec="mixed"), jacobi_sweep(C.tg.Aeps, C.tg.dinv, 0.6, x, f)),
+        ("RESTRICT", C.gp.apply("RESTRICT", dx, prec="mixed"), C.tg.P.T @ x),
+        ("A0", C.gp.apply("A0", dx, prec="mixed"), C.A0 @ x),
+    ]:
+        e = rel(C.host(g), o)
+        _log(f"  mixed {name}: rel err {e:.2e}")
+        assert e <= 2e-6, (name, e)
+    z = C.host(C.gp.apply("VCYCLE", C.dev(f), prec="mixed"))
+    e = rel(z, C.tg.vcycle(f))
+    _log(f"  mixed VCYCLE: rel err {e:.2e}")
+    assert e <= 1e-3
+
+
+SOLVES = [
+    (16.0, 64, 1, 1 + 0.5j, math.pi / 7),     # the small plane-wave configuration
+    (30.0, 32, 2, 1 + 0.5j, 1.1),
+    (40.0, 24, 3, 1 + 0.5j, 2.0),
+    (20.0, 130, 1, 1 + 0.2j, 0.3),
+]
+
+
+@pytest.mark.parametrize("k,n,p,s,th", SOLVES)
+def test_fgmres_solve_matches_oracle(hz, torch, k, n, p, s, th):
+    _log(f"[solve] k={k} n={n} p={p} s={s}")
+    gp = hz.Problem(k, 1.0 / n, p, s, restart=50)
+    op = OProblem(k, n, p, s)
+    F = op.planewave_rhs(th)
+    ro = op.solve(F, tol=1e-10, m=50)
+    dF = torch.from_numpy(F).cuda()
+    u, r = gp.solve(dF, tol=1e-10)
+    ug = u.cpu().numpy()
+    e = rel(ug, ro["u"])
+    _log(f"  iterations gpu {r['iterations']} oracle {ro['iterations']}, u rel err {e:.2e}, "
+         f"true res {r['rel_res_true']:.2e}")
+    assert r["converged"] == 1 and ro["converged"]
+    assert abs(r["iterations"] - ro["iterations"]) <= 1
+    assert e <= 1e-8
+    assert r["rel_res_true"] <= 1e-10
+    # the residual history follows the oracle's over the common iterations
+    hist = np.array(r["hist"])
+    m = min(len(hist), len(ro["hist"])) - 2
+    assert np.allclose(hist[:m], ro["hist"][:m], rtol=1e-5, atol=1e-12)
+    # the recomputed true residual, by the oracle's assembled operator
+    tr = np.linalg.norm(F - op.A0 @ ug) / np.linalg.norm(F)
+    assert tr <= 1.01e-10
+
+
+@pytest.mark.parametrize("k,n,p,s,th", SOLVES[:3])
+def test_mixed_solve(hz, torch, k, n, p, s, th):
+    gp = hz.Problem(k, 1.0 / n, p, s, prec="mixed")
+    op = OProblem(k, n, p, s)
+    F = op.planewave_rhs(th)
+    ro = op.solve(F, tol=1e-10)
+    u, r = gp.solve(torch.from_numpy(F).cuda(), tol=1e-10, prec="mixed")
+    e = rel(u.cpu().numpy(), ro["u"])
+    _log(f"[mixed] k={k} n={n} p={p}: its {r['iterations']} vs oracle {ro['iterations']} "
+         f"(delta {r['iterations'] - ro['iterations']:+d}), u rel err {e:.2e}")
+    assert r["converged"] == 1
+    assert e <= 1e-8
+    assert abs(r["iterations"] - ro["iterations"]) <= max(3, ro["iterations"] // 10)
+
+
+def test_solve_edge_cases(hz, torch):
+    gp = hz.Problem(16.0, 1 / 64, 1, 1 + 0.5j)
+    Z = torch.zeros(gp.N, dtype=torch.complex128, device="cuda")
+    u, r = gp.solve(Z)
+    assert r["iterations"] == 0 and r["converged"] == 1 and torch.count_nonzero(u).item() == 0
+    F = gp.planewave_rhs(0.4)
+    u, r = gp.solve(F, tol=1e-30, maxit=3)
+    assert r["iterations"] == 3 and r["converged"] == 0 and len(r["hist"]) == 3
+    Fn = F.clone()
+    Fn[5] = complex(float("nan"), 0)
+    with pytest.raises(hz.HZError) as ei:
+        gp.solve(Fn)
+    assert ei.value.status == hz.HZ_EINVAL
+    with pytest.raises(hz.HZError):
+        gp.solve(F, restart=60)          # beyond the capacity given at creation
+    # bitwise reproducible
+    u1, r1 = gp.solve(F, tol=1e-10)
+    u2, r2 = gp.solve(F, tol=1e-10)
+    assert torch.equal(u1, u2) and r1["hist"] == r2["hist"]
+
+
+def test_batched_equals_single(hz, torch):
+    k, n, p = 20.0, 32, 2
+    betas = [0.3, 0.9]
+    probs = [hz.Problem(k, 1.0 / n, p, 1 + 1j * b) for b in betas]
+    ths = [0.2, 1.7, 4.0]
+    Fs = [probs[i].planewave_rhs(t) for i in range(2) for t in ths]
+    us, rs = hz.solve_batched(probs, Fs, 3, tol=1e-10)
+    for q in range(6):
+        u1, r1 = probs[q // 3].solve(Fs[q], tol=1e-10)
+        assert torch.equal(u1, us[q])
+        assert r1["iterations"] == rs[q]["iterations"]
