@@ -9,6 +9,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -56,6 +57,7 @@ template <typename T> struct Level {
   DevOp<T> fine, coarse;   // A_eps on the fine and coarse lattices
   const T* rw = nullptr;   // prolongation weights
   const V2<T>* S = nullptr;
+  CoarseSolveWork cw;
   V2<T>*ua = nullptr, *ub = nullptr, *rf = nullptr, *rc = nullptr, *ec = nullptr;
 };
 
@@ -89,6 +91,7 @@ struct hz_problem {
   float2 *Zf = nullptr, *fa = nullptr, *fb = nullptr, *frf = nullptr, *ff = nullptr,
          *frc = nullptr, *fec = nullptr;
   double2* pin = nullptr;   // pinned host read-back buffer
+  CoarseSolveWork cw;       // grid-barrier counter and error flag of the coarse solve
   double gl_t[10], gl_w[10], lag[40];
   double setup_s = 0;
   std::atomic<int> busy{0};
@@ -288,6 +291,7 @@ Level<double> level64(hz_problem* pr) {
   l.coarse = DevOp<double>{pr->cAc, nullptr, pr->Mc};
   l.rw = pr->rw;
   l.S = pr->S;
+  l.cw = pr->cw;
   l.ua = pr->ua; l.ub = pr->ub; l.rf = pr->rf; l.rc = pr->rc; l.ec = pr->ec;
   return l;
 }
@@ -297,6 +301,7 @@ Level<float> level32(hz_problem* pr) {
   l.coarse = DevOp<float>{pr->fcAc, nullptr, pr->Mc};
   l.rw = pr->frw;
   l.S = pr->Sf;
+  l.cw = pr->cw;
   l.ua = pr->fa; l.ub = pr->fb; l.rf = pr->frf; l.rc = pr->frc; l.ec = pr->fec;
   return l;
 }
@@ -322,7 +327,7 @@ void vcycle(const hz_problem* pr, const Level<T>& lv, int nu, const V2<T>* f, V2
     launch_stencil<T, T, T, T>(p, ST_RESID, lv.fine, cur, f, lv.rf, 1, 0, st);
     launch_restrict<T>(p, pr->M, pr->Mc, lv.rw, lv.rf, lv.rc, 1, 0, 0, st);
   }
-  coarse_solve<T>(pr->L, lv.coarse, lv.S, lv.rc, lv.ec, 1, 0, st);
+  coarse_solve<T>(pr->L, lv.coarse, lv.S, lv.rc, lv.ec, 1, 0, lv.cw, st);
   launch_prolong<T>(p, pr->M, pr->Mc, lv.rw, lv.ec, cur, true, 1, 0, 0, st);
   if (nu == 0) {
     HZ_HIP(hipMemcpyAsync(z, cur, sizeof(V2<T>) * pr->N, hipMemcpyDeviceToDevice, st));
@@ -475,6 +480,11 @@ hz_status solve_impl(hz_problem* pr, const double2* F, double2* u, const hz_opti
     }
     if (its >= o.maxit) break;
   }
+  {
+    int e = 0;
+    HZ_HIP(hipMemcpy(&e, pr->cw.err, sizeof(int), hipMemcpyDeviceToHost));
+    if (e) return fail(HZ_EDEVICE, "coarse solve grid barrier timed out");
+  }
   out.iterations = its;
   out.converged = conv ? 1 : 0;
   out.rel_res_true = true_rel;
@@ -566,6 +576,13 @@ hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_option
     pr->partial = pr->mem.alloc<double2>(size_t(pr->nblk) * 64);
     pr->hbuf = pr->mem.alloc<double2>(4 * 64);
     pr->ybuf = pr->mem.alloc<double2>(64);
+    pr->cw.g = pr->mem.alloc<double2>(4 * size_t(pr->Nc));
+    pr->cw.err = pr->mem.alloc<int>(64);
+    HZ_HIP(hipMemsetAsync(pr->cw.err, 0, 64 * sizeof(int), st));
+    {
+      const char* env = std::getenv("HZ_COARSE_PERSISTENT");
+      pr->cw.persistent = !(env && env[0] == '0');
+    }
     HZ_HIP(hipHostMalloc(reinterpret_cast<void**>(&pr->pin), 4 * 64 * 16, hipHostMallocDefault));
     if (opt.prec == HZ_MIXED) {
       ensure_mixed_work(pr, st);
@@ -658,7 +675,7 @@ hz_status hz_apply(const hz_problem* cpr, int op, const hz_c64* d_x, const hz_c6
         case HZ_OP_RESTRICT: launch_restrict<double>(p, pr->M, pr->Mc, pr->rw, x, y, 1, 0, 0, st); break;
         case HZ_OP_PROLONG: launch_prolong<double>(p, pr->M, pr->Mc, pr->rw, x, y, false, 1, 0, 0, st); break;
         case HZ_OP_VCYCLE: vcycle<double>(pr, lv, pr->opt.nu, x, y, st); break;
-        case HZ_OP_COARSE_SOLVE: coarse_solve<double>(pr->L, lv.coarse, pr->S, x, y, 1, 0, st); break;
+        case HZ_OP_COARSE_SOLVE: coarse_solve<double>(pr->L, lv.coarse, pr->S, x, y, 1, 0, lv.cw, st); break;
         case HZ_OP_COARSE_A: launch_stencil<double, double, double, double>(p, ST_APPLY, lv.coarse, x, nullptr, y, 1, 0, st); break;
         case HZ_OP_RESID_RESTRICT:
           launch_stencil<double, double, double, double>(p, ST_RESID, lv.fine, x, f, pr->rf, 1, 0, st);
@@ -687,7 +704,7 @@ hz_status hz_apply(const hz_problem* cpr, int op, const hz_c64* d_x, const hz_c6
         case HZ_OP_RESTRICT: launch_restrict<float>(p, pr->M, pr->Mc, pr->frw, xin, yout, 1, 0, 0, st); break;
         case HZ_OP_PROLONG: launch_prolong<float>(p, pr->M, pr->Mc, pr->frw, xin, yout, false, 1, 0, 0, st); break;
         case HZ_OP_VCYCLE: vcycle<float>(pr, lv, pr->opt.nu, xin, yout, st); break;
-        case HZ_OP_COARSE_SOLVE: coarse_solve<float>(pr->L, lv.coarse, pr->Sf, xin, yout, 1, 0, st); break;
+        case HZ_OP_COARSE_SOLVE: coarse_solve<float>(pr->L, lv.coarse, pr->Sf, xin, yout, 1, 0, lv.cw, st); break;
         case HZ_OP_COARSE_A: launch_stencil<float, float, float, float>(p, ST_APPLY, lv.coarse, xin, nullptr, yout, 1, 0, st); break;
         case HZ_OP_RESID_RESTRICT:
           launch_stencil<float, float, float, float>(p, ST_RESID, lv.fine, xin, pr->fb, pr->frf, 1, 0, st);

@@ -110,9 +110,16 @@ struct CoarseFactorWork {
 hz_status coarse_factor(const CoarseLayout& L, const DevOp<double>& cop, double2* S,
                         const CoarseFactorWork& w, hipStream_t st);
 // Solves A_c y = b with the stored inverses; nrhs right-hand sides with stride cstride.
+// Runs as one persistent cooperative launch when possible (workgroups wait for each other's
+// block results through sentinel-initialised buffers), else one launch per block row.
+struct CoarseSolveWork {
+  void* g = nullptr;         // forward-sweep results, 4 right-hand sides x coarse dofs
+  int* err = nullptr;        // set to 1 if a wait for another workgroup's data timed out
+  bool persistent = true;
+};
 template <typename T>
 void coarse_solve(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b,
-                  V2<T>* y, int nrhs, long cstride, hipStream_t st);
+                  V2<T>* y, int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st);
 void launch_factor_to_f32(const double2* S, float2* Sf, size_t n, hipStream_t st);
 
 // Krylov kernels. Vectors of length N; V is row-major [nv][ldv].

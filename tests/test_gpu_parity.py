@@ -233,3 +233,18 @@ def test_batched_equals_single(hz, torch):
         u1, r1 = probs[q // 3].solve(Fs[q], tol=1e-10)
         assert torch.equal(u1, us[q])
         assert r1["iterations"] == rs[q]["iterations"]
+
+
+@pytest.mark.parametrize("c", [CASES[2], CASES[4], CASES[6]])
+def test_coarse_solve_per_step_launches(hz, torch, c, monkeypatch):
+    """The non-persistent path (one launch per block row) gives the same coarse solve."""
+    monkeypatch.setenv("HZ_COARSE_PERSISTENT", "0")
+    k, n, p, s = c
+    gp = hz.Problem(k, 1.0 / n, p, s)
+    monkeypatch.delenv("HZ_COARSE_PERSISTENT")
+    C = case(hz, torch, c)
+    rc = inputs.random_complex(C.coarse.N, seed=7)
+    y1 = gp.apply("COARSE_SOLVE", C.dev(rc))
+    y2 = C.gp.apply("COARSE_SOLVE", C.dev(rc))
+    assert torch.equal(y1, y2)          # same arithmetic, same order
+    assert rel(C.host(y1), C.tg.coarse_solve(rc)) <= 1e-10
