@@ -102,98 +102,135 @@ k_schur_left(int j, int Mc, const double2* __restrict__ coef, const double2* __r
 }
 
 // ------------------------------------------------------------------------------------------
-// Blocked Gauss-Jordan inversion, in place. One panel K = [k0, k0 + w):
-//   Pinv = X[K,K]^{-1};   X <- X - Wt Rt   with
-//   Wt[i, :] = X[i, K] Pinv (i not in K),  Wt[K, :] = I - Pinv,
-//   Rt[:, j] = X[K, j]      (j not in K),  Rt[:, K] = X[K, K] + I,
-// which leaves X[K,K] = Pinv, X[K,j] = Pinv X[K,j], X[i,K] = -X[i,K] Pinv and the Schur
-// update X[i,j] - X[i,K] Pinv X[K,j] elsewhere.
+// Blocked Gauss-Jordan inversion, in place. One panel K = [k0, k0 + w), w <= NB = 32, with
+// Pinv = X[K,K]^{-1} and W[i,:] = X[i,K] Pinv:
+//   X[K,K] <- Pinv,   X[i,K] <- -W[i,:],   X[K,j] <- Pinv X[K,j],   X[i,j] <- X[i,j] - W[i,:] X[K,j]
+// for i, j outside K. Panels and 32 x 32 tiles are aligned, so every tile of the update is
+// entirely in the pivot rows, the pivot columns, or neither (no cancellation-prone forms).
+// The panel kernel writes Wt (rows outside K: W, rows in K: Pinv) and Rt = X[K, :].
 // ------------------------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(256)
 k_gj_panel(const double2* __restrict__ X, int n, int k0, int w, double2* __restrict__ Wt,
            double2* __restrict__ Rt, int* __restrict__ flag) {
-  __shared__ double2 Y[NB][NB + 1];
-  __shared__ double2 rowt[NB], colt[NB];
+  __shared__ double2 Y[2][NB][NB + 1];         // double-buffered Gauss-Jordan on X[K,K]
+  __shared__ double2 Xp[32][NB + 1];            // this workgroup's rows of X[:, K]
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int r = idx / NB, c = idx % NB;
-    double2 v = make_double2(r == c ? 1.0 : 0.0, 0.0);
-    if (r < w && c < w) v = X[size_t(k0 + r) * n + k0 + c];
-    Y[r][c] = v;
+  const int base = blockIdx.x * 32;
+  // coalesced staging, all loads in flight at once: the diagonal panel block, this
+  // workgroup's rows of the column panel and its columns of the row panel
+  {
+    double2 vy[4], vx[4], vr[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx / NB, c = idx % NB;
+      vy[q] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+      if (r < w && c < w) vy[q] = X[size_t(k0 + r) * n + k0 + c];
+      const int i = base + r;
+      vx[q] = (i < n && c < w) ? X[size_t(i) * n + k0 + c] : make_double2(0, 0);
+      const int jj = base + idx % 32, kk = idx / 32;
+      vr[q] = (jj < n && kk < w) ? X[size_t(k0 + kk) * n + jj] : make_double2(0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx / NB, c = idx % NB;
+      Y[0][r][c] = vy[q];
+      Xp[r][c] = vx[q];
+      const int jj = base + idx % 32, kk = idx / 32;
+      if (jj < n) Rt[size_t(kk) * n + jj] = vr[q];
+    }
   }
   __syncthreads();
   bool bad = false;
+  int cur = 0;
   for (int t = 0; t < w; ++t) {
-    const double2 pv = Y[t][t];
+    const double2 pv = Y[cur][t][t];
     const double mag = pv.x * pv.x + pv.y * pv.y;
     if (!(mag > 0.0) || !isfinite(mag)) bad = true;
-    const double2 pinv = crecip(pv);
-    if (tid < NB) {
-      rowt[tid] = cmul<double>(Y[t][tid], pinv);
-      colt[tid] = Y[tid][t];
-    }
-    __syncthreads();
-    for (int idx = tid; idx < NB * NB; idx += 256) {
+    // 1/mag: hardware reciprocal refined by two Newton steps (full double precision)
+    double rm = __builtin_amdgcn_rcp(mag);
+    rm = rm * (2.0 - mag * rm);
+    rm = rm * (2.0 - mag * rm);
+    const double2 pinv = make_double2(pv.x * rm, -pv.y * rm);
+    double2 yrt[4], ytc[4], yrc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
       const int r = idx / NB, c = idx % NB;
+      yrt[q] = Y[cur][r][t];
+      ytc[q] = Y[cur][t][c];
+      yrc[q] = Y[cur][r][c];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx / NB, c = idx % NB;
+      double2 v;
       if (r == t) {
-        Y[r][c] = (c == t) ? pinv : rowt[c];
+        v = (c == t) ? pinv : cmul<double>(ytc[q], pinv);
       } else if (c == t) {
-        const double2 v = cmul<double>(colt[r], pinv);
-        Y[r][c] = make_double2(-v.x, -v.y);
+        const double2 a = cmul<double>(yrt[q], pinv);
+        v = make_double2(-a.x, -a.y);
       } else {
-        const double2 a = colt[r], b = rowt[c];
-        double2 v = Y[r][c];
+        const double2 a = cmul<double>(yrt[q], pinv), b = ytc[q];
+        v = yrc[q];
         v.x -= a.x * b.x - a.y * b.y;
         v.y -= a.x * b.y + a.y * b.x;
-        Y[r][c] = v;
       }
+      Y[cur ^ 1][r][c] = v;
     }
+    cur ^= 1;
     __syncthreads();
   }
   if (bad && tid == 0 && blockIdx.x == 0) *flag = 1;
-  const int base = blockIdx.x * 64;
-  for (int idx = tid; idx < 64 * NB; idx += 256) {
-    const int i = base + idx / NB, kk = idx % NB;
+  for (int idx = tid; idx < 32 * NB; idx += 256) {
+    const int r = idx / NB, kk = idx % NB;
+    const int i = base + r;
     if (i >= n) continue;
     double2 v = make_double2(0, 0);
     if (kk < w) {
       if (i >= k0 && i < k0 + w) {
-        const double2 y = Y[i - k0][kk];
-        v = make_double2((i - k0 == kk ? 1.0 : 0.0) - y.x, -y.y);
+        v = Y[cur][i - k0][kk];
       } else {
-        const double2* xr = X + size_t(i) * n + k0;
-        for (int t = 0; t < w; ++t) cfma(v, xr[t], Y[t][kk]);
+#pragma unroll 8
+        for (int t = 0; t < NB; ++t) cfma(v, Xp[r][t], Y[cur][t][kk]);
       }
     }
     Wt[size_t(i) * NB + kk] = v;
   }
-  for (int idx = tid; idx < 64 * NB; idx += 256) {
-    const int jj = base + idx % 64, kk = idx / 64;
-    if (jj >= n) continue;
-    double2 v = make_double2(0, 0);
-    if (kk < w) {
-      v = X[size_t(k0 + kk) * n + jj];
-      if (jj - k0 == kk) v.x += 1.0;
-    }
-    Rt[size_t(kk) * n + jj] = v;
-  }
 }
 
-// X -= Wt (n x NB) * Rt (NB x n), complex FP64 on MFMA. Each wave owns a 32 x 32 tile
-// (2 x 2 blocks of 16 x 16); operands are read straight from the (L2-resident) panels.
+// Tile update on FP64 MFMA. Each wave owns a 32 x 32 tile (2 x 2 blocks of 16 x 16);
+// operands are read straight from the (L2-resident) panels.
 // v_mfma_f64_16x16x4: lane l holds A[l%16][l/16], B[l/16][l%16] and D[l/16 + 4r][l%16]
 // (r = 0..3; the FP64 layout interleaves rows by 4, checked on the device).
 __global__ void __launch_bounds__(256)
-k_gj_update(double2* __restrict__ X, int n, const double2* __restrict__ Wt,
+k_gj_update(double2* __restrict__ X, int n, int k0, const double2* __restrict__ Wt,
             const double2* __restrict__ Rt) {
   const int lane = threadIdx.x & 63;
   const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int tiles = (n + 31) / 32;
   if (wave >= tiles * tiles) return;
   const int ti = wave / tiles, tj = wave % tiles;
+  const int kt = k0 / 32;
   const int i0 = ti * 32, j0 = tj * 32;
   const int li = lane & 15, lk = lane >> 4;
+  if (tj == kt) {
+    // pivot columns: X[i,K] = -W[i,:] (i outside K), X[K,K] = Pinv
+    for (int e = lane; e < 32 * 32; e += 64) {
+      const int r = e / 32, c = e % 32;
+      const int row = i0 + r, col = j0 + c;
+      if (row < n && col < n) {
+        double2 v = Wt[size_t(row) * NB + c];
+        if (ti != kt) v = make_double2(-v.x, -v.y);
+        X[size_t(row) * n + col] = v;
+      }
+    }
+    return;
+  }
+  const bool pivot_rows = ti == kt;        // X[K,j] = Pinv X[K,j]; else X -= W X[K,j]
   v4d cre[2][2], cim[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -203,10 +240,11 @@ k_gj_update(double2* __restrict__ X, int n, const double2* __restrict__ Wt,
       for (int r = 0; r < 4; ++r) {
         const int row = i0 + bi * 16 + lk + 4 * r, col = j0 + bj * 16 + li;
         double2 v = make_double2(0, 0);
-        if (row < n && col < n) v = X[size_t(row) * n + col];
+        if (!pivot_rows && row < n && col < n) v = X[size_t(row) * n + col];
         cre[bi][bj][r] = v.x;
         cim[bi][bj][r] = v.y;
       }
+  const double sg = pivot_rows ? 1.0 : -1.0;
 #pragma unroll
   for (int k = 0; k < NB; k += 4) {
     double are[2], aim[2], bre[2], bim[2];
@@ -215,8 +253,8 @@ k_gj_update(double2* __restrict__ X, int n, const double2* __restrict__ Wt,
       const int row = i0 + bi * 16 + li;
       double2 a = make_double2(0, 0);
       if (row < n) a = Wt[size_t(row) * NB + k + lk];
-      are[bi] = -a.x;
-      aim[bi] = -a.y;
+      are[bi] = sg * a.x;
+      aim[bi] = sg * a.y;
     }
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
@@ -230,7 +268,7 @@ k_gj_update(double2* __restrict__ X, int n, const double2* __restrict__ Wt,
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj) {
-        // (-a)(b): re = -are*bre + aim*bim, im = -are*bim - aim*bre  (are, aim hold -a)
+        // C += (sg a) b: re += are*bre - aim*bim, im += are*bim + aim*bre
         cre[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[bi], bre[bj], cre[bi][bj], 0, 0, 0);
         cre[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-aim[bi], bim[bj], cre[bi][bj], 0, 0, 0);
         cim[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[bi], bim[bj], cim[bi][bj], 0, 0, 0);
@@ -313,180 +351,158 @@ template <typename T> __global__ void k_fill_sentinel(V2<T>* a, long n, long str
   }
 }
 
-// 256 threads: wave 0 gathers the neighbour block (polling until it is complete) and the
-// right-hand side, combines the row sums and publishes the results; waves 1..3 stream the
-// rows of S_j, prefetching the next block's rows as soon as their products are formed.
+// 512 threads. Waves 0-1 ("exchange waves") gather the neighbour block (polling until it is
+// complete) and the right-hand side into LDS, combine the row sums and publish the results;
+// they never hold prefetched data, so their loads are never ordered behind the stream.
+// Waves 2-7 ("stream waves") split the columns of the workgroup's rows of S_j: each lane
+// forms the coupling values of its own columns from LDS, accumulates partial row sums and,
+// right after consuming a chunk, issues the loads of the next block's first chunk into the
+// same registers.
+constexpr int NSW = 6;   // stream waves
+
 template <int P, typename T, int NR, int RCH, int QCH>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_csolve(int s_begin, int s_end, int nc, int Mc, const V2<T>* __restrict__ coef,
          const V2<T>* __restrict__ S, const V2<T>* __restrict__ b, V2<T>* __restrict__ y,
          V2<T>* __restrict__ gbuf, int nrhs, long cstride, int* __restrict__ err) {
   constexpr int W = 2 * P + 1, W2 = W * W, NCOEF = P * P * 9 * W2;
-  constexpr int NCW = 3;                       // compute waves
-  constexpr int ENT = 24;                      // neighbour entries per lane and round
+  constexpr int ENT = 12;                      // polled entries per lane and round
   extern __shared__ char smem[];
   const int nmax = P * Mc;
   V2<T>* cl = reinterpret_cast<V2<T>*>(smem);  // coefficient table
-  V2<T>* t = cl + NCOEF;                       // [NR][nmax] coupling vector of block j
+  V2<T>* t = cl + NCOEF;                       // [NR][nmax] right-hand side, then coupling vector
   V2<T>* yn = t + NR * nmax;                   // [NR][nmax] neighbour block
-  __shared__ T red[2][NCW][RCH][NR];
+  __shared__ T red[2][NSW][RCH][NR];
   const int nb = nc + 1;
   const int G = gridDim.x, g = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sw = wave - 2;                     // stream wave index (valid for wave >= 2)
   const size_t bsz = size_t(P * Mc) * size_t(P * Mc);
   const long Nc = long(Mc) * Mc;
-  for (int i = threadIdx.x; i < NCOEF; i += 256) cl[i] = coef[i];
+  for (int i = threadIdx.x; i < NCOEF; i += 512) cl[i] = coef[i];
 
   V2<T> sv[RCH][QCH];
   bool have = false;                           // sv holds the first chunk of this step
-  auto step_rows = [&](int s, int& nj, int& r0, int& r1, int& c0, int& c1, const V2<T>*& Sj) {
-    const bool fwd = s < nb;
-    const int j = fwd ? s : 2 * nb - 2 - s;
-    nj = (j < nc ? P : 1) * Mc;
-    r0 = int((long(nj) * g) / G);
-    r1 = int((long(nj) * (g + 1)) / G);
-    c0 = (nj * (wave - 1)) / NCW;
-    c1 = (nj * wave) / NCW;
-    Sj = S + size_t(j) * bsz;
-  };
-  auto load_chunk = [&](const V2<T>* Sj, int nj, int rb, int r1, int c0, int c1, int q0) {
-#pragma unroll
-    for (int rr = 0; rr < RCH; ++rr)
-#pragma unroll
-      for (int q = 0; q < QCH; ++q) {
-        const int c = c0 + lane + 64 * (q0 + q);
-        sv[rr][q] = (rb + rr < r1 && c < c1) ? Sj[size_t(rb + rr) * nj + c] : czero<T>();
-      }
-  };
 
   for (int s = s_begin; s < s_end; ++s) {
     const bool fwd = s < nb;
     const int j = fwd ? s : 2 * nb - 2 - s;
     const int nj = (j < nc ? P : 1) * Mc;
     const long dof0 = long(P) * j * Mc;
-    // 1a. wave 0 gathers the neighbour block (g_{j-1} forward, x_{j+1} backward) and b_j
     const int jn = fwd ? j - 1 : j + 1;
     const bool has_n = fwd ? j > 0 : j < nc;
     const int nn = has_n ? (jn < nc ? P : 1) * Mc : 0;
     const long ndof0 = long(P) * jn * Mc;
-    // backward neighbour x_{nc} is the forward result of the last block
-    const V2<T>* src = fwd ? gbuf : (jn == nc ? gbuf : y);
-    if (wave == 0) {
-      for (int i0 = 0; i0 < nn * nrhs; i0 += 64 * ENT) {
-        V2<T> v[ENT];
-        unsigned pending = 0;
-#pragma unroll
-        for (int q = 0; q < ENT; ++q) {
-          const int idx = i0 + lane + 64 * q;
-          if (idx < nn * nrhs) pending |= 1u << q;
-        }
-        unsigned rounds = 0;
-        while (pending) {
-#pragma unroll
-          for (int q = 0; q < ENT; ++q) {
-            if (pending & (1u << q)) {
-              const int idx = i0 + lane + 64 * q;
-              const int h = idx / nn, c = idx - h * nn;
-              v[q] = ld_coh<T>(src + h * (fwd || jn == nc ? Nc : cstride) + ndof0 + c);
-            }
-          }
-#pragma unroll
-          for (int q = 0; q < ENT; ++q)
-            if ((pending & (1u << q)) && !is_sentinel(v[q].x) && !is_sentinel(v[q].y))
-              pending &= ~(1u << q);
-          if (pending) {
-            ++rounds;
-            if ((rounds & 255u) == 0) {   // rare checks: a timeout elsewhere, or our own
-              if (rounds > (1u << 20)) {
-                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-              }
-              if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-            }
-            if (rounds > 8) __builtin_amdgcn_s_sleep(1);
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < ENT; ++q) {
-          const int idx = i0 + lane + 64 * q;
-          if (idx < nn * nrhs) {
-            const int h = idx / nn, c = idx - h * nn;
-            yn[h * nmax + c] = v[q];
-          }
-        }
-      }
+    // backward: x_{nc} is the forward result of the last block (in gbuf)
+    const bool from_g = fwd || jn == nc;
+    const V2<T>* src = from_g ? gbuf : y;
+    const long sstride = from_g ? Nc : cstride;
+    // 1a. exchange waves: right-hand side block (forward) and the polled neighbour block
+    if (wave < 2) {
+      const int xl = threadIdx.x;              // 0..127
       if (fwd)
-        for (int idx = lane; idx < nj * nrhs; idx += 64) {
+        for (int idx = xl; idx < nj * nrhs; idx += 128) {
           const int h = idx / nj, c = idx - h * nj;
           t[h * nmax + c] = b[h * cstride + dof0 + c];
         }
-    }
-    __syncthreads();
-    // 1b. coupling vector of block j, all waves, from LDS only (row by row: no divisions)
-    {
-      const int rows = nj / Mc;
-      for (int h = 0; h < nrhs; ++h)
-        for (int rl = 0; rl < rows; ++rl) {
-          const int bc = P * j + rl;
-          const int cb = (bc % P) * P, ry = region(bc, Mc) * 3;
-          int bb_lo, bb_hi;                      // lattice rows of the neighbour block
-          if (fwd) { bb_lo = P * j - P; bb_hi = P * j - 1; }
-          else { bb_lo = P * (j + 1); bb_hi = min(P * (j + 1) + P - 1, Mc - 1); }
-          for (int ac = threadIdx.x; ac < Mc; ac += 256) {
-            const int c = rl * Mc + ac;
-            const V2<T>* cc = cl + ((cb + ac % P) * 9 + ry + region(ac, Mc)) * W2;
-            V2<T> acc = fwd ? t[h * nmax + c] : czero<T>();
-            if (has_n) {
+      for (int h = 0; h < nrhs; ++h) {
+        const V2<T>* sh = src + h * sstride + ndof0;
+        V2<T>* yh = yn + h * nmax;
+        for (int i0 = 0; i0 < nn; i0 += 128 * ENT) {
+          unsigned pending = 0;
 #pragma unroll
-              for (int dyi = 1; dyi <= P; ++dyi) {
-                const int dy = fwd ? -dyi : dyi;
-                const int bb = bc + dy;
-                if (bb < bb_lo || bb > bb_hi) continue;
-                const V2<T>* ynr = yn + h * nmax + (bb - P * jn) * Mc;
+          for (int q = 0; q < ENT; ++q)
+            if (i0 + xl + 128 * q < nn) pending |= 1u << q;
+          unsigned rounds = 0;
+          while (pending) {
+            V2<T> v[ENT];
 #pragma unroll
-                for (int dx = -P; dx <= P; ++dx) {
-                  const int aa = ac + dx;
-                  if (aa < 0 || aa >= Mc) continue;
-                  const V2<T> cf = cc[(dy + P) * W + dx + P];
-                  const V2<T> v = ynr[aa];
-                  if (fwd) {
-                    acc.x -= cf.x * v.x - cf.y * v.y;
-                    acc.y -= cf.x * v.y + cf.y * v.x;
-                  } else {
-                    cfma(acc, cf, v);
-                  }
-                }
+            for (int q = 0; q < ENT; ++q)
+              if (pending & (1u << q)) v[q] = ld_coh<T>(sh + i0 + xl + 128 * q);
+#pragma unroll
+            for (int q = 0; q < ENT; ++q)
+              if ((pending & (1u << q)) && !is_sentinel(v[q].x) && !is_sentinel(v[q].y)) {
+                yh[i0 + xl + 128 * q] = v[q];
+                pending &= ~(1u << q);
               }
+            if (pending) {
+              ++rounds;
+              if ((rounds & 255u) == 0) {
+                if (rounds > (1u << 20)) {
+                  __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                  break;
+                }
+                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+              }
+              if (rounds > 8) __builtin_amdgcn_s_sleep(1);
             }
-            t[h * nmax + c] = acc;
           }
         }
+      }
     }
     __syncthreads();
-    // 2. rows [r0, r1) of S_j t in chunks of RCH rows
-    int njs, r0, r1, c0, c1;
-    const V2<T>* Sj;
-    step_rows(s, njs, r0, r1, c0, c1, Sj);
-    const int qn = wave > 0 ? (c1 - c0 + 63) / 64 : 0;
-    const bool pre = have;   // sv was prefetched for this step
+    // 2. rows [r0, r1) of S_j t in chunks of RCH rows; stream wave sw owns columns [c0, c1)
+    const int r0 = int((long(nj) * g) / G), r1 = int((long(nj) * (g + 1)) / G);
+    const int c0 = (nj * sw) / NSW, c1 = (nj * (sw + 1)) / NSW;
+    const V2<T>* Sj = S + size_t(j) * bsz;
+    int bb_lo, bb_hi;                          // lattice rows of the neighbour block
+    if (fwd) { bb_lo = P * j - P; bb_hi = P * j - 1; }
+    else { bb_lo = P * (j + 1); bb_hi = min(P * (j + 1) + P - 1, Mc - 1); }
+    const bool pre = have;
     have = false;
     for (int rb = r0; rb < r1; rb += RCH) {
-      if (wave > 0) {
+      if (wave >= 2) {
         T ar[RCH][NR], ai[RCH][NR];
 #pragma unroll
         for (int rr = 0; rr < RCH; ++rr)
 #pragma unroll
           for (int h = 0; h < NR; ++h) { ar[rr][h] = T(0); ai[rr][h] = T(0); }
+        const int qn = (c1 - c0 + 63) / 64;
         for (int q0 = 0; q0 < qn; q0 += QCH) {
-          if (!(pre && rb == r0 && q0 == 0)) load_chunk(Sj, nj, rb, r1, c0, c1, q0);
+          if (!(pre && rb == r0 && q0 == 0)) {
+#pragma unroll
+            for (int rr = 0; rr < RCH; ++rr)
+#pragma unroll
+              for (int q = 0; q < QCH; ++q) {
+                const int c = c0 + lane + 64 * (q0 + q);
+                sv[rr][q] = (rb + rr < r1 && c < c1) ? Sj[size_t(rb + rr) * nj + c] : czero<T>();
+              }
+          }
 #pragma unroll
           for (int q = 0; q < QCH; ++q) {
             const int c = c0 + lane + 64 * (q0 + q);
             if (c >= c1) continue;
+            // coupling value of column c: t = b_j - A_{j,j-1} g_{j-1} (forward) or
+            // A_{j,j+1} x_{j+1} (backward), from the neighbour block staged in LDS
+            const int rl = c / Mc, ac = c - rl * Mc;
+            const int bc = P * j + rl;
+            const V2<T>* cc = cl + (((bc % P) * P + ac % P) * 9 + region(bc, Mc) * 3 + region(ac, Mc)) * W2;
 #pragma unroll
             for (int h = 0; h < NR; ++h) {
               if (h >= nrhs) continue;
-              const V2<T> tv = t[h * nmax + c];
+              V2<T> tv = fwd ? t[h * nmax + c] : czero<T>();
+              if (has_n) {
+#pragma unroll
+                for (int dyi = 1; dyi <= P; ++dyi) {
+                  const int dy = fwd ? -dyi : dyi;
+                  const int bb = bc + dy;
+                  if (bb < bb_lo || bb > bb_hi) continue;
+                  const V2<T>* ynr = yn + h * nmax + (bb - P * jn) * Mc;
+#pragma unroll
+                  for (int dx = -P; dx <= P; ++dx) {
+                    const int aa = ac + dx;
+                    if (aa < 0 || aa >= Mc) continue;
+                    const V2<T> cf = cc[(dy + P) * W + dx + P];
+                    const V2<T> v = ynr[aa];
+                    if (fwd) {
+                      tv.x -= cf.x * v.x - cf.y * v.y;
+                      tv.y -= cf.x * v.y + cf.y * v.x;
+                    } else {
+                      cfma(tv, cf, v);
+                    }
+                  }
+                }
+              }
 #pragma unroll
               for (int rr = 0; rr < RCH; ++rr) {
                 ar[rr][h] += sv[rr][q].x * tv.x - sv[rr][q].y * tv.y;
@@ -495,12 +511,22 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, const V2<T>* __restrict__ coef,
             }
           }
         }
-        // prefetch the first chunk of the next step as soon as this one is consumed
+        // next block's first chunk, issued as soon as this step's last chunk is consumed
         if (rb + RCH >= r1 && s + 1 < s_end) {
-          int nj2, r02, r12, c02, c12;
-          const V2<T>* Sj2;
-          step_rows(s + 1, nj2, r02, r12, c02, c12, Sj2);
-          load_chunk(Sj2, nj2, r02, r12, c02, c12, 0);
+          const int s2 = s + 1;
+          const bool fwd2 = s2 < nb;
+          const int j2 = fwd2 ? s2 : 2 * nb - 2 - s2;
+          const int nj2 = (j2 < nc ? P : 1) * Mc;
+          const int r02 = int((long(nj2) * g) / G), r12 = int((long(nj2) * (g + 1)) / G);
+          const int c02 = (nj2 * sw) / NSW, c12 = (nj2 * (sw + 1)) / NSW;
+          const V2<T>* Sj2 = S + size_t(j2) * bsz;
+#pragma unroll
+          for (int rr = 0; rr < RCH; ++rr)
+#pragma unroll
+            for (int q = 0; q < QCH; ++q) {
+              const int c = c02 + lane + 64 * q;
+              sv[rr][q] = (r02 + rr < r12 && c < c12) ? Sj2[size_t(r02 + rr) * nj2 + c] : czero<T>();
+            }
           have = true;
         }
 #pragma unroll
@@ -508,7 +534,7 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, const V2<T>* __restrict__ coef,
 #pragma unroll
           for (int h = 0; h < NR; ++h) {
             const T sr = wave_sum(ar[rr][h]), si = wave_sum(ai[rr][h]);
-            if (lane == 0) { red[0][wave - 1][rr][h] = sr; red[1][wave - 1][rr][h] = si; }
+            if (lane == 0) { red[0][sw][rr][h] = sr; red[1][sw][rr][h] = si; }
           }
       }
       __syncthreads();
@@ -516,8 +542,12 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, const V2<T>* __restrict__ coef,
         const int rr = threadIdx.x / NR, h = threadIdx.x % NR;
         const int r = rb + rr;
         if (r < r1 && h < nrhs) {
-          const T sr = (red[0][0][rr][h] + red[0][1][rr][h]) + red[0][2][rr][h];
-          const T si = (red[1][0][rr][h] + red[1][1][rr][h]) + red[1][2][rr][h];
+          T sr = red[0][0][rr][h], si = red[1][0][rr][h];
+#pragma unroll
+          for (int w2 = 1; w2 < NSW; ++w2) {
+            sr += red[0][w2][rr][h];
+            si += red[1][w2][rr][h];
+          }
           V2<T> o;
           if (fwd) {
             o.x = sr;
@@ -566,7 +596,7 @@ void csolve_launch(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, c
   HZ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   HZ_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
   int per_cu = 0;
-  HZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 256, lds));
+  HZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 512, lds));
   const int max_coresident = per_cu * cus;
   // balanced grid: R rows per workgroup, one workgroup per compute unit at most
   const int n0 = int(L.size(0));
@@ -584,10 +614,10 @@ void csolve_launch(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, c
   if (persistent) {
     void* args[] = {&s_begin, &s_end, (void*)&L.nc, (void*)&L.Mc, (void*)&cop.coef, (void*)&S,
                     (void*)&b, (void*)&y, &gbuf, &nr, (void*)&cstride, &err};
-    HZ_HIP(hipLaunchCooperativeKernel((const void*)kern, dim3(G), dim3(256), args, lds, st));
+    HZ_HIP(hipLaunchCooperativeKernel((const void*)kern, dim3(G), dim3(512), args, lds, st));
   } else {
     for (int s = 0; s < nsteps; ++s)
-      kern<<<G, 256, lds, st>>>(s, s + 1, L.nc, L.Mc, cop.coef, S, b, y, gbuf, nrhs, cstride, err);
+      kern<<<G, 512, lds, st>>>(s, s + 1, L.nc, L.Mc, cop.coef, S, b, y, gbuf, nrhs, cstride, err);
   }
   const long off = long(L.p) * L.nc * L.Mc;
   k_copy_last<T><<<unsigned((L.Mc + 255) / 256), 256, 0, st>>>(gbuf, y, off, L.Mc, Nc, cstride, nrhs);
@@ -598,12 +628,12 @@ template <int P, typename T>
 void csolve_p(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b, V2<T>* y,
               int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st) {
   if (nrhs == 1) {
-    csolve_launch<P, T, 1, 5, 8>(L, cop, S, b, y, 1, cstride, w, st);
+    csolve_launch<P, T, 1, 5, 4>(L, cop, S, b, y, 1, cstride, w, st);
     return;
   }
   for (int r0 = 0; r0 < nrhs; r0 += 4) {
     const int nr = std::min(4, nrhs - r0);
-    csolve_launch<P, T, 4, 2, 8>(L, cop, S, b + r0 * cstride, y + r0 * cstride, nr, cstride, w, st);
+    csolve_launch<P, T, 4, 2, 4>(L, cop, S, b + r0 * cstride, y + r0 * cstride, nr, cstride, w, st);
   }
 }
 
@@ -623,8 +653,8 @@ void factor_p(const CoarseLayout& L, const DevOp<double>& cop, double2* S,
     const int upd_blocks = (tiles * tiles + 3) / 4;
     for (int k0 = 0; k0 < n; k0 += NB) {
       const int wdt = std::min(NB, n - k0);
-      k_gj_panel<<<(n + 63) / 64, 256, 0, st>>>(D, n, k0, wdt, w.W, w.R, w.flag);
-      k_gj_update<<<upd_blocks, 256, 0, st>>>(D, n, w.W, w.R);
+      k_gj_panel<<<(n + 31) / 32, 256, 0, st>>>(D, n, k0, wdt, w.W, w.R, w.flag);
+      k_gj_update<<<upd_blocks, 256, 0, st>>>(D, n, k0, w.W, w.R);
     }
   }
   HZ_HIP(hipGetLastError());
