@@ -69,6 +69,7 @@ typedef struct {
   int maxit;          /* cap on the total number of preconditioner applications; 5000    */
   double tol;         /* relative residual tolerance; default 1e-8                        */
   int prec;           /* hz_precision; default HZ_FP64                                    */
+  int timing;         /* nonzero at creation: record device time of the coarse solves   */
 } hz_options;
 
 typedef struct {
@@ -79,6 +80,14 @@ typedef struct {
   double setup_s;       /* wall seconds spent in hz_create_problem (coarse factor included) */
   double solve_s;       /* wall seconds of this solve                                        */
 } hz_result;
+
+/* Device-time counters of one problem (filled when created with timing != 0). */
+typedef struct {
+  long vcycles;              /* V-cycles run by solves and by hz_apply(HZ_OP_VCYCLE)      */
+  long coarse_solves;        /* launches of the coarse block-triangular solve kernel       */
+  double coarse_solve_ms;    /* their summed device time (HIP events around each launch)  */
+  double factor_ms;          /* device time of the coarse assembly and factorisation       */
+} hz_stats;
 
 /* Operators exposed by hz_apply (parity hooks; all act on the problem's own data). */
 typedef enum {
@@ -149,6 +158,10 @@ hz_status hz_apply(const hz_problem* pr, int op, const hz_c64* d_x, const hz_c64
 hz_status hz_solve_batched(hz_problem* const* probs, int nprob, const hz_c64* const* d_F,
                            int nrhs_per_prob, hz_c64* const* d_u, const hz_options* o,
                            hz_result* res, void* hip_stream);
+
+/* Copies the problem's counters into *out (waiting for pending timed launches) and, if
+ * reset is nonzero, zeroes them. Without timing the device times stay 0. */
+hz_status hz_problem_stats(hz_problem* pr, hz_stats* out, int reset);
 
 /* Frees everything the problem owns (NULL is a no-op). */
 void hz_destroy_problem(hz_problem* pr);

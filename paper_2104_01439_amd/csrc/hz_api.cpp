@@ -95,8 +95,14 @@ struct hz_problem {
   double gl_t[10], gl_w[10], lag[40];
   double setup_s = 0;
   std::atomic<int> busy{0};
+  // device-time counters (timing mode): event pairs around each coarse-solve launch
+  bool timing = false;
+  hz_stats stats{};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free, ev_pending;
   ~hz_problem() {
     if (pin) (void)hipHostFree(pin);
+    for (auto& e : ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    for (auto& e : ev_pending) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   }
 };
 
@@ -306,12 +312,58 @@ Level<float> level32(hz_problem* pr) {
   return l;
 }
 
+// Timing mode: event pairs around the coarse-solve launches, summed when complete.
+std::pair<hipEvent_t, hipEvent_t> take_events(hz_problem* pr) {
+  if (pr->ev_free.empty()) {
+    hipEvent_t a, b;
+    HZ_HIP(hipEventCreate(&a));
+    HZ_HIP(hipEventCreate(&b));
+    pr->ev_free.emplace_back(a, b);
+  }
+  auto e = pr->ev_free.back();
+  pr->ev_free.pop_back();
+  return e;
+}
+void collect_timing(hz_problem* pr, bool wait) {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> keep;
+  for (auto& e : pr->ev_pending) {
+    if (!wait && hipEventQuery(e.second) != hipSuccess) {
+      (void)hipGetLastError();
+      keep.push_back(e);
+      continue;
+    }
+    HZ_HIP(hipEventSynchronize(e.second));
+    float ms = 0;
+    HZ_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+    pr->stats.coarse_solve_ms += ms;
+    pr->ev_free.push_back(e);
+  }
+  pr->ev_pending.swap(keep);
+}
+
+template <typename T>
+void timed_coarse_solve(hz_problem* pr, const Level<T>& lv, const V2<T>* S, const V2<T>* b,
+                        V2<T>* y, hipStream_t st) {
+  pr->stats.coarse_solves += 1;
+  if (!pr->timing) {
+    coarse_solve<T>(pr->L, lv.coarse, S, b, y, 1, 0, lv.cw, st);
+    return;
+  }
+  auto e = take_events(pr);
+  HZ_HIP(hipEventRecord(e.first, st));
+  coarse_solve<T>(pr->L, lv.coarse, S, b, y, 1, 0, lv.cw, st);
+  HZ_HIP(hipEventRecord(e.second, st));
+  pr->ev_pending.push_back(e);
+  if (pr->ev_pending.size() > 64) collect_timing(pr, true);
+}
+
 // One twogrid V(nu, nu)-cycle from a zero initial guess (Algorithm 1, two levels):
 // nu damped Jacobi sweeps, r_c = P^T (f - A_eps u), e_c = A_c^{-1} r_c, u += P e_c,
 // nu sweeps. The last sweep writes z.
 template <typename T>
-void vcycle(const hz_problem* pr, const Level<T>& lv, int nu, const V2<T>* f, V2<T>* z,
+void vcycle(hz_problem* pr, const Level<T>& lv, int nu, const V2<T>* f, V2<T>* z,
             hipStream_t st) {
+  pr->stats.vcycles += 1;
   const int p = pr->p;
   V2<T>* cur = lv.ua;
   V2<T>* nxt = lv.ub;
@@ -327,7 +379,7 @@ void vcycle(const hz_problem* pr, const Level<T>& lv, int nu, const V2<T>* f, V2
     launch_stencil<T, T, T, T>(p, ST_RESID, lv.fine, cur, f, lv.rf, 1, 0, st);
     launch_restrict<T>(p, pr->M, pr->Mc, lv.rw, lv.rf, lv.rc, 1, 0, 0, st);
   }
-  coarse_solve<T>(pr->L, lv.coarse, lv.S, lv.rc, lv.ec, 1, 0, lv.cw, st);
+  timed_coarse_solve<T>(pr, lv, lv.S, lv.rc, lv.ec, st);
   launch_prolong<T>(p, pr->M, pr->Mc, lv.rw, lv.ec, cur, true, 1, 0, 0, st);
   if (nu == 0) {
     HZ_HIP(hipMemcpyAsync(z, cur, sizeof(V2<T>) * pr->N, hipMemcpyDeviceToDevice, st));
@@ -438,6 +490,7 @@ hz_status solve_impl(hz_problem* pr, const double2* F, double2* u, const hz_opti
       launch_reduce(pr->partial, pr->nblk, 1, hn, st);
       HZ_HIP(hipMemcpyAsync(pr->pin, pr->hbuf, 129 * 16, hipMemcpyDeviceToHost, st));
       HZ_HIP(hipStreamSynchronize(st));
+      if (pr->timing) collect_timing(pr, false);
       for (int i = 0; i <= j; ++i)
         Hat(i, j) = (cd(0, 0) + cd(pr->pin[i].x, pr->pin[i].y)) + cd(pr->pin[64 + i].x, pr->pin[64 + i].y);
       const double hnext = std::sqrt(pr->pin[128].x);
@@ -510,6 +563,7 @@ hz_status hz_default_options(hz_options* o) {
   o->maxit = 5000;
   o->tol = 1e-8;
   o->prec = HZ_FP64;
+  o->timing = 0;
   return HZ_OK;
 }
 
@@ -560,7 +614,23 @@ hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_option
       wk.R = pr->mem.alloc<double2>(mb * 32);
       wk.flag = pr->mem.alloc<int>(1);
       const DevOp<double> cop{pr->cAc, nullptr, pr->Mc};
+      pr->timing = opt.timing != 0;
+      hipEvent_t f0 = nullptr, f1 = nullptr;
+      if (pr->timing) {
+        HZ_HIP(hipEventCreate(&f0));
+        HZ_HIP(hipEventCreate(&f1));
+        HZ_HIP(hipEventRecord(f0, st));
+      }
       const hz_status fs = coarse_factor(pr->L, cop, pr->S, wk, st);
+      if (pr->timing) {
+        HZ_HIP(hipEventRecord(f1, st));
+        HZ_HIP(hipEventSynchronize(f1));
+        float ms = 0;
+        HZ_HIP(hipEventElapsedTime(&ms, f0, f1));
+        pr->stats.factor_ms = ms;
+        (void)hipEventDestroy(f0);
+        (void)hipEventDestroy(f1);
+      }
       pr->mem.release(wk.T);
       pr->mem.release(wk.W);
       pr->mem.release(wk.R);
@@ -675,7 +745,7 @@ hz_status hz_apply(const hz_problem* cpr, int op, const hz_c64* d_x, const hz_c6
         case HZ_OP_RESTRICT: launch_restrict<double>(p, pr->M, pr->Mc, pr->rw, x, y, 1, 0, 0, st); break;
         case HZ_OP_PROLONG: launch_prolong<double>(p, pr->M, pr->Mc, pr->rw, x, y, false, 1, 0, 0, st); break;
         case HZ_OP_VCYCLE: vcycle<double>(pr, lv, pr->opt.nu, x, y, st); break;
-        case HZ_OP_COARSE_SOLVE: coarse_solve<double>(pr->L, lv.coarse, pr->S, x, y, 1, 0, lv.cw, st); break;
+        case HZ_OP_COARSE_SOLVE: timed_coarse_solve<double>(pr, lv, pr->S, x, y, st); break;
         case HZ_OP_COARSE_A: launch_stencil<double, double, double, double>(p, ST_APPLY, lv.coarse, x, nullptr, y, 1, 0, st); break;
         case HZ_OP_RESID_RESTRICT:
           launch_stencil<double, double, double, double>(p, ST_RESID, lv.fine, x, f, pr->rf, 1, 0, st);
@@ -704,7 +774,7 @@ hz_status hz_apply(const hz_problem* cpr, int op, const hz_c64* d_x, const hz_c6
         case HZ_OP_RESTRICT: launch_restrict<float>(p, pr->M, pr->Mc, pr->frw, xin, yout, 1, 0, 0, st); break;
         case HZ_OP_PROLONG: launch_prolong<float>(p, pr->M, pr->Mc, pr->frw, xin, yout, false, 1, 0, 0, st); break;
         case HZ_OP_VCYCLE: vcycle<float>(pr, lv, pr->opt.nu, xin, yout, st); break;
-        case HZ_OP_COARSE_SOLVE: coarse_solve<float>(pr->L, lv.coarse, pr->Sf, xin, yout, 1, 0, lv.cw, st); break;
+        case HZ_OP_COARSE_SOLVE: timed_coarse_solve<float>(pr, lv, pr->Sf, xin, yout, st); break;
         case HZ_OP_COARSE_A: launch_stencil<float, float, float, float>(p, ST_APPLY, lv.coarse, xin, nullptr, yout, 1, 0, st); break;
         case HZ_OP_RESID_RESTRICT:
           launch_stencil<float, float, float, float>(p, ST_RESID, lv.fine, xin, pr->fb, pr->frf, 1, 0, st);
@@ -735,6 +805,24 @@ hz_status hz_solve_batched(hz_problem* const* probs, int nprob, const hz_c64* co
       if (stt != HZ_OK) return stt;
     }
   return HZ_OK;
+}
+
+hz_status hz_problem_stats(hz_problem* pr, hz_stats* out, int reset) {
+  if (!pr || !out) return fail(HZ_EINVAL, "null argument");
+  BusyGuard guard(pr->busy);
+  if (!guard.ok) return fail(HZ_EBUSY, "problem is in use");
+  try {
+    collect_timing(pr, true);
+    *out = pr->stats;
+    if (reset) {
+      const double f = pr->stats.factor_ms;
+      pr->stats = hz_stats{};
+      pr->stats.factor_ms = f;
+    }
+    return HZ_OK;
+  } catch (...) {
+    return map_exception();
+  }
 }
 
 void hz_destroy_problem(hz_problem* pr) { delete pr; }

@@ -28,7 +28,16 @@ class HZError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("nu", ctypes.c_int), ("omega", ctypes.c_double), ("restart", ctypes.c_int),
-                ("maxit", ctypes.c_int), ("tol", ctypes.c_double), ("prec", ctypes.c_int)]
+                ("maxit", ctypes.c_int), ("tol", ctypes.c_double), ("prec", ctypes.c_int),
+                ("timing", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("vcycles", ctypes.c_long), ("coarse_solves", ctypes.c_long),
+                ("coarse_solve_ms", ctypes.c_double), ("factor_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Result(ctypes.Structure):
@@ -60,6 +69,7 @@ _SIGS = {
     "hz_solve_batched": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_P),
                                         ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(Options),
                                         ctypes.POINTER(Result), _P]),
+    "hz_problem_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats), ctypes.c_int]),
     "hz_destroy_problem": (None, [_P]),
     "hz_last_error": (ctypes.c_char_p, []),
 }
@@ -99,10 +109,11 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def options(nu=2, omega=0.6, restart=50, maxit=5000, tol=1e-8, prec="fp64"):
+def options(nu=2, omega=0.6, restart=50, maxit=5000, tol=1e-8, prec="fp64", timing=False):
     o = Options()
     _check(lib().hz_default_options(ctypes.byref(o)))
     o.nu, o.omega, o.restart, o.maxit, o.tol, o.prec = nu, omega, restart, maxit, tol, _PREC[prec]
+    o.timing = 1 if timing else 0
     return o
 
 
@@ -121,10 +132,10 @@ class Problem:
     """create_problem(k, h, p, s): tables, coarse factor and Krylov workspace on the GPU."""
 
     def __init__(self, k, h, p, s, nu=2, omega=0.6, restart=50, maxit=5000, tol=1e-8,
-                 prec="fp64"):
+                 prec="fp64", timing=False):
         self.k, self.h, self.p, self.s = float(k), float(h), int(p), complex(s)
         self.n = int(round(1.0 / h))
-        self.opts = options(nu, omega, restart, maxit, tol, prec)
+        self.opts = options(nu, omega, restart, maxit, tol, prec, timing)
         self._h = ctypes.c_void_p()
         _check(lib().hz_create_problem(self.k, self.h, self.p, C64(self.s.real, self.s.imag),
                                        ctypes.byref(self.opts), _stream(), ctypes.byref(self._h)))
@@ -138,6 +149,11 @@ class Problem:
         n, nc, fp = ctypes.c_long(), ctypes.c_long(), ctypes.c_size_t()
         _check(lib().hz_problem_info(self._h, ctypes.byref(n), ctypes.byref(nc), ctypes.byref(fp)))
         return {"n_dofs": n.value, "n_coarse": nc.value, "footprint_bytes": fp.value}
+
+    def stats(self, reset=False):
+        st = Stats()
+        _check(lib().hz_problem_stats(self._h, ctypes.byref(st), 1 if reset else 0))
+        return st.as_dict()
 
     def empty(self, coarse=False):
         return torch.empty(self.Nc if coarse else self.N, dtype=torch.complex128, device="cuda")
