@@ -609,9 +609,9 @@ hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_option
     {
       CoarseFactorWork wk;
       const size_t mb = size_t(pr->L.size(0));
-      wk.T = pr->mem.alloc<double2>(mb * mb);
-      wk.W = pr->mem.alloc<double2>(mb * 32);
-      wk.R = pr->mem.alloc<double2>(mb * 32);
+      wk.T = pr->mem.alloc<double2>(2 * mb * mb);     // one set per factorisation chain
+      wk.W = pr->mem.alloc<double2>(2 * mb * 32);
+      wk.R = pr->mem.alloc<double2>(2 * mb * 32);
       wk.flag = pr->mem.alloc<int>(1);
       const DevOp<double> cop{pr->cAc, nullptr, pr->Mc};
       pr->timing = opt.timing != 0;

@@ -30,12 +30,14 @@ __device__ __forceinline__ double2 crecip(double2 a) {
 // Schur complement assembly
 // ------------------------------------------------------------------------------------------
 
-// Tm[r'][c] = sum_{c' in block j-1} S_{j-1}[r'][c'] A[c'][c],  c in block j.
-// A is symmetric, so A[c'][c] is the coefficient of the stencil of c at offset c' - c.
+// Schur complement of block j against one neighbour block jn = j -/+ 1 (its inverse Sn is
+// stored): D_j -= A_{j,jn} Sn A_{jn,j}, done in two sparse-dense passes.
+// Tm[r'][c] = sum_{c' in block jn} Sn[r'][c'] A[c'][c],  c in block j. A is symmetric, so
+// A[c'][c] is the coefficient of the stencil of c at offset c' - c.
 template <int P>
 __global__ void __launch_bounds__(256)
-k_schur_right(int j, int Mc, const double2* __restrict__ coef, const double2* __restrict__ Sprev,
-              int nprev, int ncur, double2* __restrict__ Tm) {
+k_schur_right(int j, int jn, int nc, int Mc, const double2* __restrict__ coef,
+              const double2* __restrict__ Sn, int nn, int ncur, double2* __restrict__ Tm) {
   constexpr int W = 2 * P + 1, W2 = W * W;
   const int c = blockIdx.x * 256 + threadIdx.x;
   const int rp = blockIdx.y;
@@ -44,30 +46,30 @@ k_schur_right(int j, int Mc, const double2* __restrict__ coef, const double2* __
   const int cls = (bc % P) * P + (ac % P);
   const int reg = region(bc, Mc) * 3 + region(ac, Mc);
   const double2* cc = coef + (cls * 9 + reg) * W2;
-  const double2* srow = Sprev + size_t(rp) * nprev;
+  const double2* srow = Sn + size_t(rp) * nn;
+  const int lo = P * jn, hi = P * jn + (jn < nc ? P : 1);   // lattice rows of block jn
   double2 acc = make_double2(0, 0);
 #pragma unroll
-  for (int dy = -P; dy <= -1; ++dy) {
+  for (int dy = -P; dy <= P; ++dy) {
     const int bb = bc + dy;
-    if (bb >= P * j) continue;
+    if (bb < lo || bb >= hi) continue;
 #pragma unroll
     for (int dx = -P; dx <= P; ++dx) {
       const int aa = ac + dx;
       if (aa < 0 || aa >= Mc) continue;
       const double2 cf = cc[(dy + P) * W + dx + P];
       if (cf.x == 0.0 && cf.y == 0.0) continue;
-      const int col = (bb - P * (j - 1)) * Mc + aa;
-      cfma(acc, cf, srow[col]);
+      cfma(acc, cf, srow[(bb - lo) * Mc + aa]);
     }
   }
   Tm[size_t(rp) * ncur + c] = acc;
 }
 
-// D[r][c] = A_jj[r][c] - sum_{r' in block j-1} A[r][r'] Tm[r'][c]   (Tm ignored for j = 0).
+// D[r][c] = (jn < 0 ? A_jj[r][c] : D[r][c]) - sum_{r' in block jn} A[r][r'] Tm[r'][c].
 template <int P>
 __global__ void __launch_bounds__(256)
-k_schur_left(int j, int Mc, const double2* __restrict__ coef, const double2* __restrict__ Tm,
-             int ncur, double2* __restrict__ D) {
+k_schur_left(int j, int jn, int nc, int Mc, const double2* __restrict__ coef,
+             const double2* __restrict__ Tm, int ncur, double2* __restrict__ D) {
   constexpr int W = 2 * P + 1, W2 = W * W;
   const int c = blockIdx.x * 256 + threadIdx.x;
   const int r = blockIdx.y;
@@ -76,23 +78,26 @@ k_schur_left(int j, int Mc, const double2* __restrict__ coef, const double2* __r
   const int cls = (br % P) * P + (ar % P);
   const int reg = region(br, Mc) * 3 + region(ar, Mc);
   const double2* cr = coef + (cls * 9 + reg) * W2;
-  double2 acc = make_double2(0, 0);
-  const int ac = c % Mc, bc = P * j + c / Mc;
-  const int dxa = ac - ar, dya = bc - br;
-  if (dxa >= -P && dxa <= P && dya >= -P && dya <= P) acc = cr[(dya + P) * W + dxa + P];
-  if (j > 0) {
+  double2 acc;
+  if (jn < 0) {
+    acc = make_double2(0, 0);
+    const int ac = c % Mc, bc = P * j + c / Mc;
+    const int dxa = ac - ar, dya = bc - br;
+    if (dxa >= -P && dxa <= P && dya >= -P && dya <= P) acc = cr[(dya + P) * W + dxa + P];
+  } else {
+    acc = D[size_t(r) * ncur + c];
+    const int lo = P * jn, hi = P * jn + (jn < nc ? P : 1);
 #pragma unroll
-    for (int dy = -P; dy <= -1; ++dy) {
+    for (int dy = -P; dy <= P; ++dy) {
       const int bb = br + dy;
-      if (bb >= P * j) continue;
+      if (bb < lo || bb >= hi) continue;
 #pragma unroll
       for (int dx = -P; dx <= P; ++dx) {
         const int aa = ar + dx;
         if (aa < 0 || aa >= Mc) continue;
         const double2 cf = cr[(dy + P) * W + dx + P];
         if (cf.x == 0.0 && cf.y == 0.0) continue;
-        const int rp = (bb - P * (j - 1)) * Mc + aa;
-        const double2 tv = Tm[size_t(rp) * ncur + c];
+        const double2 tv = Tm[size_t((bb - lo) * Mc + aa) * ncur + c];
         acc.x -= cf.x * tv.x - cf.y * tv.y;
         acc.y -= cf.x * tv.y + cf.y * tv.x;
       }
@@ -351,13 +356,131 @@ template <typename T> __global__ void k_fill_sentinel(V2<T>* a, long n, long str
   }
 }
 
-// 512 threads. Waves 0-1 ("exchange waves") gather the neighbour block (polling until it is
-// complete) and the right-hand side into LDS, combine the row sums and publish the results;
-// they never hold prefetched data, so their loads are never ordered behind the stream.
-// Waves 2-7 ("stream waves") split the columns of the workgroup's rows of S_j: each lane
-// forms the coupling values of its own columns from LDS, accumulates partial row sums and,
-// right after consuming a chunk, issues the loads of the next block's first chunk into the
-// same registers.
+// Twisted block solve. With m = nb / 2, the top chain runs blocks 0 .. m-1 and the bottom
+// chain blocks nb-1 .. m+1 (their inverses were formed against j-1 and j+1 respectively):
+//   forward   g_j = S_j (b_j - A_{j,j-1} g_{j-1})      (top)
+//             h_j = S_j (b_j - A_{j,j+1} h_{j+1})      (bottom)
+//   middle    x_m = S_m (b_m - A_{m,m-1} g_{m-1} - A_{m,m+1} h_{m+1})
+//   backward  x_j = g_j - S_j A_{j,j+1} x_{j+1}        (top, j = m-1 .. 0)
+//             x_j = h_j - S_j A_{j,j-1} x_{j-1}        (bottom, j = m+1 .. nb-1)
+// so one solve is 2 F + 1 dependent steps, F = max(m, nb - 1 - m), each moving up to two
+// blocks. The first half of the workgroups serves the top chain, the second half the bottom
+// chain; all of them share the middle block.
+struct StepPlan {
+  int active, j, nj, r0, r1;
+  int jpre, jfly;          // neighbour coupled in a pre-pass / on the fly (-1: none)
+  int fwd, mid;            // fwd: out = S t (gbuf; y for the middle), else out = g_j - S t (y)
+};
+
+template <int P>
+__device__ __forceinline__ StepPlan make_plan(int s, int g, int G, int nc, int Mc) {
+  const int nb = nc + 1, m = nb / 2, nt = m, nbt = nb - 1 - m, F = max(nt, nbt);
+  const int Gh = G / 2;
+  const bool top = g < Gh;
+  const int gl = top ? g : g - Gh;
+  StepPlan p;
+  p.active = 0; p.j = 0; p.jpre = -1; p.jfly = -1; p.fwd = 1; p.mid = 0;
+  if (s < F) {
+    if (top ? s < nt : s < nbt) {
+      p.active = 1;
+      p.j = top ? s : nb - 1 - s;
+      p.jfly = top ? (p.j > 0 ? p.j - 1 : -1) : (p.j < nb - 1 ? p.j + 1 : -1);
+    }
+  } else if (s == F) {
+    p.active = 1; p.mid = 1; p.j = m;
+    p.jpre = m > 0 ? m - 1 : -1;
+    p.jfly = m < nb - 1 ? m + 1 : -1;
+  } else {
+    const int q = s - F - 1;
+    if (top ? q < nt : q < nbt) {
+      p.active = 1; p.fwd = 0;
+      p.j = top ? m - 1 - q : m + 1 + q;
+      p.jfly = top ? p.j + 1 : p.j - 1;
+    }
+  }
+  p.nj = (p.j < nc ? P : 1) * Mc;
+  if (!p.active) { p.r0 = p.r1 = 0; }
+  else if (p.mid) { p.r0 = int((long(p.nj) * g) / G); p.r1 = int((long(p.nj) * (g + 1)) / G); }
+  else { p.r0 = int((long(p.nj) * gl) / Gh); p.r1 = int((long(p.nj) * (gl + 1)) / Gh); }
+  return p;
+}
+
+// Sum over the couplings of column c of block j into block jn of coef * value (the values of
+// block jn staged in LDS, row-major by lattice row).
+template <int P, typename T>
+__device__ __forceinline__ V2<T> coupling(int c, int j, int jn, int nc, int Mc,
+                                          const V2<T>* __restrict__ cl, const V2<T>* yv) {
+  constexpr int W = 2 * P + 1, W2 = W * W;
+  const int rl = c / Mc, ac = c - rl * Mc;
+  const int bc = P * j + rl;
+  const V2<T>* cc = cl + (((bc % P) * P + ac % P) * 9 + region(bc, Mc) * 3 + region(ac, Mc)) * W2;
+  const int lo = P * jn, hi = P * jn + (jn < nc ? P : 1);
+  V2<T> acc = czero<T>();
+#pragma unroll
+  for (int dy = -P; dy <= P; ++dy) {
+    const int bb = bc + dy;
+    if (bb < lo || bb >= hi) continue;
+    const V2<T>* yr = yv + (bb - lo) * Mc;
+#pragma unroll
+    for (int dx = -P; dx <= P; ++dx) {
+      const int aa = ac + dx;
+      if (aa < 0 || aa >= Mc) continue;
+      cfma(acc, cc[(dy + P) * W + dx + P], yr[aa]);
+    }
+  }
+  return acc;
+}
+
+// Polls block jn of src (stride sstride per right-hand side) until no value is the
+// sentinel, staging it into yv[h * nmax + .]; executed by the 128 exchange threads.
+template <int P, typename T, int ENT>
+__device__ __forceinline__ void gather_block(const V2<T>* src, long sstride, int jn, int nc,
+                                             int Mc, int nrhs, int nmax, V2<T>* yv, int xl,
+                                             int* err) {
+  const int nn = (jn < nc ? P : 1) * Mc;
+  const long d0 = long(P) * jn * Mc;
+  for (int h = 0; h < nrhs; ++h) {
+    const V2<T>* sh = src + h * sstride + d0;
+    V2<T>* yh = yv + h * nmax;
+    for (int i0 = 0; i0 < nn; i0 += 128 * ENT) {
+      unsigned pending = 0;
+#pragma unroll
+      for (int q = 0; q < ENT; ++q)
+        if (i0 + xl + 128 * q < nn) pending |= 1u << q;
+      unsigned rounds = 0;
+      while (pending) {
+        V2<T> v[ENT];
+#pragma unroll
+        for (int q = 0; q < ENT; ++q)
+          if (pending & (1u << q)) v[q] = ld_coh<T>(sh + i0 + xl + 128 * q);
+#pragma unroll
+        for (int q = 0; q < ENT; ++q)
+          if ((pending & (1u << q)) && !is_sentinel(v[q].x) && !is_sentinel(v[q].y)) {
+            yh[i0 + xl + 128 * q] = v[q];
+            pending &= ~(1u << q);
+          }
+        if (pending) {
+          ++rounds;
+          if ((rounds & 255u) == 0) {
+            if (rounds > (1u << 20)) {
+              __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+          }
+          if (rounds > 8) __builtin_amdgcn_s_sleep(1);
+        }
+      }
+    }
+  }
+}
+
+// 512 threads. Waves 0-1 ("exchange waves") gather neighbour results (polling) and the
+// right-hand side into LDS, combine the row sums and publish the results; they never hold
+// prefetched data, so their loads are never ordered behind the stream. Waves 2-7 ("stream
+// waves") split the columns of the workgroup's rows of S_j: each lane forms the coupling
+// values of its own columns from LDS, accumulates partial row sums and, right after
+// consuming its last chunk, issues the loads of its first chunk of the next step.
 constexpr int NSW = 6;   // stream waves
 
 template <int P, typename T, int NR, int RCH, int QCH>
@@ -370,10 +493,9 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, const V2<T>* __restrict__ coef,
   extern __shared__ char smem[];
   const int nmax = P * Mc;
   V2<T>* cl = reinterpret_cast<V2<T>*>(smem);  // coefficient table
-  V2<T>* t = cl + NCOEF;                       // [NR][nmax] right-hand side, then coupling vector
-  V2<T>* yn = t + NR * nmax;                   // [NR][nmax] neighbour block
+  V2<T>* t = cl + NCOEF;                       // [NR][nmax] b_j (or 0) minus the pre-pass term
+  V2<T>* yn = t + NR * nmax;                   // [NR][nmax] neighbour block (on-the-fly term)
   __shared__ T red[2][NSW][RCH][NR];
-  const int nb = nc + 1;
   const int G = gridDim.x, g = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int sw = wave - 2;                     // stream wave index (valid for wave >= 2)
@@ -385,69 +507,40 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, const V2<T>* __restrict__ coef,
   bool have = false;                           // sv holds the first chunk of this step
 
   for (int s = s_begin; s < s_end; ++s) {
-    const bool fwd = s < nb;
-    const int j = fwd ? s : 2 * nb - 2 - s;
-    const int nj = (j < nc ? P : 1) * Mc;
+    const StepPlan pl = make_plan<P>(s, g, G, nc, Mc);
+    const int j = pl.j, nj = pl.nj;
     const long dof0 = long(P) * j * Mc;
-    const int jn = fwd ? j - 1 : j + 1;
-    const bool has_n = fwd ? j > 0 : j < nc;
-    const int nn = has_n ? (jn < nc ? P : 1) * Mc : 0;
-    const long ndof0 = long(P) * jn * Mc;
-    // backward: x_{nc} is the forward result of the last block (in gbuf)
-    const bool from_g = fwd || jn == nc;
-    const V2<T>* src = from_g ? gbuf : y;
-    const long sstride = from_g ? Nc : cstride;
-    // 1a. exchange waves: right-hand side block (forward) and the polled neighbour block
-    if (wave < 2) {
-      const int xl = threadIdx.x;              // 0..127
-      if (fwd)
-        for (int idx = xl; idx < nj * nrhs; idx += 128) {
-          const int h = idx / nj, c = idx - h * nj;
-          t[h * nmax + c] = b[h * cstride + dof0 + c];
-        }
-      for (int h = 0; h < nrhs; ++h) {
-        const V2<T>* sh = src + h * sstride + ndof0;
-        V2<T>* yh = yn + h * nmax;
-        for (int i0 = 0; i0 < nn; i0 += 128 * ENT) {
-          unsigned pending = 0;
-#pragma unroll
-          for (int q = 0; q < ENT; ++q)
-            if (i0 + xl + 128 * q < nn) pending |= 1u << q;
-          unsigned rounds = 0;
-          while (pending) {
-            V2<T> v[ENT];
-#pragma unroll
-            for (int q = 0; q < ENT; ++q)
-              if (pending & (1u << q)) v[q] = ld_coh<T>(sh + i0 + xl + 128 * q);
-#pragma unroll
-            for (int q = 0; q < ENT; ++q)
-              if ((pending & (1u << q)) && !is_sentinel(v[q].x) && !is_sentinel(v[q].y)) {
-                yh[i0 + xl + 128 * q] = v[q];
-                pending &= ~(1u << q);
-              }
-            if (pending) {
-              ++rounds;
-              if ((rounds & 255u) == 0) {
-                if (rounds > (1u << 20)) {
-                  __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                  break;
-                }
-                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-              }
-              if (rounds > 8) __builtin_amdgcn_s_sleep(1);
-            }
-          }
-        }
+    // 1. exchange waves: right-hand side and the polled neighbour(s). The middle step couples
+    // two neighbours: the first is folded into t by all waves (LDS only) between two
+    // workgroup barriers; every barrier is reached by all waves (pl is uniform per workgroup).
+    if (wave < 2 && pl.active) {
+      const int xl = threadIdx.x;
+      for (int idx = xl; idx < nj * nrhs; idx += 128) {
+        const int h = idx / nj, c = idx - h * nj;
+        t[h * nmax + c] = pl.fwd ? b[h * cstride + dof0 + c] : czero<T>();
       }
+      if (pl.jpre >= 0) gather_block<P, T, ENT>(gbuf, Nc, pl.jpre, nc, Mc, nrhs, nmax, yn, xl, err);
+    }
+    if (pl.jpre >= 0) {
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < nj * nrhs; idx += 512) {
+        const int h = idx / nj, c = idx - h * nj;
+        const V2<T> cp = coupling<P, T>(c, j, pl.jpre, nc, Mc, cl, yn + h * nmax);
+        t[h * nmax + c] = csub<T>(t[h * nmax + c], cp);
+      }
+      __syncthreads();
+    }
+    if (wave < 2 && pl.active && pl.jfly >= 0) {
+      const bool from_g = pl.fwd;              // forward/middle neighbours are in gbuf
+      gather_block<P, T, ENT>(from_g ? gbuf : y, from_g ? Nc : cstride, pl.jfly, nc, Mc, nrhs,
+                              nmax, yn, threadIdx.x, err);
     }
     __syncthreads();
     // 2. rows [r0, r1) of S_j t in chunks of RCH rows; stream wave sw owns columns [c0, c1)
-    const int r0 = int((long(nj) * g) / G), r1 = int((long(nj) * (g + 1)) / G);
+    const int r0 = pl.r0, r1 = pl.r1;
     const int c0 = (nj * sw) / NSW, c1 = (nj * (sw + 1)) / NSW;
     const V2<T>* Sj = S + size_t(j) * bsz;
-    int bb_lo, bb_hi;                          // lattice rows of the neighbour block
-    if (fwd) { bb_lo = P * j - P; bb_hi = P * j - 1; }
-    else { bb_lo = P * (j + 1); bb_hi = min(P * (j + 1) + P - 1, Mc - 1); }
+    const T sgn = pl.fwd ? T(-1) : T(1);
     const bool pre = have;
     have = false;
     for (int rb = r0; rb < r1; rb += RCH) {
@@ -472,36 +565,14 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, const V2<T>* __restrict__ coef,
           for (int q = 0; q < QCH; ++q) {
             const int c = c0 + lane + 64 * (q0 + q);
             if (c >= c1) continue;
-            // coupling value of column c: t = b_j - A_{j,j-1} g_{j-1} (forward) or
-            // A_{j,j+1} x_{j+1} (backward), from the neighbour block staged in LDS
-            const int rl = c / Mc, ac = c - rl * Mc;
-            const int bc = P * j + rl;
-            const V2<T>* cc = cl + (((bc % P) * P + ac % P) * 9 + region(bc, Mc) * 3 + region(ac, Mc)) * W2;
 #pragma unroll
             for (int h = 0; h < NR; ++h) {
               if (h >= nrhs) continue;
-              V2<T> tv = fwd ? t[h * nmax + c] : czero<T>();
-              if (has_n) {
-#pragma unroll
-                for (int dyi = 1; dyi <= P; ++dyi) {
-                  const int dy = fwd ? -dyi : dyi;
-                  const int bb = bc + dy;
-                  if (bb < bb_lo || bb > bb_hi) continue;
-                  const V2<T>* ynr = yn + h * nmax + (bb - P * jn) * Mc;
-#pragma unroll
-                  for (int dx = -P; dx <= P; ++dx) {
-                    const int aa = ac + dx;
-                    if (aa < 0 || aa >= Mc) continue;
-                    const V2<T> cf = cc[(dy + P) * W + dx + P];
-                    const V2<T> v = ynr[aa];
-                    if (fwd) {
-                      tv.x -= cf.x * v.x - cf.y * v.y;
-                      tv.y -= cf.x * v.y + cf.y * v.x;
-                    } else {
-                      cfma(tv, cf, v);
-                    }
-                  }
-                }
+              V2<T> tv = t[h * nmax + c];
+              if (pl.jfly >= 0) {
+                const V2<T> cp = coupling<P, T>(c, j, pl.jfly, nc, Mc, cl, yn + h * nmax);
+                tv.x += sgn * cp.x;
+                tv.y += sgn * cp.y;
               }
 #pragma unroll
               for (int rr = 0; rr < RCH; ++rr) {
@@ -511,23 +582,23 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, const V2<T>* __restrict__ coef,
             }
           }
         }
-        // next block's first chunk, issued as soon as this step's last chunk is consumed
+        // first chunk of the next step, issued as soon as this step's last chunk is consumed
         if (rb + RCH >= r1 && s + 1 < s_end) {
-          const int s2 = s + 1;
-          const bool fwd2 = s2 < nb;
-          const int j2 = fwd2 ? s2 : 2 * nb - 2 - s2;
-          const int nj2 = (j2 < nc ? P : 1) * Mc;
-          const int r02 = int((long(nj2) * g) / G), r12 = int((long(nj2) * (g + 1)) / G);
-          const int c02 = (nj2 * sw) / NSW, c12 = (nj2 * (sw + 1)) / NSW;
-          const V2<T>* Sj2 = S + size_t(j2) * bsz;
+          const StepPlan pn = make_plan<P>(s + 1, g, G, nc, Mc);
+          if (pn.active && pn.r1 > pn.r0) {
+            const int nj2 = pn.nj;
+            const int c02 = (nj2 * sw) / NSW, c12 = (nj2 * (sw + 1)) / NSW;
+            const V2<T>* Sj2 = S + size_t(pn.j) * bsz;
 #pragma unroll
-          for (int rr = 0; rr < RCH; ++rr)
+            for (int rr = 0; rr < RCH; ++rr)
 #pragma unroll
-            for (int q = 0; q < QCH; ++q) {
-              const int c = c02 + lane + 64 * q;
-              sv[rr][q] = (r02 + rr < r12 && c < c12) ? Sj2[size_t(r02 + rr) * nj2 + c] : czero<T>();
-            }
-          have = true;
+              for (int q = 0; q < QCH; ++q) {
+                const int c = c02 + lane + 64 * q;
+                sv[rr][q] = (pn.r0 + rr < pn.r1 && c < c12) ? Sj2[size_t(pn.r0 + rr) * nj2 + c]
+                                                            : czero<T>();
+              }
+            have = true;
+          }
         }
 #pragma unroll
         for (int rr = 0; rr < RCH; ++rr)
@@ -549,10 +620,10 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, const V2<T>* __restrict__ coef,
             si += red[1][w2][rr][h];
           }
           V2<T> o;
-          if (fwd) {
+          if (pl.fwd) {
             o.x = sr;
             o.y = si;
-            st_coh<T>(gbuf + h * Nc + dof0 + r, o);
+            st_coh<T>((pl.mid ? y + h * cstride : gbuf + h * Nc) + dof0 + r, o);
           } else {
             o = ld_coh<T>(gbuf + h * Nc + dof0 + r);
             o.x -= sr;
@@ -566,21 +637,13 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, const V2<T>* __restrict__ coef,
   }
 }
 
-// Copies the forward result of the last block into the solution (x_{nc} = g_{nc}).
-template <typename T>
-__global__ void k_copy_last(const V2<T>* __restrict__ gbuf, V2<T>* __restrict__ y, long off,
-                            long n, long Nc, long cstride, int nrhs) {
-  const long i = long(blockIdx.x) * 256 + threadIdx.x;
-  if (i >= n) return;
-  for (int h = 0; h < nrhs; ++h) y[h * cstride + off + i] = gbuf[h * Nc + off + i];
-}
-
 template <int P, typename T, int NR, int RCH, int QCH>
 void csolve_launch(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b,
                    V2<T>* y, int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st) {
   auto kern = k_csolve<P, T, NR, RCH, QCH>;
-  const int nb = L.nblocks();
-  const int nsteps = 2 * nb - 1;
+  const int nb = L.nblocks(), m = nb / 2;
+  const int F = std::max(m, nb - 1 - m);
+  const int nsteps = 2 * F + 1;
   constexpr int NCOEF = P * P * 9 * (2 * P + 1) * (2 * P + 1);
   const size_t lds = (NCOEF + 2 * size_t(L.size(0)) * NR) * sizeof(V2<T>);
   // dynamic LDS beyond the default limit must be requested; the static part counts too
@@ -598,11 +661,13 @@ void csolve_launch(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, c
   int per_cu = 0;
   HZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 512, lds));
   const int max_coresident = per_cu * cus;
-  // balanced grid: R rows per workgroup, one workgroup per compute unit at most
+  // two chains, each with Gh workgroups holding R rows of a block (one per compute unit)
   const int n0 = int(L.size(0));
-  const int R = (n0 + cus - 1) / cus;
-  int G = (n0 + R - 1) / R;
-  const bool persistent = coop && w.persistent && max_coresident >= G && G > 0;
+  const int half = std::max(1, cus / 2);
+  const int R = (n0 + half - 1) / half;
+  const int Gh = (n0 + R - 1) / R;
+  const int G = 2 * Gh;
+  const bool persistent = coop && w.persistent && max_coresident >= G;
   int s_begin = 0, s_end = nsteps;
   V2<T>* gbuf = reinterpret_cast<V2<T>*>(w.g);
   int* err = w.err;
@@ -619,8 +684,6 @@ void csolve_launch(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, c
     for (int s = 0; s < nsteps; ++s)
       kern<<<G, 512, lds, st>>>(s, s + 1, L.nc, L.Mc, cop.coef, S, b, y, gbuf, nrhs, cstride, err);
   }
-  const long off = long(L.p) * L.nc * L.Mc;
-  k_copy_last<T><<<unsigned((L.Mc + 255) / 256), 256, 0, st>>>(gbuf, y, off, L.Mc, Nc, cstride, nrhs);
   HZ_HIP(hipGetLastError());
 }
 
@@ -628,36 +691,71 @@ template <int P, typename T>
 void csolve_p(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b, V2<T>* y,
               int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st) {
   if (nrhs == 1) {
-    csolve_launch<P, T, 1, 5, 4>(L, cop, S, b, y, 1, cstride, w, st);
+    csolve_launch<P, T, 1, 9, 3>(L, cop, S, b, y, 1, cstride, w, st);
     return;
   }
   for (int r0 = 0; r0 < nrhs; r0 += 4) {
     const int nr = std::min(4, nrhs - r0);
-    csolve_launch<P, T, 4, 2, 4>(L, cop, S, b + r0 * cstride, y + r0 * cstride, nr, cstride, w, st);
+    csolve_launch<P, T, 4, 3, 3>(L, cop, S, b + r0 * cstride, y + r0 * cstride, nr, cstride, w, st);
+  }
+}
+
+// Twisted block LU: the top chain factors blocks 0 .. m-1 downwards (D_j against j-1), the
+// bottom chain blocks nb-1 .. m+1 upwards (D_j against j+1), on two streams; the middle
+// block m takes both Schur complements. Each inverse is stored in place of its block.
+template <int P>
+void factor_block(const CoarseLayout& L, const DevOp<double>& cop, double2* S, int j, int jn1,
+                  int jn2, double2* T, double2* W, double2* R, int* flag, hipStream_t st) {
+  const int n = int(L.size(j));
+  double2* D = S + L.off(j);
+  const dim3 g2((n + 255) / 256, n);
+  k_schur_left<P><<<g2, 256, 0, st>>>(j, -1, L.nc, L.Mc, cop.coef, T, n, D);
+  for (int jn : {jn1, jn2}) {
+    if (jn < 0) continue;
+    const int nn = int(L.size(jn));
+    k_schur_right<P><<<dim3((n + 255) / 256, nn), 256, 0, st>>>(j, jn, L.nc, L.Mc, cop.coef,
+                                                                S + L.off(jn), nn, n, T);
+    k_schur_left<P><<<g2, 256, 0, st>>>(j, jn, L.nc, L.Mc, cop.coef, T, n, D);
+  }
+  const int tiles = (n + 31) / 32;
+  const int upd_blocks = (tiles * tiles + 3) / 4;
+  for (int k0 = 0; k0 < n; k0 += NB) {
+    const int wdt = std::min(NB, n - k0);
+    k_gj_panel<<<(n + 31) / 32, 256, 0, st>>>(D, n, k0, wdt, W, R, flag);
+    k_gj_update<<<upd_blocks, 256, 0, st>>>(D, n, k0, W, R);
   }
 }
 
 template <int P>
 void factor_p(const CoarseLayout& L, const DevOp<double>& cop, double2* S,
               const CoarseFactorWork& w, hipStream_t st) {
-  for (int j = 0; j < L.nblocks(); ++j) {
-    const int n = int(L.size(j));
-    double2* D = S + L.off(j);
-    if (j > 0) {
-      const int np = int(L.size(j - 1));
-      k_schur_right<P><<<dim3((n + 255) / 256, np), 256, 0, st>>>(j, L.Mc, cop.coef, S + L.off(j - 1),
-                                                                  np, n, w.T);
-    }
-    k_schur_left<P><<<dim3((n + 255) / 256, n), 256, 0, st>>>(j, L.Mc, cop.coef, w.T, n, D);
-    const int tiles = (n + 31) / 32;
-    const int upd_blocks = (tiles * tiles + 3) / 4;
-    for (int k0 = 0; k0 < n; k0 += NB) {
-      const int wdt = std::min(NB, n - k0);
-      k_gj_panel<<<(n + 31) / 32, 256, 0, st>>>(D, n, k0, wdt, w.W, w.R, w.flag);
-      k_gj_update<<<upd_blocks, 256, 0, st>>>(D, n, k0, w.W, w.R);
-    }
+  const int nb = L.nblocks(), m = nb / 2;
+  const size_t mb = size_t(L.size(0));
+  hipStream_t s2 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  HZ_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+  HZ_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+  HZ_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+  HZ_HIP(hipEventRecord(fork, st));
+  HZ_HIP(hipStreamWaitEvent(s2, fork, 0));
+  // top chain on st, bottom chain on s2 (own temporaries)
+  double2* T2 = w.T + mb * mb;
+  double2* W2 = w.W + mb * NB;
+  double2* R2 = w.R + mb * NB;
+  int step = 0;
+  for (int jt = 0, jb = nb - 1; jt < m || jb > m; ++jt, --jb, ++step) {
+    if (jt < m) factor_block<P>(L, cop, S, jt, jt > 0 ? jt - 1 : -1, -1, w.T, w.W, w.R, w.flag, st);
+    if (jb > m) factor_block<P>(L, cop, S, jb, jb < nb - 1 ? jb + 1 : -1, -1, T2, W2, R2, w.flag, s2);
   }
+  HZ_HIP(hipEventRecord(join, s2));
+  HZ_HIP(hipStreamWaitEvent(st, join, 0));
+  factor_block<P>(L, cop, S, m, m > 0 ? m - 1 : -1, m < nb - 1 ? m + 1 : -1, w.T, w.W, w.R,
+                  w.flag, st);
   HZ_HIP(hipGetLastError());
+  HZ_HIP(hipStreamSynchronize(st));
+  (void)hipEventDestroy(fork);
+  (void)hipEventDestroy(join);
+  (void)hipStreamDestroy(s2);
 }
 
 }  // namespace

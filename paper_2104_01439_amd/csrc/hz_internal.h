@@ -102,8 +102,8 @@ void launch_f2d(const float2* x, double2* y, long n, hipStream_t st);
 // Coarse factorisation: assembles and inverts every block in sequence. Returns HZ_OK or
 // HZ_ESINGULAR (pivot check on device, read back at the end).
 struct CoarseFactorWork {
-  double2* T = nullptr;      // temp block (max block size ^2)
-  double2* W = nullptr;      // GJ panel buffers
+  double2* T = nullptr;      // temp blocks, 2 x (max block size)^2 (one per chain)
+  double2* W = nullptr;      // Gauss-Jordan panel buffers, 2 x (max block size) x 32
   double2* R = nullptr;
   int* flag = nullptr;       // device error flag
 };
