@@ -20,21 +20,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
+from paper_2104_01439_amd.roofline import HBM_PEAK_GBS, coarse_solve_bytes  # noqa: E402
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
-
-
-def coarse_solve_bytes(n, p, itemsize=16):
-    """Algorithmic bytes of one coarse solve: every stored block inverse read twice
-    (forward and backward sweep), plus the coarse right-hand side and solution."""
-    nc = n // 2
-    Mc = p * nc + 1
-    blocks = nc * (p * Mc) ** 2 + Mc ** 2
-    bwd = blocks - Mc ** 2          # the last block is read in the forward sweep only
-    return (blocks + bwd) * itemsize + 3 * Mc * Mc * itemsize
 
 
 def cpu_baseline(cfg, iterations):

@@ -39,8 +39,9 @@ def _compile(src, obj):
     subprocess.run(cmd, check=True)
 
 
-def build(jobs=None, verbose=False):
-    """Compiles every source (in parallel) and links libhz.so; returns its path."""
+def build(jobs=None, verbose=False, out=None):
+    """Compiles every source (in parallel) and links libhz.so (or `out`); returns its path."""
+    lib_path = out or LIB
     from concurrent.futures import ThreadPoolExecutor
 
     tmp = tempfile.mkdtemp(prefix="hzbuild_")
@@ -49,18 +50,18 @@ def build(jobs=None, verbose=False):
         jobs = jobs or min(len(SOURCES), os.cpu_count() or 4)
         with ThreadPoolExecutor(jobs) as ex:
             list(ex.map(lambda a: _compile(*a), zip(SOURCES, objs)))
-        out_tmp = LIB + ".tmp"
+        out_tmp = lib_path + ".tmp"
         cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", out_tmp,
                "-L/opt/rocm/lib", "-lamdhip64"]
         subprocess.run(cmd, check=True)
-        os.replace(out_tmp, LIB)
+        os.replace(out_tmp, lib_path)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, out=sys.argv[1] if len(sys.argv) > 1 else None)
     sys.exit(0)
