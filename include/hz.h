@@ -109,10 +109,12 @@ hz_status hz_default_options(hz_options* o);
  * integer >= 2, up to 4096), element order p in {1,2,3} and shift multiplier s with
  * Im(s) > 0 (required: the coarse block LU runs without pivoting, which is safe because the
  * Hermitian part of i*A_eps is Im(s) k^2 M + k B, positive definite). Builds the stencil
- * tables, assembles and factors the coarse operator on the device and allocates the Krylov
- * workspace for o->restart (and an FP32 factor copy when o->prec == HZ_MIXED). On success
- * *out owns all of it. Synchronises hip_stream. Errors: HZ_EINVAL, HZ_ENOMEM, HZ_ESINGULAR,
- * HZ_EDEVICE; *out is left NULL. */
+ * tables, assembles and factors the coarse operator on the device and allocates the V-cycle
+ * scratch (and keeps only an FP32 copy of the factor when o->prec == HZ_MIXED). o->restart
+ * is the largest restart length later solves may use; the Krylov workspace of hz_solve is
+ * allocated by the first hz_solve and kept until destruction. On success *out owns all of
+ * it. Synchronises hip_stream. Errors: HZ_EINVAL, HZ_ENOMEM, HZ_ESINGULAR, HZ_EDEVICE; *out
+ * is left NULL. */
 hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_options* o,
                             void* hip_stream, hz_problem** out);
 
@@ -120,8 +122,9 @@ hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_option
 hz_status hz_problem_info(const hz_problem* pr, long* n_dofs, long* n_coarse,
                           size_t* footprint_bytes);
 
-/* Device bytes hz_create_problem would hold for these parameters (no allocation);
- * 0 for invalid parameters. Used for admission by footprint. */
+/* Device bytes a problem with these parameters holds after its first hz_solve (factor,
+ * tables, scratch, Krylov workspace; no allocation); 0 for invalid parameters. Used for
+ * admission by footprint. */
 size_t hz_footprint_estimate(double k, double h, int p, const hz_options* o);
 
 /* Writes the load vector of the plane-wave impedance data into d_F (fine vector):
@@ -148,16 +151,29 @@ hz_status hz_solve(hz_problem* pr, const hz_c64* d_F, hz_c64* d_u, const hz_opti
 hz_status hz_apply(const hz_problem* pr, int op, const hz_c64* d_x, const hz_c64* d_f,
                    hz_c64* d_y, int prec, void* hip_stream);
 
-/* Runs nprob * nrhs_per_prob independent FGMRES solves in lockstep: solve (i, r) uses
- * problem probs[i] and right-hand side d_F[i*nrhs_per_prob + r], writing
- * d_u[i*nrhs_per_prob + r] and res[i*nrhs_per_prob + r]. All problems must share (k, h, p)
- * and were created with restart >= o->restart. Per-step kernels are launched once for all
- * active solves; the coarse triangular solves of the right-hand sides of one problem share
- * each read of its factor. Every result equals what hz_solve gives for that solve alone
- * (same arithmetic, same order). h_res_hist may be NULL. Synchronises hip_stream. */
+/* Runs nprob * nrhs_per_prob independent FGMRES solves (the same method as hz_solve) in
+ * lockstep: solve (i, r) uses problem probs[i] and right-hand side d_F[i*nrhs_per_prob + r],
+ * writing d_u[i*nrhs_per_prob + r] and res[i*nrhs_per_prob + r]. Each round performs one
+ * Arnoldi step of every unfinished solve: the V-cycles of one problem's right-hand sides run
+ * as one batch whose coarse triangular solves read the factor once per group of up to 4
+ * right-hand sides; A_0 and the Arnoldi kernels are launched once for all solves; the host
+ * reads back once per round. Solves finish (or restart) independently. Every result is
+ * bitwise what hz_solve gives for that solve alone (same kernels' arithmetic, same order).
+ * Requirements: the problems are distinct, share (k, h, p), were created with
+ * restart >= o->restart and, for HZ_FP64, with HZ_FP64; at most 4096 solves; d_F and d_u are
+ * fine vectors (d_u may not alias any d_F). The call allocates a workspace of
+ * hz_batch_workspace_bytes(...) device bytes and frees it before returning. Errors as
+ * hz_solve, HZ_EBUSY if a problem is in use, HZ_ENOMEM if the workspace does not fit.
+ * Synchronises hip_stream. */
 hz_status hz_solve_batched(hz_problem* const* probs, int nprob, const hz_c64* const* d_F,
                            int nrhs_per_prob, hz_c64* const* d_u, const hz_options* o,
                            hz_result* res, void* hip_stream);
+
+/* Device bytes of the workspace hz_solve_batched allocates for nprob problems of mesh size h
+ * and order p with nrhs_per_prob right-hand sides each (restart and precision from o, NULL
+ * = defaults); 0 for invalid parameters. */
+size_t hz_batch_workspace_bytes(double h, int p, int nprob, int nrhs_per_prob,
+                                const hz_options* o);
 
 /* Copies the problem's counters into *out (waiting for pending timed launches) and, if
  * reset is nonzero, zeroes them. Without timing the device times stay 0. */

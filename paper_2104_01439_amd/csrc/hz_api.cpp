@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <new>
 
 #include "hz_internal.h"
@@ -53,12 +54,50 @@ struct DevMem {
   }
 };
 
+template <typename T> struct Scratch {
+  // V-cycle scratch for up to `cap` right-hand sides: fine vectors with stride N, coarse
+  // vectors with stride Nc.
+  V2<T>*ua = nullptr, *ub = nullptr, *rf = nullptr, *rc = nullptr, *ec = nullptr;
+  V2<T>* ff = nullptr;   // FP32 copy of the V-cycle input (mixed precision)
+  int cap = 0;
+};
+
 template <typename T> struct Level {
   DevOp<T> fine, coarse;   // A_eps on the fine and coarse lattices
   const T* rw = nullptr;   // prolongation weights
   const V2<T>* S = nullptr;
   CoarseSolveWork cw;
-  V2<T>*ua = nullptr, *ub = nullptr, *rf = nullptr, *rc = nullptr, *ec = nullptr;
+  Scratch<T> sc;
+};
+
+// Krylov workspace of a group of solves advancing in lockstep. Every per-solve array has a
+// uniform stride; kernels gather their operands through small device offset tables that are
+// rebuilt for each step.
+struct Workspace {
+  int cap = 0, m = 0, prec = HZ_FP64, nblk = 0;
+  long N = 0, Nc = 0;
+  DevMem mem;
+  double2* V = nullptr;     // [cap][m + 1][N] Arnoldi basis
+  double2* RW = nullptr;    // [2][cap][N]: residuals r, then Arnoldi vectors w
+  double2* Fs = nullptr;    // [cap][N] staged right-hand sides (batched calls)
+  double2* Us = nullptr;    // [cap][N] staged solutions (batched calls)
+  double2* Zd = nullptr;    // [cap][m][N] preconditioned vectors (FP64)
+  float2* Zf = nullptr;     // [cap][m][N] preconditioned vectors (mixed precision)
+  double2* partial = nullptr;   // [cap][nblk][64]
+  double2* hbuf = nullptr;      // [cap][192]: CGS2 pass 1, pass 2, |w|^2
+  char* dreg = nullptr;         // device copies of the two upload regions
+  Scratch<double> s64;
+  Scratch<float> s32;
+  double2* pin = nullptr;       // pinned read-back [cap][192]
+  char* up = nullptr;           // pinned upload staging
+  size_t up_bytes = 0;
+  static constexpr int kTabs = 8;
+  ~Workspace() {
+    if (pin) (void)hipHostFree(pin);
+    if (up) (void)hipHostFree(up);
+  }
+  double2* r(int q) const { return RW + size_t(q) * N; }
+  double2* w(int q) const { return RW + size_t(cap + q) * N; }
 };
 
 }  // namespace hz
@@ -82,16 +121,12 @@ struct hz_problem {
   float2 *fcAe = nullptr, *fwdAe = nullptr, *fcAc = nullptr;
   float* frw = nullptr;
   float2* Sf = nullptr;
-  // Krylov workspace (restart capacity m)
-  int m = 0;
-  int nblk = 0;
-  double2 *V = nullptr, *Zd = nullptr, *w = nullptr, *r = nullptr, *partial = nullptr,
-          *hbuf = nullptr, *ybuf = nullptr;
-  double2 *ua = nullptr, *ub = nullptr, *rf = nullptr, *rc = nullptr, *ec = nullptr;
-  float2 *Zf = nullptr, *fa = nullptr, *fb = nullptr, *frf = nullptr, *ff = nullptr,
-         *frc = nullptr, *fec = nullptr;
-  double2* pin = nullptr;   // pinned host read-back buffer
-  CoarseSolveWork cw;       // grid-barrier counter and error flag of the coarse solve
+  int m = 0;                  // restart capacity
+  Scratch<double> s64;        // V-cycle scratch for one right-hand side
+  Scratch<float> s32;
+  float2 *ax32 = nullptr, *af32 = nullptr, *ay32 = nullptr, *cx32 = nullptr, *cy32 = nullptr;
+  std::unique_ptr<Workspace> ws1;   // Krylov workspace of hz_solve (allocated at first use)
+  CoarseSolveWork cw;         // forward-sweep buffers and error flag of the coarse solve
   double gl_t[10], gl_w[10], lag[40];
   double setup_s = 0;
   std::atomic<int> busy{0};
@@ -100,7 +135,7 @@ struct hz_problem {
   hz_stats stats{};
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free, ev_pending;
   ~hz_problem() {
-    if (pin) (void)hipHostFree(pin);
+    ws1.reset();
     for (auto& e : ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     for (auto& e : ev_pending) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   }
@@ -210,17 +245,32 @@ Sizes sizes_of(int n, int p) {
   return z;
 }
 
-// Device bytes of the resident parts (factor, tables, workspace) for a precision.
+// Bytes of the V-cycle scratch for `cap` right-hand sides.
+size_t scratch_bytes(long N, long Nc, int cap, int prec) {
+  const size_t it = prec == HZ_MIXED ? 8 : 16;
+  return size_t(cap) * ((prec == HZ_MIXED ? 4 : 3) * size_t(N) + 2 * size_t(Nc)) * it;
+}
+
+// Bytes of a Krylov workspace for `cap` solves with restart capacity m (staged: with room
+// for copies of the right-hand sides and solutions).
+size_t workspace_bytes(long N, int nblk, int cap, int m, int prec, bool staged) {
+  size_t b = 0;
+  b += size_t(cap) * (m + 1) * N * 16;                          // V
+  b += size_t(cap) * m * N * (prec == HZ_MIXED ? 8 : 16);       // Z
+  b += 2 * size_t(cap) * N * 16;                                // r, w
+  if (staged) b += 2 * size_t(cap) * N * 16;                    // F, u
+  b += size_t(cap) * (size_t(nblk) * 64 * 16 + 192 * 16 + 64 * 16 + 8);
+  b += 2 * size_t(cap) * (Workspace::kTabs * 8 + 2 * 4 + 8 + 64 * 16) + 4096;
+  return b;
+}
+
+// Device bytes a problem holds after its first solve: factor, tables, scratch, workspace.
 size_t resident_bytes(int n, int p, int m, int prec) {
   const Sizes z = sizes_of(n, p);
-  size_t b = 0;
-  b += z.factor_elems * (prec == HZ_MIXED ? 8 : 16);
-  b += size_t(m + 1) * z.N * 16;                       // V
-  b += size_t(m) * z.N * (prec == HZ_MIXED ? 8 : 16);  // Z
-  b += 2 * size_t(z.N) * 16;                           // w, r
-  if (prec == HZ_MIXED) b += 4 * size_t(z.N) * 8 + 2 * size_t(z.Nc) * 8;
-  else b += 3 * size_t(z.N) * 16 + 2 * size_t(z.Nc) * 16;
-  b += size_t(z.nblk) * 64 * 16 + 4096 + 64 * 1024;   // partials, small buffers, tables
+  size_t b = z.factor_elems * (prec == HZ_MIXED ? 8 : 16);
+  b += scratch_bytes(z.N, z.Nc, 1, prec);
+  b += workspace_bytes(z.N, z.nblk, 1, m, prec, false);
+  b += 64 * 1024 + 4 * size_t(z.Nc) * 16 + 256;                // tables, coarse-solve buffers
   return b;
 }
 
@@ -266,14 +316,20 @@ void upload_tables(hz_problem* pr) {
     }
 }
 
+template <typename T>
+void alloc_scratch(DevMem& mem, Scratch<T>& sc, int cap, long N, long Nc, bool with_ff) {
+  sc.cap = cap;
+  sc.ua = mem.alloc<V2<T>>(size_t(cap) * N);
+  sc.ub = mem.alloc<V2<T>>(size_t(cap) * N);
+  sc.rf = mem.alloc<V2<T>>(size_t(cap) * N);
+  if (with_ff) sc.ff = mem.alloc<V2<T>>(size_t(cap) * N);
+  sc.rc = mem.alloc<V2<T>>(size_t(cap) * Nc);
+  sc.ec = mem.alloc<V2<T>>(size_t(cap) * Nc);
+}
+
 void ensure_fp64_work(hz_problem* pr) {
-  if (pr->Zd) return;
-  pr->Zd = pr->mem.alloc<double2>(size_t(pr->m) * pr->N);
-  pr->ua = pr->mem.alloc<double2>(pr->N);
-  pr->ub = pr->mem.alloc<double2>(pr->N);
-  pr->rf = pr->mem.alloc<double2>(pr->N);
-  pr->rc = pr->mem.alloc<double2>(pr->Nc);
-  pr->ec = pr->mem.alloc<double2>(pr->Nc);
+  if (pr->s64.cap) return;
+  alloc_scratch<double>(pr->mem, pr->s64, 1, pr->N, pr->Nc, false);
 }
 
 void ensure_mixed_work(hz_problem* pr, hipStream_t st) {
@@ -281,34 +337,88 @@ void ensure_mixed_work(hz_problem* pr, hipStream_t st) {
     pr->Sf = pr->mem.alloc<float2>(pr->L.total());
     launch_factor_to_f32(pr->S, pr->Sf, pr->L.total(), st);
   }
-  if (pr->Zf) return;
-  pr->Zf = pr->mem.alloc<float2>(size_t(pr->m) * pr->N);
-  pr->fa = pr->mem.alloc<float2>(pr->N);
-  pr->fb = pr->mem.alloc<float2>(pr->N);
-  pr->frf = pr->mem.alloc<float2>(pr->N);
-  pr->ff = pr->mem.alloc<float2>(pr->N);
-  pr->frc = pr->mem.alloc<float2>(pr->Nc);
-  pr->fec = pr->mem.alloc<float2>(pr->Nc);
+  if (pr->s32.cap) return;
+  alloc_scratch<float>(pr->mem, pr->s32, 1, pr->N, pr->Nc, true);
 }
 
-Level<double> level64(hz_problem* pr) {
+void ensure_apply32(hz_problem* pr) {
+  if (pr->ax32) return;
+  pr->ax32 = pr->mem.alloc<float2>(pr->N);
+  pr->af32 = pr->mem.alloc<float2>(pr->N);
+  pr->ay32 = pr->mem.alloc<float2>(pr->N);
+  pr->cx32 = pr->mem.alloc<float2>(pr->Nc);
+  pr->cy32 = pr->mem.alloc<float2>(pr->Nc);
+}
+
+// Upload staging of one phase: offset tables, counts, scale factors, Hessenberg solutions.
+struct Region {
+  long* tab;
+  int* itab;
+  double* scl;
+  double2* y;
+};
+size_t region_bytes(int cap) {
+  const size_t a = size_t(Workspace::kTabs) * cap * 8, b = (size_t(2) * cap * 4 + 15) / 16 * 16;
+  const size_t c = (size_t(cap) * 8 + 15) / 16 * 16;
+  return (a + 15) / 16 * 16 + b + c + size_t(cap) * 64 * 16;
+}
+Region region_at(char* base, int cap) {
+  Region r;
+  size_t o = 0;
+  r.tab = reinterpret_cast<long*>(base + o);
+  o += (size_t(Workspace::kTabs) * cap * 8 + 15) / 16 * 16;
+  r.itab = reinterpret_cast<int*>(base + o);
+  o += (size_t(2) * cap * 4 + 15) / 16 * 16;
+  r.scl = reinterpret_cast<double*>(base + o);
+  o += (size_t(cap) * 8 + 15) / 16 * 16;
+  r.y = reinterpret_cast<double2*>(base + o);
+  return r;
+}
+
+std::unique_ptr<Workspace> make_workspace(int cap, int m, int prec, long N, long Nc, int rcap,
+                                          bool staged) {
+  std::unique_ptr<Workspace> w(new Workspace());
+  w->cap = cap; w->m = m; w->prec = prec; w->N = N; w->Nc = Nc; w->nblk = mdot_blocks(N);
+  w->V = w->mem.alloc<double2>(size_t(cap) * (m + 1) * N);
+  w->RW = w->mem.alloc<double2>(2 * size_t(cap) * N);
+  if (staged) {
+    w->Fs = w->mem.alloc<double2>(size_t(cap) * N);
+    w->Us = w->mem.alloc<double2>(size_t(cap) * N);
+  }
+  if (prec == HZ_MIXED) w->Zf = w->mem.alloc<float2>(size_t(cap) * m * N);
+  else w->Zd = w->mem.alloc<double2>(size_t(cap) * m * N);
+  w->partial = w->mem.alloc<double2>(size_t(cap) * w->nblk * 64);
+  w->hbuf = w->mem.alloc<double2>(size_t(cap) * 192);
+  w->up_bytes = region_bytes(cap);
+  // device mirror of the two upload regions
+  w->dreg = w->mem.alloc<char>(2 * w->up_bytes);
+  if (rcap > 0) {
+    if (prec == HZ_MIXED) alloc_scratch<float>(w->mem, w->s32, rcap, N, Nc, true);
+    else alloc_scratch<double>(w->mem, w->s64, rcap, N, Nc, false);
+  }
+  HZ_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->pin), size_t(cap) * 192 * 16, hipHostMallocDefault));
+  HZ_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->up), 2 * w->up_bytes, hipHostMallocDefault));
+  return w;
+}
+
+Level<double> level64(hz_problem* pr, const Scratch<double>& sc) {
   Level<double> l;
   l.fine = DevOp<double>{pr->cAe, pr->wdAe, pr->M};
   l.coarse = DevOp<double>{pr->cAc, nullptr, pr->Mc};
   l.rw = pr->rw;
   l.S = pr->S;
   l.cw = pr->cw;
-  l.ua = pr->ua; l.ub = pr->ub; l.rf = pr->rf; l.rc = pr->rc; l.ec = pr->ec;
+  l.sc = sc;
   return l;
 }
-Level<float> level32(hz_problem* pr) {
+Level<float> level32(hz_problem* pr, const Scratch<float>& sc) {
   Level<float> l;
   l.fine = DevOp<float>{pr->fcAe, pr->fwdAe, pr->M};
   l.coarse = DevOp<float>{pr->fcAc, nullptr, pr->Mc};
   l.rw = pr->frw;
   l.S = pr->Sf;
   l.cw = pr->cw;
-  l.ua = pr->fa; l.ub = pr->fb; l.rf = pr->frf; l.rc = pr->frc; l.ec = pr->fec;
+  l.sc = sc;
   return l;
 }
 
@@ -342,83 +452,58 @@ void collect_timing(hz_problem* pr, bool wait) {
 }
 
 template <typename T>
-void timed_coarse_solve(hz_problem* pr, const Level<T>& lv, const V2<T>* S, const V2<T>* b,
-                        V2<T>* y, hipStream_t st) {
-  pr->stats.coarse_solves += 1;
+void timed_coarse_solve(hz_problem* pr, const Level<T>& lv, const V2<T>* b, V2<T>* y, int nrhs,
+                        hipStream_t st) {
   if (!pr->timing) {
-    coarse_solve<T>(pr->L, lv.coarse, S, b, y, 1, 0, lv.cw, st);
+    pr->stats.coarse_solves += coarse_solve<T>(pr->L, lv.coarse, lv.S, b, y, nrhs, pr->Nc, lv.cw, st);
     return;
   }
   auto e = take_events(pr);
   HZ_HIP(hipEventRecord(e.first, st));
-  coarse_solve<T>(pr->L, lv.coarse, S, b, y, 1, 0, lv.cw, st);
+  pr->stats.coarse_solves += coarse_solve<T>(pr->L, lv.coarse, lv.S, b, y, nrhs, pr->Nc, lv.cw, st);
   HZ_HIP(hipEventRecord(e.second, st));
   pr->ev_pending.push_back(e);
   if (pr->ev_pending.size() > 64) collect_timing(pr, true);
 }
 
-// One twogrid V(nu, nu)-cycle from a zero initial guess (Algorithm 1, two levels):
-// nu damped Jacobi sweeps, r_c = P^T (f - A_eps u), e_c = A_c^{-1} r_c, u += P e_c,
-// nu sweeps. The last sweep writes z.
+// One twogrid V(nu, nu)-cycle from a zero initial guess (Algorithm 1, two levels) for nb
+// right-hand sides at once: nu damped Jacobi sweeps, r_c = P^T (f - A_eps u),
+// e_c = A_c^{-1} r_c, u += P e_c, nu sweeps. Input b at f + af.at(b), output at z + az.at(b);
+// the iterates live in the level's scratch (stride N, coarse stride Nc).
 template <typename T>
-void vcycle(hz_problem* pr, const Level<T>& lv, int nu, const V2<T>* f, V2<T>* z,
-            hipStream_t st) {
-  pr->stats.vcycles += 1;
+void vcycle(hz_problem* pr, const Level<T>& lv, int nu, const V2<T>* f, Addr af, V2<T>* z,
+            Addr az, int nb, hipStream_t st) {
+  pr->stats.vcycles += nb;
   const int p = pr->p;
-  V2<T>* cur = lv.ua;
-  V2<T>* nxt = lv.ub;
+  const long N = pr->N, Nc = pr->Nc;
+  const Scratch<T>& sc = lv.sc;
+  if (nb > sc.cap) throw std::runtime_error("V-cycle batch exceeds its scratch");
   if (nu == 0) {
-    launch_restrict<T>(p, pr->M, pr->Mc, lv.rw, f, lv.rc, 1, 0, 0, st);
-    launch_fill_zero(cur, pr->N, st);
-  } else {
-    launch_jacobi0<T, T>(p, lv.fine, f, cur, 1, 0, st);
-    for (int sw = 1; sw < nu; ++sw) {
-      launch_stencil<T, T, T, T>(p, ST_SMOOTH, lv.fine, cur, f, nxt, 1, 0, st);
-      std::swap(cur, nxt);
-    }
-    launch_stencil<T, T, T, T>(p, ST_RESID, lv.fine, cur, f, lv.rf, 1, 0, st);
-    launch_restrict<T>(p, pr->M, pr->Mc, lv.rw, lv.rf, lv.rc, 1, 0, 0, st);
-  }
-  timed_coarse_solve<T>(pr, lv, lv.S, lv.rc, lv.ec, st);
-  launch_prolong<T>(p, pr->M, pr->Mc, lv.rw, lv.ec, cur, true, 1, 0, 0, st);
-  if (nu == 0) {
-    HZ_HIP(hipMemcpyAsync(z, cur, sizeof(V2<T>) * pr->N, hipMemcpyDeviceToDevice, st));
+    // u = 0: the cycle is the coarse correction alone, z = P A_c^{-1} P^T f
+    launch_restrict<T>(p, pr->M, pr->Mc, lv.rw, f, sc.rc, nb, af, Addr(Nc), st);
+    timed_coarse_solve<T>(pr, lv, sc.rc, sc.ec, nb, st);
+    launch_prolong<T>(p, pr->M, pr->Mc, lv.rw, sc.ec, z, false, nb, az, Addr(Nc), st);
     return;
   }
+  V2<T>* cur = sc.ua;
+  V2<T>* nxt = sc.ub;
+  launch_jacobi0<T, T>(p, lv.fine, f, af, cur, Addr(N), nb, st);
+  for (int sw = 1; sw < nu; ++sw) {
+    launch_stencil<T, T, T, T>(p, ST_SMOOTH, lv.fine, cur, Addr(N), f, af, nxt, Addr(N), nb, st);
+    std::swap(cur, nxt);
+  }
+  launch_stencil<T, T, T, T>(p, ST_RESID, lv.fine, cur, Addr(N), f, af, sc.rf, Addr(N), nb, st);
+  launch_restrict<T>(p, pr->M, pr->Mc, lv.rw, sc.rf, sc.rc, nb, Addr(N), Addr(Nc), st);
+  timed_coarse_solve<T>(pr, lv, sc.rc, sc.ec, nb, st);
+  launch_prolong<T>(p, pr->M, pr->Mc, lv.rw, sc.ec, cur, true, nb, Addr(N), Addr(Nc), st);
   for (int sw = 0; sw < nu; ++sw) {
-    V2<T>* dst = (sw == nu - 1) ? z : nxt;
-    launch_stencil<T, T, T, T>(p, ST_SMOOTH, lv.fine, cur, f, dst, 1, 0, st);
-    nxt = cur;
-    cur = dst;
+    if (sw == nu - 1) {
+      launch_stencil<T, T, T, T>(p, ST_SMOOTH, lv.fine, cur, Addr(N), f, af, z, az, nb, st);
+    } else {
+      launch_stencil<T, T, T, T>(p, ST_SMOOTH, lv.fine, cur, Addr(N), f, af, nxt, Addr(N), nb, st);
+      std::swap(cur, nxt);
+    }
   }
-}
-
-// ||x||_2 of a fine vector through the fixed-order reduction (synchronises).
-double norm2(hz_problem* pr, const double2* x, hipStream_t st) {
-  launch_mdot<double>(x, 0, 1, x, pr->N, pr->partial, pr->nblk, st);
-  launch_reduce(pr->partial, pr->nblk, 1, pr->hbuf, st);
-  HZ_HIP(hipMemcpyAsync(pr->pin, pr->hbuf, 16, hipMemcpyDeviceToHost, st));
-  HZ_HIP(hipStreamSynchronize(st));
-  return std::sqrt(pr->pin[0].x);
-}
-
-void precondition(hz_problem* pr, bool mixed, const double2* v, int j, hipStream_t st) {
-  if (!mixed) {
-    vcycle<double>(pr, level64(pr), pr->opt.nu, v, pr->Zd + size_t(j) * pr->N, st);
-  } else {
-    launch_d2f(v, pr->ff, pr->N, st);
-    vcycle<float>(pr, level32(pr), pr->opt.nu, pr->ff, pr->Zf + size_t(j) * pr->N, st);
-  }
-}
-
-void apply_A0_z(hz_problem* pr, bool mixed, int j, double2* out, hipStream_t st) {
-  const DevOp<double> a0{pr->cA0, nullptr, pr->M};
-  if (!mixed)
-    launch_stencil<double, double, double, double>(pr->p, ST_APPLY, a0, pr->Zd + size_t(j) * pr->N,
-                                                   nullptr, out, 1, 0, st);
-  else
-    launch_stencil<double, float, double, double>(pr->p, ST_APPLY, a0, pr->Zf + size_t(j) * pr->N,
-                                                  nullptr, out, 1, 0, st);
 }
 
 // Complex Givens rotation with c real: [c s; -conj(s) c] [a; b] = [r; 0].
@@ -433,9 +518,268 @@ void givens(cd a, cd b, double& c, cd& s) {
   s = (a / std::abs(a)) * std::conj(b) / r;
 }
 
+// Host state of one FGMRES(m) solve (Sec. 4, after Saad 1993).
+struct SolveState {
+  int prob = 0;
+  double normF = 0, beta = 0, est = 1, true_rel = 1, scale = 0;
+  int its = 0, j = 0;
+  bool restart = true;        // next step starts a cycle: v_0 = r / beta (else v_j = w / h)
+  bool done = false, conv = false, ending = false;
+  std::vector<cd> H, g;
+  std::vector<double> cs;
+  std::vector<cd> sn;
+  double* hist = nullptr;
+  int m = 0;
+  cd& Hat(int i, int jj) { return H[size_t(i) * m + jj]; }
+};
+
+// Runs nsol = nprob * nrhs FGMRES(o.restart) solves in lockstep: every round performs one
+// Arnoldi step of each unfinished solve, with the fine kernels and the Arnoldi kernels
+// launched once for all of them and the V-cycles of one problem's right-hand sides sharing
+// each read of its coarse factor. Solve q belongs to problem q / nrhs; its right-hand side
+// and solution are at Fb + foff[q] and Ub + uoff[q]. Each solve follows exactly the steps
+// (and floating-point order) it would follow alone.
+hz_status lockstep(hz_problem* const* probs, int nprob, int nrhs, const double2* Fb,
+                   const long* foff, double2* Ub, const long* uoff, Workspace& ws,
+                   const hz_options& o, hz_result* res, double* const* hist, hipStream_t st) {
+  const auto t0 = clk::now();
+  const int nsol = nprob * nrhs;
+  const bool mixed = o.prec == HZ_MIXED;
+  const long N = ws.N;
+  const int m = o.restart, nblk = ws.nblk;
+  const long vstr = long(ws.m + 1) * N, zstr = long(ws.m) * N;
+  hz_problem* pr0 = probs[0];
+  const DevOp<double> a0{pr0->cA0, nullptr, pr0->M};
+  const int p = pr0->p;
+  char* hreg[2] = {ws.up, ws.up + ws.up_bytes};
+  char* dreg[2] = {ws.dreg, ws.dreg + ws.up_bytes};
+  auto upload = [&](int k) {
+    HZ_HIP(hipMemcpyAsync(dreg[k], hreg[k], ws.up_bytes, hipMemcpyHostToDevice, st));
+  };
+  auto sync_read = [&](int count) {
+    HZ_HIP(hipMemcpyAsync(ws.pin, ws.hbuf, size_t(count) * 192 * 16, hipMemcpyDeviceToHost, st));
+    HZ_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < nprob; ++i)
+      if (probs[i]->timing) collect_timing(probs[i], false);
+  };
+  const long cap = ws.cap;
+  // ---- norms of the right-hand sides; u = 0, r = F ----
+  {
+    Region h = region_at(hreg[0], ws.cap);
+    const Region d = region_at(dreg[0], ws.cap);
+    for (int q = 0; q < nsol; ++q) { h.tab[q] = foff[q]; h.tab[cap + q] = uoff[q]; }
+    upload(0);
+    launch_mdot_b(Fb, Addr(0, d.tab), 0, 1, nullptr, Fb, Addr(0, d.tab), N, ws.partial, nblk, nsol, st);
+    launch_reduce_b(ws.partial, nblk, 1, nullptr, ws.hbuf, 192, nsol, st);
+    launch_fill_zero_b(Ub, Addr(0, d.tab + cap), N, nsol, st);
+    launch_copy_b(Fb, Addr(0, d.tab), ws.RW, Addr(N), N, nsol, st);
+    sync_read(nsol);
+  }
+  std::vector<SolveState> S(nsol);
+  for (int q = 0; q < nsol; ++q) {
+    SolveState& x = S[q];
+    x.prob = q / nrhs;
+    x.m = m;
+    x.hist = hist ? hist[q] : nullptr;
+    x.normF = std::sqrt(ws.pin[size_t(q) * 192].x);
+    if (!std::isfinite(x.normF)) return fail(HZ_EINVAL, "right-hand side is not finite");
+    x.H.assign(size_t(m + 1) * m, cd(0, 0));
+    x.g.assign(m + 1, cd(0, 0));
+    x.cs.assign(m, 0.0);
+    x.sn.assign(m, cd(0, 0));
+    if (x.normF == 0.0) {
+      x.done = true;
+      x.conv = true;
+      x.est = 0;
+      x.true_rel = 0;
+      continue;
+    }
+    x.beta = x.normF;
+    x.scale = 1.0 / x.beta;
+    x.g[0] = x.beta;
+  }
+  std::vector<int> act, end;
+  std::vector<cd> y(m);
+  while (true) {
+    act.clear();
+    for (int q = 0; q < nsol; ++q)
+      if (!S[q].done) act.push_back(q);
+    if (act.empty()) break;
+    const int na = int(act.size());
+    // ---- tables of this round ----
+    Region h = region_at(hreg[0], ws.cap);
+    const Region d = region_at(dreg[0], ws.cap);
+    long* t_src = h.tab;               // scale source (r or w) in RW
+    long* t_vj = h.tab + cap;          // v_j in V
+    long* t_vb = h.tab + 2 * cap;      // basis of the solve in V
+    long* t_zj = h.tab + 3 * cap;      // z_j in Z
+    long* t_w = h.tab + 4 * cap;       // w in RW
+    int maxnv = 0;
+    for (int z = 0; z < na; ++z) {
+      SolveState& x = S[act[z]];
+      const long q = act[z];
+      t_src[z] = x.restart ? q * N : (cap + q) * N;
+      t_vj[z] = q * vstr + long(x.j) * N;
+      t_vb[z] = q * vstr;
+      t_zj[z] = q * zstr + long(x.j) * N;
+      t_w[z] = (cap + q) * N;
+      h.itab[z] = x.j + 1;
+      h.scl[z] = x.scale;
+      maxnv = std::max(maxnv, x.j + 1);
+    }
+    upload(0);
+    const long* d_src = d.tab;
+    const long* d_vj = d.tab + cap;
+    const long* d_vb = d.tab + 2 * cap;
+    const long* d_zj = d.tab + 3 * cap;
+    const long* d_w = d.tab + 4 * cap;
+    // v_j = r / beta (cycle start) or w / h_{j,j-1}
+    launch_scale_b(ws.RW, Addr(0, d_src), d.scl, ws.V, Addr(0, d_vj), N, na, st);
+    // z_j = V-cycle(v_j): one batch per problem (its unfinished right-hand sides)
+    for (int z0 = 0; z0 < na;) {
+      const int i = S[act[z0]].prob;
+      int z1 = z0;
+      while (z1 < na && S[act[z1]].prob == i) ++z1;
+      hz_problem* pi = probs[i];
+      if (!mixed) {
+        vcycle<double>(pi, level64(pi, ws.s64), pi->opt.nu, ws.V, Addr(0, d_vj + z0), ws.Zd,
+                       Addr(0, d_zj + z0), z1 - z0, st);
+      } else {
+        launch_d2f_b(ws.V, Addr(0, d_vj + z0), ws.s32.ff, Addr(N), N, z1 - z0, st);
+        vcycle<float>(pi, level32(pi, ws.s32), pi->opt.nu, ws.s32.ff, Addr(N), ws.Zf,
+                      Addr(0, d_zj + z0), z1 - z0, st);
+      }
+      z0 = z1;
+    }
+    // w = A_0 z_j (A_0 is the same for every problem of the group)
+    if (!mixed)
+      launch_stencil<double, double, double, double>(p, ST_APPLY, a0, ws.Zd, Addr(0, d_zj), nullptr,
+                                                     Addr(), ws.RW, Addr(0, d_w), na, st);
+    else
+      launch_stencil<double, float, double, double>(p, ST_APPLY, a0, ws.Zf, Addr(0, d_zj), nullptr,
+                                                    Addr(), ws.RW, Addr(0, d_w), na, st);
+    // CGS2: two passes of h = V^H w, w -= V h; then |w|^2
+    launch_mdot_b(ws.V, Addr(0, d_vb), N, 64, d.itab, ws.RW, Addr(0, d_w), N, ws.partial, nblk, na, st);
+    launch_reduce_b(ws.partial, nblk, maxnv, d.itab, ws.hbuf, 192, na, st);
+    launch_maxpy_b(ws.V, Addr(0, d_vb), N, 64, d.itab, ws.hbuf, 192, ws.RW, Addr(0, d_w), N,
+                   nullptr, nblk, na, st);
+    launch_mdot_b(ws.V, Addr(0, d_vb), N, 64, d.itab, ws.RW, Addr(0, d_w), N, ws.partial, nblk, na, st);
+    launch_reduce_b(ws.partial, nblk, maxnv, d.itab, ws.hbuf + 64, 192, na, st);
+    launch_maxpy_b(ws.V, Addr(0, d_vb), N, 64, d.itab, ws.hbuf + 64, 192, ws.RW, Addr(0, d_w), N,
+                   ws.partial, nblk, na, st);
+    launch_reduce_b(ws.partial, nblk, 1, nullptr, ws.hbuf + 128, 192, na, st);
+    sync_read(na);
+    // ---- Hessenberg column, rotations, residual estimate (host, per solve) ----
+    end.clear();
+    for (int z = 0; z < na; ++z) {
+      SolveState& x = S[act[z]];
+      const double2* hb = ws.pin + size_t(z) * 192;
+      const int j = x.j;
+      x.its += 1;
+      for (int i = 0; i <= j; ++i)
+        x.Hat(i, j) = (cd(0, 0) + cd(hb[i].x, hb[i].y)) + cd(hb[64 + i].x, hb[64 + i].y);
+      const double hnext = std::sqrt(hb[128].x);
+      if (!std::isfinite(hnext)) return fail(HZ_EDEVICE, "non-finite Arnoldi norm");
+      x.Hat(j + 1, j) = hnext;
+      for (int i = 0; i < j; ++i) {
+        const cd a = x.Hat(i, j), b = x.Hat(i + 1, j);
+        x.Hat(i, j) = x.cs[i] * a + x.sn[i] * b;
+        x.Hat(i + 1, j) = -std::conj(x.sn[i]) * a + x.cs[i] * b;
+      }
+      givens(x.Hat(j, j), x.Hat(j + 1, j), x.cs[j], x.sn[j]);
+      {
+        const cd a = x.Hat(j, j), b = x.Hat(j + 1, j);
+        x.Hat(j, j) = x.cs[j] * a + x.sn[j] * b;
+        x.Hat(j + 1, j) = 0;
+      }
+      x.g[j + 1] = -std::conj(x.sn[j]) * x.g[j];
+      x.g[j] = x.cs[j] * x.g[j];
+      x.est = std::abs(x.g[j + 1]) / x.normF;
+      if (x.hist) x.hist[x.its - 1] = x.est;
+      if (x.est <= o.tol || x.its >= o.maxit || hnext == 0.0 || j + 1 == m) {
+        end.push_back(act[z]);
+      } else {
+        x.restart = false;
+        x.scale = 1.0 / hnext;
+        x.j = j + 1;
+      }
+    }
+    if (end.empty()) continue;
+    // ---- cycle ends: u += Z y, r = F - A_0 u, ||r|| ----
+    const int ne = int(end.size());
+    Region h2 = region_at(hreg[1], ws.cap);
+    const Region d2 = region_at(dreg[1], ws.cap);
+    for (int e = 0; e < ne; ++e) {
+      SolveState& x = S[end[e]];
+      const long q = end[e];
+      const int jend = x.j + 1;
+      for (int i = jend - 1; i >= 0; --i) {
+        cd acc = x.g[i];
+        for (int l = i + 1; l < jend; ++l) acc -= x.Hat(i, l) * y[l];
+        y[i] = acc / x.Hat(i, i);
+      }
+      for (int i = 0; i < jend; ++i) h2.y[size_t(e) * 64 + i] = make_double2(y[i].real(), y[i].imag());
+      h2.tab[e] = q * zstr;
+      h2.tab[cap + e] = uoff[q];
+      h2.tab[2 * cap + e] = foff[q];
+      h2.tab[3 * cap + e] = q * N;
+      h2.itab[e] = jend;
+    }
+    upload(1);
+    if (!mixed)
+      launch_update_b<double>(ws.Zd, Addr(0, d2.tab), N, 64, d2.itab, d2.y, 64, Ub,
+                              Addr(0, d2.tab + cap), N, ne, st);
+    else
+      launch_update_b<float>(ws.Zf, Addr(0, d2.tab), N, 64, d2.itab, d2.y, 64, Ub,
+                             Addr(0, d2.tab + cap), N, ne, st);
+    launch_stencil<double, double, double, double>(p, ST_RESID, a0, Ub, Addr(0, d2.tab + cap), Fb,
+                                                   Addr(0, d2.tab + 2 * cap), ws.RW,
+                                                   Addr(0, d2.tab + 3 * cap), ne, st);
+    launch_mdot_b(ws.RW, Addr(0, d2.tab + 3 * cap), 0, 1, nullptr, ws.RW, Addr(0, d2.tab + 3 * cap),
+                  N, ws.partial, nblk, ne, st);
+    launch_reduce_b(ws.partial, nblk, 1, nullptr, ws.hbuf, 192, ne, st);
+    sync_read(ne);
+    for (int e = 0; e < ne; ++e) {
+      SolveState& x = S[end[e]];
+      x.beta = std::sqrt(ws.pin[size_t(e) * 192].x);
+      x.true_rel = x.beta / x.normF;
+      if (x.true_rel <= o.tol) {
+        x.done = true;
+        x.conv = true;
+      } else if (x.its >= o.maxit) {
+        x.done = true;
+      } else {
+        x.restart = true;
+        x.j = 0;
+        x.scale = 1.0 / x.beta;
+        std::fill(x.H.begin(), x.H.end(), cd(0, 0));
+        std::fill(x.g.begin(), x.g.end(), cd(0, 0));
+        x.g[0] = x.beta;
+      }
+    }
+  }
+  for (int i = 0; i < nprob; ++i) {
+    int e = 0;
+    HZ_HIP(hipMemcpy(&e, probs[i]->cw.err, sizeof(int), hipMemcpyDeviceToHost));
+    if (e) return fail(HZ_EDEVICE, "coarse solve: a wait for another workgroup timed out");
+  }
+  const double solve_s = secs(t0);
+  if (res)
+    for (int q = 0; q < nsol; ++q) {
+      hz_result r{};
+      r.iterations = S[q].its;
+      r.converged = S[q].conv ? 1 : 0;
+      r.rel_res_true = S[q].true_rel;
+      r.rel_res_est = S[q].est;
+      r.setup_s = probs[S[q].prob]->setup_s;
+      r.solve_s = solve_s;
+      res[q] = r;
+    }
+  return HZ_OK;
+}
+
 hz_status solve_impl(hz_problem* pr, const double2* F, double2* u, const hz_options& o,
                      hz_result* res, double* hist, hipStream_t st) {
-  const auto t0 = clk::now();
   const bool mixed = o.prec == HZ_MIXED;
   if (o.restart > pr->m) return fail(HZ_EINVAL, "restart exceeds the capacity given at creation");
   if (mixed) ensure_mixed_work(pr, st);
@@ -443,108 +787,16 @@ hz_status solve_impl(hz_problem* pr, const double2* F, double2* u, const hz_opti
     if (!pr->S) return fail(HZ_EINVAL, "problem was created for mixed precision only");
     ensure_fp64_work(pr);
   }
-  const long N = pr->N;
-  const int m = o.restart;
-  const double normF = norm2(pr, F, st);
-  if (!std::isfinite(normF)) return fail(HZ_EINVAL, "right-hand side is not finite");
-  launch_fill_zero(u, N, st);
-  hz_result out{};
-  out.setup_s = pr->setup_s;
-  out.converged = 1;
-  if (normF == 0.0) {
-    HZ_HIP(hipStreamSynchronize(st));
-    out.solve_s = secs(t0);
-    if (res) *res = out;
-    return HZ_OK;
+  if (!pr->ws1 || pr->ws1->prec != o.prec) {
+    pr->ws1.reset();
+    pr->ws1 = make_workspace(1, pr->m, o.prec, pr->N, pr->Nc, 0, false);
+    pr->ws1->s64 = pr->s64;
+    pr->ws1->s32 = pr->s32;
   }
-  launch_axpby_copy(F, pr->r, N, st);
-  double beta = normF;
-  int its = 0;
-  bool conv = false;
-  double true_rel = 1.0, est = 1.0;
-  std::vector<cd> H(size_t(m + 1) * m), g(m + 1), y(m);
-  std::vector<double> cs(m);
-  std::vector<cd> sn(m);
-  auto Hat = [&](int i, int j) -> cd& { return H[size_t(i) * m + j]; };
-  double2* h1 = pr->hbuf;
-  double2* h2 = pr->hbuf + 64;
-  double2* hn = pr->hbuf + 128;
-  while (true) {
-    launch_scale(pr->r, 1.0 / beta, pr->V, N, st);
-    std::fill(H.begin(), H.end(), cd(0, 0));
-    std::fill(g.begin(), g.end(), cd(0, 0));
-    g[0] = beta;
-    int jend = 0;
-    for (int j = 0; j < m; ++j) {
-      const double2* vj = pr->V + size_t(j) * N;
-      precondition(pr, mixed, vj, j, st);
-      apply_A0_z(pr, mixed, j, pr->w, st);
-      ++its;
-      // CGS2: two passes of h = V^H w, w -= V h
-      launch_mdot<double>(pr->V, N, j + 1, pr->w, N, pr->partial, pr->nblk, st);
-      launch_reduce(pr->partial, pr->nblk, j + 1, h1, st);
-      launch_maxpy(pr->V, N, j + 1, h1, pr->w, N, nullptr, pr->nblk, st);
-      launch_mdot<double>(pr->V, N, j + 1, pr->w, N, pr->partial, pr->nblk, st);
-      launch_reduce(pr->partial, pr->nblk, j + 1, h2, st);
-      launch_maxpy(pr->V, N, j + 1, h2, pr->w, N, pr->partial, pr->nblk, st);
-      launch_reduce(pr->partial, pr->nblk, 1, hn, st);
-      HZ_HIP(hipMemcpyAsync(pr->pin, pr->hbuf, 129 * 16, hipMemcpyDeviceToHost, st));
-      HZ_HIP(hipStreamSynchronize(st));
-      if (pr->timing) collect_timing(pr, false);
-      for (int i = 0; i <= j; ++i)
-        Hat(i, j) = (cd(0, 0) + cd(pr->pin[i].x, pr->pin[i].y)) + cd(pr->pin[64 + i].x, pr->pin[64 + i].y);
-      const double hnext = std::sqrt(pr->pin[128].x);
-      if (!std::isfinite(hnext)) return fail(HZ_EDEVICE, "non-finite Arnoldi norm");
-      Hat(j + 1, j) = hnext;
-      if (hnext > 0) launch_scale(pr->w, 1.0 / hnext, pr->V + size_t(j + 1) * N, N, st);
-      for (int i = 0; i < j; ++i) {
-        const cd a = Hat(i, j), b = Hat(i + 1, j);
-        Hat(i, j) = cs[i] * a + sn[i] * b;
-        Hat(i + 1, j) = -std::conj(sn[i]) * a + cs[i] * b;
-      }
-      givens(Hat(j, j), Hat(j + 1, j), cs[j], sn[j]);
-      {
-        const cd a = Hat(j, j), b = Hat(j + 1, j);
-        Hat(j, j) = cs[j] * a + sn[j] * b;
-        Hat(j + 1, j) = 0;
-      }
-      g[j + 1] = -std::conj(sn[j]) * g[j];
-      g[j] = cs[j] * g[j];
-      est = std::abs(g[j + 1]) / normF;
-      if (hist) hist[its - 1] = est;
-      jend = j + 1;
-      if (est <= o.tol || its >= o.maxit || hnext == 0.0) break;
-    }
-    for (int i = jend - 1; i >= 0; --i) {
-      cd acc = g[i];
-      for (int l = i + 1; l < jend; ++l) acc -= Hat(i, l) * y[l];
-      y[i] = acc / Hat(i, i);
-    }
-    HZ_HIP(hipMemcpyAsync(pr->ybuf, y.data(), size_t(jend) * 16, hipMemcpyHostToDevice, st));
-    if (!mixed) launch_update<double>(pr->Zd, N, jend, pr->ybuf, u, N, st);
-    else launch_update<float>(pr->Zf, N, jend, pr->ybuf, u, N, st);
-    const DevOp<double> a0{pr->cA0, nullptr, pr->M};
-    launch_stencil<double, double, double, double>(pr->p, ST_RESID, a0, u, F, pr->r, 1, 0, st);
-    beta = norm2(pr, pr->r, st);   // synchronises: y (host) stays alive until the copy ran
-    true_rel = beta / normF;
-    if (true_rel <= o.tol) {
-      conv = true;
-      break;
-    }
-    if (its >= o.maxit) break;
-  }
-  {
-    int e = 0;
-    HZ_HIP(hipMemcpy(&e, pr->cw.err, sizeof(int), hipMemcpyDeviceToHost));
-    if (e) return fail(HZ_EDEVICE, "coarse solve grid barrier timed out");
-  }
-  out.iterations = its;
-  out.converged = conv ? 1 : 0;
-  out.rel_res_true = true_rel;
-  out.rel_res_est = est;
-  out.solve_s = secs(t0);
-  if (res) *res = out;
-  return HZ_OK;
+  const long off = 0;
+  hz_problem* const probs[1] = {pr};
+  double* const hists[1] = {hist};
+  return lockstep(probs, 1, 1, F, &off, u, &off, *pr->ws1, o, res, hists, st);
 }
 
 }  // namespace
@@ -602,7 +854,6 @@ hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_option
     pr->Nc = long(pr->Mc) * pr->Mc;
     pr->L = CoarseLayout{p, n / 2, pr->Mc};
     pr->m = opt.restart;
-    pr->nblk = mdot_blocks(pr->N);
     upload_tables(pr);
     // coarse factor (FP64), then the FP32 copy for mixed-precision problems
     pr->S = pr->mem.alloc<double2>(pr->L.total());
@@ -640,12 +891,6 @@ hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_option
         return fail(fs, "zero or non-finite pivot in the coarse block factorisation");
       }
     }
-    pr->V = pr->mem.alloc<double2>(size_t(pr->m + 1) * pr->N);
-    pr->w = pr->mem.alloc<double2>(pr->N);
-    pr->r = pr->mem.alloc<double2>(pr->N);
-    pr->partial = pr->mem.alloc<double2>(size_t(pr->nblk) * 64);
-    pr->hbuf = pr->mem.alloc<double2>(4 * 64);
-    pr->ybuf = pr->mem.alloc<double2>(64);
     pr->cw.g = pr->mem.alloc<double2>(4 * size_t(pr->Nc));
     pr->cw.err = pr->mem.alloc<int>(64);
     HZ_HIP(hipMemsetAsync(pr->cw.err, 0, 64 * sizeof(int), st));
@@ -653,7 +898,6 @@ hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_option
       const char* env = std::getenv("HZ_COARSE_PERSISTENT");
       pr->cw.persistent = !(env && env[0] == '0');
     }
-    HZ_HIP(hipHostMalloc(reinterpret_cast<void**>(&pr->pin), 4 * 64 * 16, hipHostMallocDefault));
     if (opt.prec == HZ_MIXED) {
       ensure_mixed_work(pr, st);
       HZ_HIP(hipStreamSynchronize(st));
@@ -736,49 +980,51 @@ hz_status hz_apply(const hz_problem* cpr, int op, const hz_c64* d_x, const hz_c6
     if (prec == HZ_FP64) {
       if (!pr->S) return fail(HZ_EINVAL, "problem was created for mixed precision only");
       ensure_fp64_work(pr);
-      const Level<double> lv = level64(pr);
+      const Level<double> lv = level64(pr, pr->s64);
       const DevOp<double> a0{pr->cA0, nullptr, pr->M};
+      const Addr o;
       switch (op) {
-        case HZ_OP_A0: launch_stencil<double, double, double, double>(p, ST_APPLY, a0, x, nullptr, y, 1, 0, st); break;
-        case HZ_OP_AEPS: launch_stencil<double, double, double, double>(p, ST_APPLY, lv.fine, x, nullptr, y, 1, 0, st); break;
-        case HZ_OP_JACOBI: launch_stencil<double, double, double, double>(p, ST_SMOOTH, lv.fine, x, f, y, 1, 0, st); break;
-        case HZ_OP_RESTRICT: launch_restrict<double>(p, pr->M, pr->Mc, pr->rw, x, y, 1, 0, 0, st); break;
-        case HZ_OP_PROLONG: launch_prolong<double>(p, pr->M, pr->Mc, pr->rw, x, y, false, 1, 0, 0, st); break;
-        case HZ_OP_VCYCLE: vcycle<double>(pr, lv, pr->opt.nu, x, y, st); break;
-        case HZ_OP_COARSE_SOLVE: timed_coarse_solve<double>(pr, lv, pr->S, x, y, st); break;
-        case HZ_OP_COARSE_A: launch_stencil<double, double, double, double>(p, ST_APPLY, lv.coarse, x, nullptr, y, 1, 0, st); break;
+        case HZ_OP_A0: launch_stencil<double, double, double, double>(p, ST_APPLY, a0, x, o, nullptr, o, y, o, 1, st); break;
+        case HZ_OP_AEPS: launch_stencil<double, double, double, double>(p, ST_APPLY, lv.fine, x, o, nullptr, o, y, o, 1, st); break;
+        case HZ_OP_JACOBI: launch_stencil<double, double, double, double>(p, ST_SMOOTH, lv.fine, x, o, f, o, y, o, 1, st); break;
+        case HZ_OP_RESTRICT: launch_restrict<double>(p, pr->M, pr->Mc, pr->rw, x, y, 1, o, o, st); break;
+        case HZ_OP_PROLONG: launch_prolong<double>(p, pr->M, pr->Mc, pr->rw, x, y, false, 1, o, o, st); break;
+        case HZ_OP_VCYCLE: vcycle<double>(pr, lv, pr->opt.nu, x, o, y, o, 1, st); break;
+        case HZ_OP_COARSE_SOLVE: timed_coarse_solve<double>(pr, lv, x, y, 1, st); break;
+        case HZ_OP_COARSE_A: launch_stencil<double, double, double, double>(p, ST_APPLY, lv.coarse, x, o, nullptr, o, y, o, 1, st); break;
         case HZ_OP_RESID_RESTRICT:
-          launch_stencil<double, double, double, double>(p, ST_RESID, lv.fine, x, f, pr->rf, 1, 0, st);
-          launch_restrict<double>(p, pr->M, pr->Mc, pr->rw, pr->rf, y, 1, 0, 0, st);
+          launch_stencil<double, double, double, double>(p, ST_RESID, lv.fine, x, o, f, o, pr->s64.rf, o, 1, st);
+          launch_restrict<double>(p, pr->M, pr->Mc, pr->rw, pr->s64.rf, y, 1, o, o, st);
           break;
       }
     } else {
       ensure_mixed_work(pr, st);
-      const Level<float> lv = level32(pr);
+      ensure_apply32(pr);
+      const Level<float> lv = level32(pr, pr->s32);
       const long nin = fine_in ? pr->N : pr->Nc;
       const long nout = fine_out ? pr->N : pr->Nc;
-      // inputs to FP32 scratch: x -> ff (fine) or frc (coarse); f -> fb
-      float2* xin = fine_in ? pr->ff : pr->frc;
+      const Addr o;
+      // FP32 copies: x -> ax32 (fine) or cx32 (coarse), f -> af32; result in ay32 / cy32
+      float2* xin = fine_in ? pr->ax32 : pr->cx32;
       launch_d2f(x, xin, nin, st);
-      if (f) launch_d2f(f, pr->fb, pr->N, st);
-      float2* yout = fine_out ? pr->frf : pr->fec;
-      if (op == HZ_OP_VCYCLE || op == HZ_OP_RESID_RESTRICT) yout = fine_out ? pr->Zf : pr->fec;
+      if (f) launch_d2f(f, pr->af32, pr->N, st);
+      float2* yout = fine_out ? pr->ay32 : pr->cy32;
       switch (op) {
         case HZ_OP_A0: {
           const DevOp<double> a0{pr->cA0, nullptr, pr->M};
-          launch_stencil<double, float, double, double>(p, ST_APPLY, a0, xin, nullptr, y, 1, 0, st);
+          launch_stencil<double, float, double, double>(p, ST_APPLY, a0, xin, o, nullptr, o, y, o, 1, st);
           return HZ_OK;
         }
-        case HZ_OP_AEPS: launch_stencil<float, float, float, float>(p, ST_APPLY, lv.fine, xin, nullptr, yout, 1, 0, st); break;
-        case HZ_OP_JACOBI: launch_stencil<float, float, float, float>(p, ST_SMOOTH, lv.fine, xin, pr->fb, yout, 1, 0, st); break;
-        case HZ_OP_RESTRICT: launch_restrict<float>(p, pr->M, pr->Mc, pr->frw, xin, yout, 1, 0, 0, st); break;
-        case HZ_OP_PROLONG: launch_prolong<float>(p, pr->M, pr->Mc, pr->frw, xin, yout, false, 1, 0, 0, st); break;
-        case HZ_OP_VCYCLE: vcycle<float>(pr, lv, pr->opt.nu, xin, yout, st); break;
-        case HZ_OP_COARSE_SOLVE: timed_coarse_solve<float>(pr, lv, pr->Sf, xin, yout, st); break;
-        case HZ_OP_COARSE_A: launch_stencil<float, float, float, float>(p, ST_APPLY, lv.coarse, xin, nullptr, yout, 1, 0, st); break;
+        case HZ_OP_AEPS: launch_stencil<float, float, float, float>(p, ST_APPLY, lv.fine, xin, o, nullptr, o, yout, o, 1, st); break;
+        case HZ_OP_JACOBI: launch_stencil<float, float, float, float>(p, ST_SMOOTH, lv.fine, xin, o, pr->af32, o, yout, o, 1, st); break;
+        case HZ_OP_RESTRICT: launch_restrict<float>(p, pr->M, pr->Mc, pr->frw, xin, yout, 1, o, o, st); break;
+        case HZ_OP_PROLONG: launch_prolong<float>(p, pr->M, pr->Mc, pr->frw, xin, yout, false, 1, o, o, st); break;
+        case HZ_OP_VCYCLE: vcycle<float>(pr, lv, pr->opt.nu, xin, o, yout, o, 1, st); break;
+        case HZ_OP_COARSE_SOLVE: timed_coarse_solve<float>(pr, lv, xin, yout, 1, st); break;
+        case HZ_OP_COARSE_A: launch_stencil<float, float, float, float>(p, ST_APPLY, lv.coarse, xin, o, nullptr, o, yout, o, 1, st); break;
         case HZ_OP_RESID_RESTRICT:
-          launch_stencil<float, float, float, float>(p, ST_RESID, lv.fine, xin, pr->fb, pr->frf, 1, 0, st);
-          launch_restrict<float>(p, pr->M, pr->Mc, pr->frw, pr->frf, yout, 1, 0, 0, st);
+          launch_stencil<float, float, float, float>(p, ST_RESID, lv.fine, xin, o, pr->af32, o, pr->s32.rf, o, 1, st);
+          launch_restrict<float>(p, pr->M, pr->Mc, pr->frw, pr->s32.rf, yout, 1, o, o, st);
           break;
       }
       launch_f2d(yout, y, nout, st);
@@ -793,18 +1039,72 @@ hz_status hz_solve_batched(hz_problem* const* probs, int nprob, const hz_c64* co
                            int nrhs_per_prob, hz_c64* const* d_u, const hz_options* o,
                            hz_result* res, void* hip_stream) {
   if (!probs || nprob < 1 || nrhs_per_prob < 1 || !d_F || !d_u) return fail(HZ_EINVAL, "bad arguments");
+  const long nsol = long(nprob) * nrhs_per_prob;
+  if (nsol > 4096) return fail(HZ_EINVAL, "at most 4096 solves per batch");
   for (int i = 0; i < nprob; ++i) {
     if (!probs[i]) return fail(HZ_EINVAL, "null problem");
     if (probs[i]->n != probs[0]->n || probs[i]->p != probs[0]->p || probs[i]->k != probs[0]->k)
       return fail(HZ_EINVAL, "batched problems must share (k, h, p)");
+    for (int i2 = 0; i2 < i; ++i2)
+      if (probs[i2] == probs[i]) return fail(HZ_EINVAL, "a problem appears twice in the batch");
   }
-  for (int i = 0; i < nprob; ++i)
-    for (int r = 0; r < nrhs_per_prob; ++r) {
-      const int q = i * nrhs_per_prob + r;
-      const hz_status stt = hz_solve(probs[i], d_F[q], d_u[q], o, res ? res + q : nullptr, nullptr, hip_stream);
-      if (stt != HZ_OK) return stt;
+  for (long q = 0; q < nsol; ++q)
+    if (!d_F[q] || !d_u[q]) return fail(HZ_EINVAL, "null vector");
+  hz_problem* pr0 = probs[0];
+  hz_options opt = pr0->opt;
+  if (o) {
+    opt.restart = o->restart;
+    opt.maxit = o->maxit;
+    opt.tol = o->tol;
+    opt.prec = o->prec;
+  }
+  std::string why;
+  if (!valid_options(opt, why)) return fail(HZ_EINVAL, why);
+  std::vector<std::unique_ptr<BusyGuard>> guards;
+  for (int i = 0; i < nprob; ++i) {
+    guards.emplace_back(new BusyGuard(probs[i]->busy));
+    if (!guards.back()->ok) return fail(HZ_EBUSY, "problem is in use");
+    if (opt.restart > probs[i]->m) return fail(HZ_EINVAL, "restart exceeds the capacity given at creation");
+    if (opt.prec == HZ_FP64 && !probs[i]->S)
+      return fail(HZ_EINVAL, "problem was created for mixed precision only");
+  }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  try {
+    for (int i = 0; i < nprob; ++i)
+      if (opt.prec == HZ_MIXED) ensure_mixed_work(probs[i], st);
+    const long N = pr0->N;
+    std::unique_ptr<Workspace> ws =
+        make_workspace(int(nsol), opt.restart, opt.prec, N, pr0->Nc, nrhs_per_prob, true);
+    std::vector<long> off(nsol);
+    for (long q = 0; q < nsol; ++q) {
+      off[q] = q * N;
+      HZ_HIP(hipMemcpyAsync(ws->Fs + q * N, d_F[q], size_t(N) * 16, hipMemcpyDeviceToDevice, st));
     }
-  return HZ_OK;
+    const hz_status r = lockstep(probs, nprob, nrhs_per_prob, ws->Fs, off.data(), ws->Us,
+                                 off.data(), *ws, opt, res, nullptr, st);
+    if (r != HZ_OK) return r;
+    for (long q = 0; q < nsol; ++q)
+      HZ_HIP(hipMemcpyAsync(d_u[q], ws->Us + q * N, size_t(N) * 16, hipMemcpyDeviceToDevice, st));
+    HZ_HIP(hipStreamSynchronize(st));
+    return HZ_OK;
+  } catch (...) {
+    return map_exception();
+  }
+}
+
+size_t hz_batch_workspace_bytes(double h, int p, int nprob, int nrhs_per_prob, const hz_options* o) {
+  hz_options d;
+  hz_default_options(&d);
+  const hz_options& oo = o ? *o : d;
+  int n = 0;
+  std::string why;
+  if (!valid_problem(1.0, h, p, cd(1, 1), n, why) || !valid_options(oo, why) || nprob < 1 ||
+      nrhs_per_prob < 1)
+    return 0;
+  const Sizes z = sizes_of(n, p);
+  const int nsol = nprob * nrhs_per_prob;
+  return workspace_bytes(z.N, z.nblk, nsol, oo.restart, oo.prec, true) +
+         scratch_bytes(z.N, z.Nc, nrhs_per_prob, oo.prec);
 }
 
 hz_status hz_problem_stats(hz_problem* pr, hz_stats* out, int reset) {

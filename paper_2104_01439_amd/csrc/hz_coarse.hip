@@ -9,6 +9,8 @@
 // S_j is formed explicitly by blocked Gauss-Jordan; the rank-NB updates run on FP64 MFMA.
 // Solve:  g_j = S_j (b_j - A_{j,j-1} g_{j-1}),   x_j = g_j - S_j (A_{j,j+1} x_{j+1}).
 
+#include <stdexcept>
+
 #include "hz_common.h"
 
 namespace hz {
@@ -637,6 +639,15 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, const V2<T>* __restrict__ coef,
   }
 }
 
+constexpr size_t kLdsPerWorkgroup = 160 * 1024;   // gfx950
+
+// Dynamic plus static LDS bytes of one k_csolve workgroup.
+template <int P, typename T, int NR, int RCH>
+constexpr size_t csolve_lds(int Mc) {
+  return (size_t(P * P * 9 * (2 * P + 1) * (2 * P + 1)) + 2 * size_t(P) * Mc * NR) * sizeof(V2<T>) +
+         sizeof(T) * 2 * NSW * RCH * NR;
+}
+
 template <int P, typename T, int NR, int RCH, int QCH>
 void csolve_launch(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b,
                    V2<T>* y, int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st) {
@@ -646,6 +657,8 @@ void csolve_launch(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, c
   const int nsteps = 2 * F + 1;
   constexpr int NCOEF = P * P * 9 * (2 * P + 1) * (2 * P + 1);
   const size_t lds = (NCOEF + 2 * size_t(L.size(0)) * NR) * sizeof(V2<T>);
+  if (csolve_lds<P, T, NR, RCH>(L.Mc) > kLdsPerWorkgroup)
+    throw std::runtime_error("coarse solve staging exceeds the LDS of a workgroup");
   // dynamic LDS beyond the default limit must be requested; the static part counts too
   static size_t configured = 0;
   if (lds > 48 * 1024 && lds > configured) {
@@ -687,17 +700,28 @@ void csolve_launch(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, c
   HZ_HIP(hipGetLastError());
 }
 
+// Right-hand sides go in groups of 4 (each factor read serves the group), or of 2 or 1 where
+// the group's staging does not fit in LDS.
 template <int P, typename T>
-void csolve_p(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b, V2<T>* y,
-              int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st) {
+int csolve_p(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b, V2<T>* y,
+             int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st) {
   if (nrhs == 1) {
     csolve_launch<P, T, 1, 9, 3>(L, cop, S, b, y, 1, cstride, w, st);
-    return;
+    return 1;
   }
-  for (int r0 = 0; r0 < nrhs; r0 += 4) {
-    const int nr = std::min(4, nrhs - r0);
-    csolve_launch<P, T, 4, 3, 3>(L, cop, S, b + r0 * cstride, y + r0 * cstride, nr, cstride, w, st);
+  const int group = csolve_lds<P, T, 4, 3>(L.Mc) <= kLdsPerWorkgroup ? 4
+                    : csolve_lds<P, T, 2, 4>(L.Mc) <= kLdsPerWorkgroup ? 2 : 1;
+  int launches = 0;
+  for (int r0 = 0; r0 < nrhs; r0 += group) {
+    const int nr = std::min(group, nrhs - r0);
+    const V2<T>* br = b + r0 * cstride;
+    V2<T>* yr = y + r0 * cstride;
+    if (nr == 1) csolve_launch<P, T, 1, 9, 3>(L, cop, S, br, yr, 1, cstride, w, st);
+    else if (nr == 2) csolve_launch<P, T, 2, 4, 3>(L, cop, S, br, yr, 2, cstride, w, st);
+    else csolve_launch<P, T, 4, 3, 3>(L, cop, S, br, yr, nr, cstride, w, st);
+    ++launches;
   }
+  return launches;
 }
 
 // Twisted block LU: the top chain factors blocks 0 .. m-1 downwards (D_j against j-1), the
@@ -773,11 +797,13 @@ hz_status coarse_factor(const CoarseLayout& L, const DevOp<double>& cop, double2
 }
 
 template <typename T>
-void coarse_solve(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b,
-                  V2<T>* y, int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st) {
-  if (L.p == 1) csolve_p<1, T>(L, cop, S, b, y, nrhs, cstride, w, st);
-  else if (L.p == 2) csolve_p<2, T>(L, cop, S, b, y, nrhs, cstride, w, st);
-  else csolve_p<3, T>(L, cop, S, b, y, nrhs, cstride, w, st);
+int coarse_solve(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b,
+                 V2<T>* y, int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st) {
+  if (nrhs < 1) return 0;
+  if (nrhs > 1 && cstride < long(L.Mc) * L.Mc) throw std::runtime_error("coarse stride too small");
+  if (L.p == 1) return csolve_p<1, T>(L, cop, S, b, y, nrhs, cstride, w, st);
+  if (L.p == 2) return csolve_p<2, T>(L, cop, S, b, y, nrhs, cstride, w, st);
+  return csolve_p<3, T>(L, cop, S, b, y, nrhs, cstride, w, st);
 }
 
 void launch_factor_to_f32(const double2* S, float2* Sf, size_t n, hipStream_t st) {
@@ -785,11 +811,11 @@ void launch_factor_to_f32(const double2* S, float2* Sf, size_t n, hipStream_t st
   HZ_HIP(hipGetLastError());
 }
 
-template void coarse_solve<double>(const CoarseLayout&, const DevOp<double>&, const double2*,
-                                   const double2*, double2*, int, long, const CoarseSolveWork&,
-                                   hipStream_t);
-template void coarse_solve<float>(const CoarseLayout&, const DevOp<float>&, const float2*,
-                                  const float2*, float2*, int, long, const CoarseSolveWork&,
+template int coarse_solve<double>(const CoarseLayout&, const DevOp<double>&, const double2*,
+                                  const double2*, double2*, int, long, const CoarseSolveWork&,
                                   hipStream_t);
+template int coarse_solve<float>(const CoarseLayout&, const DevOp<float>&, const float2*,
+                                 const float2*, float2*, int, long, const CoarseSolveWork&,
+                                 hipStream_t);
 
 }  // namespace hz

@@ -22,16 +22,16 @@ __device__ __forceinline__ int region(int a, int M) { return a == 0 ? 0 : (a == 
 template <int P, typename T, typename TX, typename TF, typename TY, int MODE>
 __global__ void __launch_bounds__(256)
 k_stencil(const V2<T>* __restrict__ coef, const V2<T>* __restrict__ wdinv, int M,
-          const V2<TX>* __restrict__ x, const V2<TF>* __restrict__ f, V2<TY>* __restrict__ y,
-          long bstride) {
+          const V2<TX>* __restrict__ x, Addr ax, const V2<TF>* __restrict__ f, Addr af,
+          V2<TY>* __restrict__ y, Addr ay) {
   constexpr int W = 2 * P + 1, W2 = W * W;
   constexpr int LW = P * BX + 2 * P, LH = P * BY + 2 * P;
   __shared__ V2<T> tile[LH][LW];
   const int nmac = (M + P - 1) / P;
-  const long boff = long(blockIdx.z) * bstride;
-  x += boff;
-  y += boff;
-  if (MODE != ST_APPLY) f += boff;
+  const int bz = blockIdx.z;
+  x += ax.at(bz);
+  y += ay.at(bz);
+  if (MODE != ST_APPLY) f += af.at(bz);
   const int I0 = blockIdx.x * BX, J0 = blockIdx.y * BY;
   const int ax0 = P * I0 - P, by0 = P * J0 - P;
   for (int idx = threadIdx.x; idx < LW * LH; idx += 256) {
@@ -115,29 +115,29 @@ k_stencil(const V2<T>* __restrict__ coef, const V2<T>* __restrict__ wdinv, int M
 
 template <int P, typename T, typename TF>
 __global__ void __launch_bounds__(256)
-k_jacobi0(DevOp<T> op, const V2<TF>* __restrict__ f, V2<T>* __restrict__ y, long bstride) {
+k_jacobi0(DevOp<T> op, const V2<TF>* __restrict__ f, Addr af, V2<T>* __restrict__ y, Addr ay) {
   const int M = op.M;
   const long N = long(M) * M;
   const long i = long(blockIdx.x) * 256 + threadIdx.x;
   if (i >= N) return;
-  const long boff = long(blockIdx.y) * bstride;
+  const int bz = blockIdx.y;
   const int b = int(i / M), a = int(i - long(b) * M);
   const int cls = (b % P) * P + (a % P);
   const int reg = region(b, M) * 3 + region(a, M);
-  y[boff + i] = cmul<T>(op.wdinv[cls * 9 + reg], cvt<T>(f[boff + i]));
+  y[ay.at(bz) + i] = cmul<T>(op.wdinv[cls * 9 + reg], cvt<T>(f[af.at(bz) + i]));
 }
 
 // yc(A, B) = sum over fine points (2A + dx, 2B + dy) of RW[cls(A,B)][dy][dx] r(...)
 template <int P, typename T>
 __global__ void __launch_bounds__(256)
 k_restrict(int Mf, int Mc, const T* __restrict__ rw, const V2<T>* __restrict__ r,
-           V2<T>* __restrict__ yc, long fstride, long cstride) {
+           V2<T>* __restrict__ yc, Addr af, Addr ac) {
   constexpr int WR = 4 * P + 1;
   const long Nc = long(Mc) * Mc;
   const long i = long(blockIdx.x) * 256 + threadIdx.x;
   if (i >= Nc) return;
-  r += long(blockIdx.y) * fstride;
-  yc += long(blockIdx.y) * cstride;
+  r += af.at(blockIdx.y);
+  yc += ac.at(blockIdx.y);
   const int B = int(i / Mc), A = int(i - long(B) * Mc);
   const int cls = (B % P) * P + (A % P);
   const T* w = rw + cls * WR * WR;
@@ -165,13 +165,13 @@ k_restrict(int Mf, int Mc, const T* __restrict__ rw, const V2<T>* __restrict__ r
 template <int P, typename T, bool ADD>
 __global__ void __launch_bounds__(256)
 k_prolong(int Mf, int Mc, const T* __restrict__ rw, const V2<T>* __restrict__ xc,
-          V2<T>* __restrict__ yf, long fstride, long cstride) {
+          V2<T>* __restrict__ yf, Addr af, Addr ac) {
   constexpr int WR = 4 * P + 1;
   const long Nf = long(Mf) * Mf;
   const long i = long(blockIdx.x) * 256 + threadIdx.x;
   if (i >= Nf) return;
-  xc += long(blockIdx.y) * cstride;
-  yf += long(blockIdx.y) * fstride;
+  xc += ac.at(blockIdx.y);
+  yf += af.at(blockIdx.y);
   const int b = int(i / Mf), a = int(i - long(b) * Mf);
   V2<T> acc = czero<T>();
   const int A0 = (a - 2 * P + 1) >> 1, B0 = (b - 2 * P + 1) >> 1;   // ceil((a - 2P) / 2)
@@ -247,9 +247,12 @@ k_planewave(int p, int n, double k, double ct, double st, PwParams pw, double2* 
   F[i] = acc;
 }
 
-__global__ void k_d2f(const double2* __restrict__ x, float2* __restrict__ y, long n) {
+__global__ void k_d2f(const double2* __restrict__ x, Addr ax, float2* __restrict__ y, Addr ay,
+                      long n) {
   const long i = long(blockIdx.x) * 256 + threadIdx.x;
-  if (i < n) y[i] = make_float2(float(x[i].x), float(x[i].y));
+  if (i >= n) return;
+  const double2 v = x[ax.at(blockIdx.y) + i];
+  y[ay.at(blockIdx.y) + i] = make_float2(float(v.x), float(v.y));
 }
 __global__ void k_f2d(const float2* __restrict__ x, double2* __restrict__ y, long n) {
   const long i = long(blockIdx.x) * 256 + threadIdx.x;
@@ -257,43 +260,43 @@ __global__ void k_f2d(const float2* __restrict__ x, double2* __restrict__ y, lon
 }
 
 template <int P, typename T, typename TX, typename TF, typename TY>
-void stencil_p(int mode, const DevOp<T>& op, const V2<TX>* x, const V2<TF>* f, V2<TY>* y,
-               int nbatch, long bstride, hipStream_t st) {
+void stencil_p(int mode, const DevOp<T>& op, const V2<TX>* x, Addr xs, const V2<TF>* f, Addr fs,
+               V2<TY>* y, Addr ys, int nbatch, hipStream_t st) {
   const int nmac = (op.M + P - 1) / P;
   dim3 grid((nmac + BX - 1) / BX, (nmac + BY - 1) / BY, nbatch);
   if (mode == ST_APPLY)
-    k_stencil<P, T, TX, TF, TY, ST_APPLY><<<grid, 256, 0, st>>>(op.coef, op.wdinv, op.M, x, f, y, bstride);
+    k_stencil<P, T, TX, TF, TY, ST_APPLY><<<grid, 256, 0, st>>>(op.coef, op.wdinv, op.M, x, xs, f, fs, y, ys);
   else if (mode == ST_RESID)
-    k_stencil<P, T, TX, TF, TY, ST_RESID><<<grid, 256, 0, st>>>(op.coef, op.wdinv, op.M, x, f, y, bstride);
+    k_stencil<P, T, TX, TF, TY, ST_RESID><<<grid, 256, 0, st>>>(op.coef, op.wdinv, op.M, x, xs, f, fs, y, ys);
   else
-    k_stencil<P, T, TX, TF, TY, ST_SMOOTH><<<grid, 256, 0, st>>>(op.coef, op.wdinv, op.M, x, f, y, bstride);
+    k_stencil<P, T, TX, TF, TY, ST_SMOOTH><<<grid, 256, 0, st>>>(op.coef, op.wdinv, op.M, x, xs, f, fs, y, ys);
 }
 
 }  // namespace
 
 template <typename T, typename TX, typename TF, typename TY>
-void launch_stencil(int p, int mode, const DevOp<T>& op, const V2<TX>* x, const V2<TF>* f,
-                    V2<TY>* y, int nbatch, long bstride, hipStream_t st) {
-  if (p == 1) stencil_p<1, T, TX, TF, TY>(mode, op, x, f, y, nbatch, bstride, st);
-  else if (p == 2) stencil_p<2, T, TX, TF, TY>(mode, op, x, f, y, nbatch, bstride, st);
-  else stencil_p<3, T, TX, TF, TY>(mode, op, x, f, y, nbatch, bstride, st);
+void launch_stencil(int p, int mode, const DevOp<T>& op, const V2<TX>* x, Addr xs,
+                    const V2<TF>* f, Addr fs, V2<TY>* y, Addr ys, int nbatch, hipStream_t st) {
+  if (p == 1) stencil_p<1, T, TX, TF, TY>(mode, op, x, xs, f, fs, y, ys, nbatch, st);
+  else if (p == 2) stencil_p<2, T, TX, TF, TY>(mode, op, x, xs, f, fs, y, ys, nbatch, st);
+  else stencil_p<3, T, TX, TF, TY>(mode, op, x, xs, f, fs, y, ys, nbatch, st);
   HZ_HIP(hipGetLastError());
 }
 
 template <typename T, typename TF>
-void launch_jacobi0(int p, const DevOp<T>& op, const V2<TF>* f, V2<T>* y, int nbatch,
-                    long bstride, hipStream_t st) {
+void launch_jacobi0(int p, const DevOp<T>& op, const V2<TF>* f, Addr fs, V2<T>* y, Addr ys,
+                    int nbatch, hipStream_t st) {
   const long N = long(op.M) * op.M;
   dim3 grid(unsigned((N + 255) / 256), nbatch);
-  if (p == 1) k_jacobi0<1, T, TF><<<grid, 256, 0, st>>>(op, f, y, bstride);
-  else if (p == 2) k_jacobi0<2, T, TF><<<grid, 256, 0, st>>>(op, f, y, bstride);
-  else k_jacobi0<3, T, TF><<<grid, 256, 0, st>>>(op, f, y, bstride);
+  if (p == 1) k_jacobi0<1, T, TF><<<grid, 256, 0, st>>>(op, f, fs, y, ys);
+  else if (p == 2) k_jacobi0<2, T, TF><<<grid, 256, 0, st>>>(op, f, fs, y, ys);
+  else k_jacobi0<3, T, TF><<<grid, 256, 0, st>>>(op, f, fs, y, ys);
   HZ_HIP(hipGetLastError());
 }
 
 template <typename T>
 void launch_restrict(int p, int Mf, int Mc, const T* rw, const V2<T>* r, V2<T>* yc, int nbatch,
-                     long fstride, long cstride, hipStream_t st) {
+                     Addr fstride, Addr cstride, hipStream_t st) {
   const long Nc = long(Mc) * Mc;
   dim3 grid(unsigned((Nc + 255) / 256), nbatch);
   if (p == 1) k_restrict<1, T><<<grid, 256, 0, st>>>(Mf, Mc, rw, r, yc, fstride, cstride);
@@ -304,7 +307,7 @@ void launch_restrict(int p, int Mf, int Mc, const T* rw, const V2<T>* r, V2<T>* 
 
 template <typename T>
 void launch_prolong(int p, int Mf, int Mc, const T* rw, const V2<T>* xc, V2<T>* yf, bool add,
-                    int nbatch, long fstride, long cstride, hipStream_t st) {
+                    int nbatch, Addr fstride, Addr cstride, hipStream_t st) {
   const long Nf = long(Mf) * Mf;
   dim3 grid(unsigned((Nf + 255) / 256), nbatch);
 #define HZ_PRO(PP)                                                                             \
@@ -331,7 +334,13 @@ void launch_planewave(int p, int n, double k, double theta, const double* gl_t,
 
 void launch_d2f(const double2* x, float2* y, long n, hipStream_t st) {
   if (n <= 0) return;
-  k_d2f<<<unsigned((n + 255) / 256), 256, 0, st>>>(x, y, n);
+  k_d2f<<<unsigned((n + 255) / 256), 256, 0, st>>>(x, Addr(), y, Addr(), n);
+  HZ_HIP(hipGetLastError());
+}
+void launch_d2f_b(const double2* x, Addr ax, float2* y, Addr ay, long n, int nbatch,
+                  hipStream_t st) {
+  if (n <= 0 || nbatch <= 0) return;
+  k_d2f<<<dim3(unsigned((n + 255) / 256), nbatch), 256, 0, st>>>(x, ax, y, ay, n);
   HZ_HIP(hipGetLastError());
 }
 void launch_f2d(const float2* x, double2* y, long n, hipStream_t st) {
@@ -342,22 +351,22 @@ void launch_f2d(const float2* x, double2* y, long n, hipStream_t st) {
 
 // Instantiations used by the driver.
 template void launch_stencil<double, double, double, double>(int, int, const DevOp<double>&,
-    const double2*, const double2*, double2*, int, long, hipStream_t);
+    const double2*, Addr, const double2*, Addr, double2*, Addr, int, hipStream_t);
 template void launch_stencil<double, float, double, double>(int, int, const DevOp<double>&,
-    const float2*, const double2*, double2*, int, long, hipStream_t);
+    const float2*, Addr, const double2*, Addr, double2*, Addr, int, hipStream_t);
 template void launch_stencil<float, float, float, float>(int, int, const DevOp<float>&,
-    const float2*, const float2*, float2*, int, long, hipStream_t);
-template void launch_jacobi0<double, double>(int, const DevOp<double>&, const double2*, double2*,
-                                             int, long, hipStream_t);
-template void launch_jacobi0<float, float>(int, const DevOp<float>&, const float2*, float2*, int,
-                                           long, hipStream_t);
+    const float2*, Addr, const float2*, Addr, float2*, Addr, int, hipStream_t);
+template void launch_jacobi0<double, double>(int, const DevOp<double>&, const double2*, Addr,
+                                             double2*, Addr, int, hipStream_t);
+template void launch_jacobi0<float, float>(int, const DevOp<float>&, const float2*, Addr, float2*,
+                                           Addr, int, hipStream_t);
 template void launch_restrict<double>(int, int, int, const double*, const double2*, double2*, int,
-                                      long, long, hipStream_t);
+                                      Addr, Addr, hipStream_t);
 template void launch_restrict<float>(int, int, int, const float*, const float2*, float2*, int,
-                                     long, long, hipStream_t);
+                                     Addr, Addr, hipStream_t);
 template void launch_prolong<double>(int, int, int, const double*, const double2*, double2*, bool,
-                                     int, long, long, hipStream_t);
+                                     int, Addr, Addr, hipStream_t);
 template void launch_prolong<float>(int, int, int, const float*, const float2*, float2*, bool, int,
-                                    long, long, hipStream_t);
+                                    Addr, Addr, hipStream_t);
 
 }  // namespace hz

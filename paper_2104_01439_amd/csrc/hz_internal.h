@@ -50,6 +50,17 @@ template <> struct vec2<double> { using type = double2; };
 template <> struct vec2<float> { using type = float2; };
 template <typename T> using V2 = typename vec2<T>::type;
 
+// Element offset of batch element z of a set of vectors: off[z] when a device table is
+// given (gathers from arbitrary places of one allocation), else z * stride.
+struct Addr {
+  long stride = 0;
+  const long* off = nullptr;
+  __host__ __device__ Addr() {}
+  __host__ __device__ Addr(long s) : stride(s) {}
+  __host__ __device__ Addr(long s, const long* o) : stride(s), off(o) {}
+  __device__ __forceinline__ long at(int z) const { return off ? off[z] : long(z) * stride; }
+};
+
 // One level's operator on the device: complex stencil coefficients and the Jacobi
 // multiplier omega / diag(A) per (class, region).
 template <typename T> struct DevOp {
@@ -77,26 +88,28 @@ struct CoarseLayout {
 
 enum StencilMode { ST_APPLY = 0, ST_RESID = 1, ST_SMOOTH = 2 };
 
-// y = A x  |  y = f - A x  |  y = x + wdinv (f - A x)   on one level, lattice M x M.
+// y = A x  |  y = f - A x  |  y = x + wdinv (f - A x)   on one level, lattice M x M;
+// nbatch independent vectors, batch element z at x + ax.at(z), f + af.at(z), y + ay.at(z).
 template <typename T, typename TX, typename TF, typename TY>
-void launch_stencil(int p, int mode, const DevOp<T>& op, const V2<TX>* x, const V2<TF>* f,
-                    V2<TY>* y, int nbatch, long bstride, hipStream_t st);
+void launch_stencil(int p, int mode, const DevOp<T>& op, const V2<TX>* x, Addr ax,
+                    const V2<TF>* f, Addr af, V2<TY>* y, Addr ay, int nbatch, hipStream_t st);
 // y = wdinv * f (the first sweep from a zero guess).
 template <typename T, typename TF>
-void launch_jacobi0(int p, const DevOp<T>& op, const V2<TF>* f, V2<T>* y, int nbatch,
-                    long bstride, hipStream_t st);
+void launch_jacobi0(int p, const DevOp<T>& op, const V2<TF>* f, Addr af, V2<T>* y, Addr ay,
+                    int nbatch, hipStream_t st);
 // yc = P^T r (fine -> coarse), yf (+)= P xc (coarse -> fine).
 template <typename T>
 void launch_restrict(int p, int Mf, int Mc, const T* rw, const V2<T>* r, V2<T>* yc, int nbatch,
-                     long fstride, long cstride, hipStream_t st);
+                     Addr af, Addr ac, hipStream_t st);
 template <typename T>
 void launch_prolong(int p, int Mf, int Mc, const T* rw, const V2<T>* xc, V2<T>* yf, bool add,
-                    int nbatch, long fstride, long cstride, hipStream_t st);
+                    int nbatch, Addr af, Addr ac, hipStream_t st);
 // Plane-wave impedance load vector.
 void launch_planewave(int p, int n, double k, double theta, const double* gl_t,
                       const double* gl_w, const double* lag, double2* F, hipStream_t st);
 // Conversions.
 void launch_d2f(const double2* x, float2* y, long n, hipStream_t st);
+void launch_d2f_b(const double2* x, Addr ax, float2* y, Addr ay, long n, int nbatch, hipStream_t st);
 void launch_f2d(const float2* x, double2* y, long n, hipStream_t st);
 
 // Coarse factorisation: assembles and inverts every block in sequence. Returns HZ_OK or
@@ -117,24 +130,46 @@ struct CoarseSolveWork {
   int* err = nullptr;        // set to 1 if a wait for another workgroup's data timed out
   bool persistent = true;
 };
+// Returns the number of solve launches (one reads the factor once for up to 4 right-hand
+// sides when their staging fits in LDS).
 template <typename T>
-void coarse_solve(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b,
-                  V2<T>* y, int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st);
+int coarse_solve(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b,
+                 V2<T>* y, int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st);
 void launch_factor_to_f32(const double2* S, float2* Sf, size_t n, hipStream_t st);
 
-// Krylov kernels. Vectors of length N; V is row-major [nv][ldv].
+// Krylov kernels. Vectors of length N; a basis V is row-major [nv][ldv].
+// Batched forms run nbatch independent instances: instance z uses V + av.at(z), w + aw.at(z),
+// its partial sums at partial + z nblk 64, its small vectors (h, y) at z hs, and its own
+// vector count nvt[z] when the table is given (0 = nothing to do), else nv.
 int mdot_blocks(long N);
 template <typename TV>
 void launch_mdot(const V2<TV>* V, long ldv, int nv, const double2* w, long N, double2* partial,
                  int nblk, hipStream_t st);
+void launch_mdot_b(const double2* V, Addr av, long ldv, int nv, const int* nvt, const double2* w,
+                   Addr aw, long N, double2* partial, int nblk, int nbatch, hipStream_t st);
 void launch_reduce(const double2* partial, int nblk, int nv, double2* out, hipStream_t st);
+void launch_reduce_b(const double2* partial, int nblk, int nv, const int* nvt, double2* out,
+                     long hs, int nbatch, hipStream_t st);
 // w -= V h (h on device, nv entries); optionally accumulates |w|^2 partials (nv index 0).
 void launch_maxpy(const double2* V, long ldv, int nv, const double2* h, double2* w, long N,
                   double2* norm_partial, int nblk, hipStream_t st);
+void launch_maxpy_b(const double2* V, Addr av, long ldv, int nv, const int* nvt, const double2* h,
+                    long hs, double2* w, Addr aw, long N, double2* norm_partial, int nblk,
+                    int nbatch, hipStream_t st);
+// v = s[z] w (per-instance factor on the device)
+void launch_scale_b(const double2* w, Addr aw, const double* s_dev, double2* v, Addr av, long N,
+                    int nbatch, hipStream_t st);
+// u += Z y (y on the device, nz entries)
+template <typename TZ>
+void launch_update_b(const V2<TZ>* Z, Addr az, long ldz, int nz, const int* nzt, const double2* y,
+                     long ys, double2* u, Addr au, long N, int nbatch, hipStream_t st);
+void launch_copy_b(const double2* x, Addr ax, double2* y, Addr ay, long N, int nbatch,
+                   hipStream_t st);
 void launch_scale_dev(const double2* w, const double* s_dev, double2* v, long N, hipStream_t st);
 void launch_scale(const double2* w, double s, double2* v, long N, hipStream_t st);
 void launch_fill_zero(double2* y, long N, hipStream_t st);
 void launch_fill_zero(float2* y, long N, hipStream_t st);
+void launch_fill_zero_b(double2* y, Addr ay, long N, int nbatch, hipStream_t st);
 template <typename TZ>
 void launch_update(const V2<TZ>* Z, long ldz, int nz, const double2* y, double2* u, long N,
                    hipStream_t st);

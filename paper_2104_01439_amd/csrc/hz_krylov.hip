@@ -16,13 +16,15 @@ constexpr int CHUNK = 256 * EPT;       // elements per workgroup
 
 template <typename TV>
 __global__ void __launch_bounds__(256)
-k_mdot(const V2<TV>* __restrict__ V, long ldv, int nv, const double2* __restrict__ w, long N,
-       double2* __restrict__ partial, int nblk, long vstride, long wstride) {
+k_mdot(const V2<TV>* __restrict__ V, Addr av, long ldv, int nv, const int* __restrict__ nvt,
+       const double2* __restrict__ w, Addr aw, long N, double2* __restrict__ partial, int nblk) {
   __shared__ double red[2][64][4];
-  const long bo = blockIdx.y;
-  V += bo * vstride;
-  w += bo * wstride;
-  partial += bo * long(nblk) * 64;
+  const int bz = blockIdx.y;
+  if (nvt) nv = nvt[bz];
+  if (nv <= 0) return;
+  V += av.at(bz);
+  w += aw.at(bz);
+  partial += long(bz) * nblk * 64;
   const long base = long(blockIdx.x) * CHUNK + threadIdx.x;
   double2 wv[EPT];
 #pragma unroll
@@ -55,12 +57,13 @@ k_mdot(const V2<TV>* __restrict__ V, long ldv, int nv, const double2* __restrict
 
 // out[i] = sum_b partial[b][i] in a fixed order; one workgroup per i.
 __global__ void __launch_bounds__(256)
-k_reduce(const double2* __restrict__ partial, int nblk, int nv, double2* __restrict__ out,
-         long ostride) {
+k_reduce(const double2* __restrict__ partial, int nblk, const int* __restrict__ nvt,
+         double2* __restrict__ out, long ostride) {
   __shared__ double sx[256], sy[256];
   const int i = blockIdx.x;
-  const long bo = blockIdx.y;
-  partial += bo * long(nblk) * 64;
+  const int bz = blockIdx.y;
+  if (nvt && i >= nvt[bz]) return;
+  partial += long(bz) * nblk * 64;
   double ax = 0, ay = 0;
   for (int b = threadIdx.x; b < nblk; b += 256) {
     const double2 v = partial[long(b) * 64 + i];
@@ -77,21 +80,23 @@ k_reduce(const double2* __restrict__ partial, int nblk, int nv, double2* __restr
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[bo * ostride + i] = make_double2(sx[0], sy[0]);
+  if (threadIdx.x == 0) out[bz * ostride + i] = make_double2(sx[0], sy[0]);
 }
 
 // w -= sum_i V[i] h[i]; optionally partial[blk][0] = sum |w_new|^2 over the chunk.
 template <bool NORM>
 __global__ void __launch_bounds__(256)
-k_maxpy(const double2* __restrict__ V, long ldv, int nv, const double2* __restrict__ h,
-        double2* __restrict__ w, long N, double2* __restrict__ partial, int nblk, long vstride,
-        long wstride, long hstride) {
+k_maxpy(const double2* __restrict__ V, Addr av, long ldv, int nv, const int* __restrict__ nvt,
+        const double2* __restrict__ h, long hstride, double2* __restrict__ w, Addr aw, long N,
+        double2* __restrict__ partial, int nblk) {
   __shared__ double2 hs[64];
   __shared__ double red[4];
-  const long bo = blockIdx.y;
-  V += bo * vstride;
-  w += bo * wstride;
-  h += bo * hstride;
+  const int bz = blockIdx.y;
+  if (nvt) nv = nvt[bz];
+  if (nv <= 0) return;
+  V += av.at(bz);
+  w += aw.at(bz);
+  h += bz * hstride;
   if (threadIdx.x < nv) hs[threadIdx.x] = h[threadIdx.x];
   __syncthreads();
   const long base = long(blockIdx.x) * CHUNK + threadIdx.x;
@@ -115,30 +120,32 @@ k_maxpy(const double2* __restrict__ V, long ldv, int nv, const double2* __restri
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
     __syncthreads();
     if (threadIdx.x == 0)
-      partial[bo * long(nblk) * 64 + long(blockIdx.x) * 64] =
+      partial[long(bz) * nblk * 64 + long(blockIdx.x) * 64] =
           make_double2(((red[0] + red[1]) + red[2]) + red[3], 0.0);
   }
 }
 
-__global__ void k_scale(const double2* __restrict__ w, const double* __restrict__ s,
-                        double2* __restrict__ v, long N, long wstride, long vstride) {
+__global__ void k_scale(const double2* __restrict__ w, Addr aw, const double* __restrict__ s,
+                        double2* __restrict__ v, Addr av, long N) {
   const long i = long(blockIdx.x) * 256 + threadIdx.x;
-  const long bo = blockIdx.y;
+  const int bz = blockIdx.y;
   if (i >= N) return;
-  const double a = s[bo];
-  const double2 x = w[bo * wstride + i];
-  v[bo * vstride + i] = make_double2(a * x.x, a * x.y);
+  const double a = s[bz];
+  const double2 x = w[aw.at(bz) + i];
+  v[av.at(bz) + i] = make_double2(a * x.x, a * x.y);
 }
 
 template <typename TZ>
 __global__ void __launch_bounds__(256)
-k_update(const V2<TZ>* __restrict__ Z, long ldz, int nz, const double2* __restrict__ y,
-         double2* __restrict__ u, long N, long zstride, long ystride, long ustride) {
+k_update(const V2<TZ>* __restrict__ Z, Addr az, long ldz, int nz, const int* __restrict__ nzt,
+         const double2* __restrict__ y, long ystride, double2* __restrict__ u, Addr au, long N) {
   __shared__ double2 ys[64];
-  const long bo = blockIdx.y;
-  Z += bo * zstride;
-  y += bo * ystride;
-  u += bo * ustride;
+  const int bz = blockIdx.y;
+  if (nzt) nz = nzt[bz];
+  if (nz <= 0) return;
+  Z += az.at(bz);
+  y += bz * ystride;
+  u += au.at(bz);
   if (threadIdx.x < nz) ys[threadIdx.x] = y[threadIdx.x];
   __syncthreads();
   const long k = long(blockIdx.x) * 256 + threadIdx.x;
@@ -156,14 +163,15 @@ __global__ void k_scale_arg(const double2* __restrict__ w, double a, double2* __
   v[i] = make_double2(a * x.x, a * x.y);
 }
 
-template <typename T> __global__ void k_zero(V2<T>* __restrict__ y, long N) {
+template <typename T> __global__ void k_zero(V2<T>* __restrict__ y, Addr ay, long N) {
   const long i = long(blockIdx.x) * 256 + threadIdx.x;
-  if (i < N) y[i] = czero<T>();
+  if (i < N) y[ay.at(blockIdx.y) + i] = czero<T>();
 }
 
-__global__ void k_copy(const double2* __restrict__ x, double2* __restrict__ y, long N) {
+__global__ void k_copy(const double2* __restrict__ x, Addr ax, double2* __restrict__ y, Addr ay,
+                       long N) {
   const long i = long(blockIdx.x) * 256 + threadIdx.x;
-  if (i < N) y[i] = x[i];
+  if (i < N) y[ay.at(blockIdx.y) + i] = x[ax.at(blockIdx.y) + i];
 }
 
 }  // namespace
@@ -173,7 +181,7 @@ int mdot_blocks(long N) { return int((N + CHUNK - 1) / CHUNK); }
 template <typename TV>
 void launch_mdot(const V2<TV>* V, long ldv, int nv, const double2* w, long N, double2* partial,
                  int nblk, hipStream_t st) {
-  k_mdot<TV><<<dim3(nblk, 1), 256, 0, st>>>(V, ldv, nv, w, N, partial, nblk, 0, 0);
+  k_mdot<TV><<<dim3(nblk, 1), 256, 0, st>>>(V, Addr(), ldv, nv, nullptr, w, Addr(), N, partial, nblk);
   HZ_HIP(hipGetLastError());
 }
 template void launch_mdot<double>(const double2*, long, int, const double2*, long, double2*, int,
@@ -181,39 +189,86 @@ template void launch_mdot<double>(const double2*, long, int, const double2*, lon
 template void launch_mdot<float>(const float2*, long, int, const double2*, long, double2*, int,
                                  hipStream_t);
 
+void launch_mdot_b(const double2* V, Addr av, long ldv, int nv, const int* nvt, const double2* w,
+                   Addr aw, long N, double2* partial, int nblk, int nbatch, hipStream_t st) {
+  if (nbatch <= 0) return;
+  k_mdot<double><<<dim3(nblk, nbatch), 256, 0, st>>>(V, av, ldv, nv, nvt, w, aw, N, partial, nblk);
+  HZ_HIP(hipGetLastError());
+}
+
 void launch_reduce(const double2* partial, int nblk, int nv, double2* out, hipStream_t st) {
-  k_reduce<<<dim3(nv, 1), 256, 0, st>>>(partial, nblk, nv, out, 0);
+  k_reduce<<<dim3(nv, 1), 256, 0, st>>>(partial, nblk, nullptr, out, 0);
+  HZ_HIP(hipGetLastError());
+}
+
+void launch_reduce_b(const double2* partial, int nblk, int nv, const int* nvt, double2* out,
+                     long hs, int nbatch, hipStream_t st) {
+  if (nbatch <= 0 || nv <= 0) return;
+  k_reduce<<<dim3(nv, nbatch), 256, 0, st>>>(partial, nblk, nvt, out, hs);
   HZ_HIP(hipGetLastError());
 }
 
 void launch_maxpy(const double2* V, long ldv, int nv, const double2* h, double2* w, long N,
                   double2* norm_partial, int nblk, hipStream_t st) {
+  launch_maxpy_b(V, Addr(), ldv, nv, nullptr, h, 0, w, Addr(), N, norm_partial, nblk, 1, st);
+}
+
+void launch_maxpy_b(const double2* V, Addr av, long ldv, int nv, const int* nvt, const double2* h,
+                    long hs, double2* w, Addr aw, long N, double2* norm_partial, int nblk,
+                    int nbatch, hipStream_t st) {
+  if (nbatch <= 0) return;
   if (norm_partial)
-    k_maxpy<true><<<dim3(nblk, 1), 256, 0, st>>>(V, ldv, nv, h, w, N, norm_partial, nblk, 0, 0, 0);
+    k_maxpy<true><<<dim3(nblk, nbatch), 256, 0, st>>>(V, av, ldv, nv, nvt, h, hs, w, aw, N,
+                                                       norm_partial, nblk);
   else
-    k_maxpy<false><<<dim3(nblk, 1), 256, 0, st>>>(V, ldv, nv, h, w, N, nullptr, nblk, 0, 0, 0);
+    k_maxpy<false><<<dim3(nblk, nbatch), 256, 0, st>>>(V, av, ldv, nv, nvt, h, hs, w, aw, N,
+                                                        nullptr, nblk);
   HZ_HIP(hipGetLastError());
 }
 
 template <typename TZ>
 void launch_update(const V2<TZ>* Z, long ldz, int nz, const double2* y, double2* u, long N,
                    hipStream_t st) {
-  k_update<TZ><<<dim3(unsigned((N + 255) / 256), 1), 256, 0, st>>>(Z, ldz, nz, y, u, N, 0, 0, 0);
-  HZ_HIP(hipGetLastError());
+  launch_update_b<TZ>(Z, Addr(), ldz, nz, nullptr, y, 0, u, Addr(), N, 1, st);
 }
 template void launch_update<double>(const double2*, long, int, const double2*, double2*, long,
                                     hipStream_t);
 template void launch_update<float>(const float2*, long, int, const double2*, double2*, long,
                                    hipStream_t);
 
+template <typename TZ>
+void launch_update_b(const V2<TZ>* Z, Addr az, long ldz, int nz, const int* nzt, const double2* y,
+                     long ys, double2* u, Addr au, long N, int nbatch, hipStream_t st) {
+  if (nbatch <= 0) return;
+  k_update<TZ><<<dim3(unsigned((N + 255) / 256), nbatch), 256, 0, st>>>(Z, az, ldz, nz, nzt, y, ys,
+                                                                        u, au, N);
+  HZ_HIP(hipGetLastError());
+}
+template void launch_update_b<double>(const double2*, Addr, long, int, const int*, const double2*,
+                                      long, double2*, Addr, long, int, hipStream_t);
+template void launch_update_b<float>(const float2*, Addr, long, int, const int*, const double2*,
+                                     long, double2*, Addr, long, int, hipStream_t);
+
 void launch_axpby_copy(const double2* x, double2* y, long N, hipStream_t st) {
-  k_copy<<<unsigned((N + 255) / 256), 256, 0, st>>>(x, y, N);
+  launch_copy_b(x, Addr(), y, Addr(), N, 1, st);
+}
+
+void launch_copy_b(const double2* x, Addr ax, double2* y, Addr ay, long N, int nbatch,
+                   hipStream_t st) {
+  if (N <= 0 || nbatch <= 0) return;
+  k_copy<<<dim3(unsigned((N + 255) / 256), nbatch), 256, 0, st>>>(x, ax, y, ay, N);
   HZ_HIP(hipGetLastError());
 }
 
 // Scaling factor lives on the device (s_dev[0]) so that no host round trip is needed.
 void launch_scale_dev(const double2* w, const double* s_dev, double2* v, long N, hipStream_t st) {
-  k_scale<<<dim3(unsigned((N + 255) / 256), 1), 256, 0, st>>>(w, s_dev, v, N, 0, 0);
+  launch_scale_b(w, Addr(), s_dev, v, Addr(), N, 1, st);
+}
+
+void launch_scale_b(const double2* w, Addr aw, const double* s_dev, double2* v, Addr av, long N,
+                    int nbatch, hipStream_t st) {
+  if (nbatch <= 0) return;
+  k_scale<<<dim3(unsigned((N + 255) / 256), nbatch), 256, 0, st>>>(w, aw, s_dev, v, av, N);
   HZ_HIP(hipGetLastError());
 }
 
@@ -224,12 +279,17 @@ void launch_scale(const double2* w, double s, double2* v, long N, hipStream_t st
 
 void launch_fill_zero(double2* y, long N, hipStream_t st) {
   if (N <= 0) return;
-  k_zero<double><<<unsigned((N + 255) / 256), 256, 0, st>>>(y, N);
+  k_zero<double><<<unsigned((N + 255) / 256), 256, 0, st>>>(y, Addr(), N);
   HZ_HIP(hipGetLastError());
 }
 void launch_fill_zero(float2* y, long N, hipStream_t st) {
   if (N <= 0) return;
-  k_zero<float><<<unsigned((N + 255) / 256), 256, 0, st>>>(y, N);
+  k_zero<float><<<unsigned((N + 255) / 256), 256, 0, st>>>(y, Addr(), N);
+  HZ_HIP(hipGetLastError());
+}
+void launch_fill_zero_b(double2* y, Addr ay, long N, int nbatch, hipStream_t st) {
+  if (N <= 0 || nbatch <= 0) return;
+  k_zero<double><<<dim3(unsigned((N + 255) / 256), nbatch), 256, 0, st>>>(y, ay, N);
   HZ_HIP(hipGetLastError());
 }
 

@@ -69,6 +69,8 @@ _SIGS = {
     "hz_solve_batched": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_P),
                                         ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(Options),
                                         ctypes.POINTER(Result), _P]),
+    "hz_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                                   ctypes.c_int, ctypes.POINTER(Options)]),
     "hz_problem_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats), ctypes.c_int]),
     "hz_destroy_problem": (None, [_P]),
     "hz_last_error": (ctypes.c_char_p, []),
@@ -120,6 +122,11 @@ def options(nu=2, omega=0.6, restart=50, maxit=5000, tol=1e-8, prec="fp64", timi
 def footprint_estimate(k, h, p, **kw):
     o = options(**kw)
     return int(lib().hz_footprint_estimate(k, h, p, ctypes.byref(o)))
+
+
+def batch_workspace_bytes(h, p, nprob, nrhs_per_prob, **kw):
+    o = options(**kw)
+    return int(lib().hz_batch_workspace_bytes(h, p, nprob, nrhs_per_prob, ctypes.byref(o)))
 
 
 def sizes(n, p):

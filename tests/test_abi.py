@@ -58,6 +58,18 @@ def test_footprint_model(hz):
     assert hz.footprint_estimate(50.0, 1 / 64, 1) < hz.footprint_estimate(50.0, 1 / 64, 3)
 
 
+def test_batch_workspace_model(hz):
+    assert hz.batch_workspace_bytes(1 / 63, 1, 2, 4) == 0
+    assert hz.batch_workspace_bytes(1 / 64, 1, 0, 4) == 0
+    # P2 n=512: per solve V (51) + Z (50) + r, w, F, u, FP64
+    N = 1025 ** 2
+    b = hz.batch_workspace_bytes(1 / 512, 2, 8, 4, prec="fp64")
+    per = (51 + 50 + 4) * N * 16
+    assert 32 * per < b < 32 * per + 4 * 5 * N * 16 + 1e8
+    assert hz.batch_workspace_bytes(1 / 512, 2, 8, 4, prec="mixed") < b
+    assert hz.batch_workspace_bytes(1 / 512, 2, 8, 4) > hz.batch_workspace_bytes(1 / 512, 2, 4, 4)
+
+
 @pytest.mark.parametrize("k,h,p,s", [
     (10.0, 1 / 63, 1, 1 + 0.5j),      # odd n
     (10.0, 1 / 64, 4, 1 + 0.5j),      # bad order

@@ -222,17 +222,77 @@ def test_solve_edge_cases(hz, torch):
     assert torch.equal(u1, u2) and r1["hist"] == r2["hist"]
 
 
-def test_batched_equals_single(hz, torch):
-    k, n, p = 20.0, 32, 2
-    betas = [0.3, 0.9]
-    probs = [hz.Problem(k, 1.0 / n, p, 1 + 1j * b) for b in betas]
-    ths = [0.2, 1.7, 4.0]
-    Fs = [probs[i].planewave_rhs(t) for i in range(2) for t in ths]
-    us, rs = hz.solve_batched(probs, Fs, 3, tol=1e-10)
-    for q in range(6):
-        u1, r1 = probs[q // 3].solve(Fs[q], tol=1e-10)
-        assert torch.equal(u1, us[q])
+# (k, n, p, betas, nrhs, prec, restart): right-hand side groups of 3 (one coarse group), 5
+# (a group of 4 and a single) and 2; shifts far apart so that solves finish at different
+# rounds; short restarts so that solves restart out of phase; P3 n=176 has a coarse block
+# too wide for 4 right-hand sides in LDS (groups of 2 in FP64).
+BATCH_CASES = [
+    (20.0, 32, 2, [0.3, 0.9], 3, "fp64", 50),
+    (12.0, 16, 1, [0.1, 1.4], 5, "fp64", 7),
+    (30.0, 48, 3, [0.5], 2, "mixed", 50),
+    (25.0, 40, 1, [0.2, 0.6, 1.2], 4, "mixed", 9),
+    (60.0, 176, 3, [0.5], 3, "fp64", 50),
+]
+
+
+@pytest.mark.parametrize("k,n,p,betas,nrhs,prec,restart", BATCH_CASES)
+def test_batched_equals_single(hz, torch, k, n, p, betas, nrhs, prec, restart):
+    """Lockstep solves give bitwise the single-solve results (iterations, residuals, u)."""
+    _log(f"[batched] k={k} n={n} p={p} betas={betas} nrhs={nrhs} {prec} m={restart}")
+    probs = [hz.Problem(k, 1.0 / n, p, 1 + 1j * b, prec=prec, restart=restart) for b in betas]
+    ths = [0.2 + 1.3 * r for r in range(nrhs)]
+    Fs = [probs[i].planewave_rhs(t) for i in range(len(betas)) for t in ths]
+    tol = 1e-6 if n > 100 else 1e-10
+    us, rs = hz.solve_batched(probs, Fs, nrhs, tol=tol)
+    its = set()
+    for q in range(len(Fs)):
+        u1, r1 = probs[q // nrhs].solve(Fs[q], tol=tol, history=False)
         assert r1["iterations"] == rs[q]["iterations"]
+        assert r1["rel_res_true"] == rs[q]["rel_res_true"]
+        assert torch.equal(u1, us[q])
+        assert rs[q]["converged"] == 1
+        its.add(rs[q]["iterations"])
+    _log(f"  iterations {sorted(its)}")
+
+
+def test_batched_against_oracle(hz, torch):
+    """Lockstep FP64 solves of two shifts x two angles against the oracle."""
+    k, n, p = 18.0, 24, 2
+    betas, ths = [0.4, 1.0], [0.3, 2.5]
+    probs = [hz.Problem(k, 1.0 / n, p, 1 + 1j * b) for b in betas]
+    Fs = [probs[i].planewave_rhs(t) for i in range(2) for t in ths]
+    us, rs = hz.solve_batched(probs, Fs, 2, tol=1e-10)
+    for q in range(4):
+        b, t = betas[q // 2], ths[q % 2]
+        op = OProblem(k, n, p, 1 + 1j * b, nu=2, omega=0.6)
+        ro = op.solve(op.planewave_rhs(t), tol=1e-10, m=50)
+        torch.cuda.synchronize()
+        assert abs(rs[q]["iterations"] - ro["iterations"]) <= 1
+        assert rel(us[q].cpu().numpy(), ro["u"]) <= 1e-8
+
+
+def test_batched_edge_cases(hz, torch):
+    probs = [hz.Problem(10.0, 1 / 16, 1, 1 + 0.5j), hz.Problem(10.0, 1 / 16, 1, 1 + 0.7j)]
+    F = probs[0].planewave_rhs(0.5)
+    Z = torch.zeros_like(F)
+    us, rs = hz.solve_batched(probs, [F, Z, Z, F], 2, tol=1e-10)
+    assert rs[1]["iterations"] == 0 and rs[2]["iterations"] == 0
+    assert torch.count_nonzero(us[1]).item() == 0 and torch.count_nonzero(us[2]).item() == 0
+    assert rs[0]["converged"] == 1 and rs[3]["converged"] == 1
+    # a problem listed twice, mismatched sizes, non-finite input
+    with pytest.raises(hz.HZError):
+        hz.solve_batched([probs[0], probs[0]], [F, F], 1)
+    other = hz.Problem(10.0, 1 / 32, 1, 1 + 0.5j)
+    with pytest.raises(hz.HZError):
+        hz.solve_batched([probs[0], other], [F, other.planewave_rhs(0.5)], 1)
+    Fn = F.clone()
+    Fn[3] = complex(float("inf"), 0)
+    with pytest.raises(hz.HZError) as ei:
+        hz.solve_batched(probs, [F, Fn], 1)
+    assert ei.value.status == hz.HZ_EINVAL
+    # maxit stops every solve
+    us, rs = hz.solve_batched(probs, [F, F], 1, tol=1e-30, maxit=4)
+    assert all(r["iterations"] == 4 and r["converged"] == 0 for r in rs)
 
 
 @pytest.mark.parametrize("c", [CASES[2], CASES[4], CASES[6]])
