@@ -16,11 +16,14 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-from paper_2104_01439_amd.roofline import HBM_PEAK_GBS, coarse_solve_bytes  # noqa: E402
+from paper_2104_01439_amd.roofline import (HBM_PEAK_GBS, coarse_solve_bytes,  # noqa: E402
+                                           factor_bytes)
 
 
 def log(msg):
@@ -153,6 +156,89 @@ def run_gpu(cfg, steps, warmup, prec):
                 coarse_launches=launches, factor_ms=factor_ms)
 
 
+def near_optimal_beta(betas, its, rhos):
+    """argmin over beta of the mean iteration count over the right-hand sides; ties broken by
+    the smaller mean convergence factor, then by the smaller beta."""
+    keys = [(float(np.mean(its[i])), float(np.mean(rhos[i])), betas[i]) for i in range(len(betas))]
+    return min(keys)[2]
+
+
+def run_sweep(cfg, steps, warmup, prec):
+    """The shift sweep: every beta with every incidence angle, the right-hand sides of one
+    shift and several shifts in one lockstep batch; groups of shifts sized to HBM."""
+    import torch
+    from paper_2104_01439_amd import hz, inputs
+
+    torch.cuda.set_device(0)
+    k, n, p, tol = cfg["k"], cfg["n"], cfg["p"], cfg["tol"]
+    betas, thetas = inputs.sweep_betas(), inputs.sweep_thetas()
+    nr = len(thetas)
+    free, _ = torch.cuda.mem_get_info()
+    item = 8 if prec == "mixed" else 16
+    per_shift = factor_bytes(n, p, item) + hz.batch_workspace_bytes(1.0 / n, p, 1, nr, prec=prec,
+                                                                    restart=cfg["restart"])
+    gmax = max(1, int(0.85 * (free - 2 * factor_bytes(n, p)) // per_shift))
+    ngroups = -(-len(betas) // gmax)
+    gsize = -(-len(betas) // ngroups)
+    log(f"sweep: {len(betas)} shifts x {nr} angles, groups of {gsize} shifts "
+        f"({per_shift / 1e9:.2f} GB per shift, {free / 1e9:.0f} GB free)")
+
+    def sweep(record):
+        its = [[0] * nr for _ in betas]
+        rhos = [[0.0] * nr for _ in betas]
+        stats, setup_s, conv = [], 0.0, True
+        Fs = None
+        for g0 in range(0, len(betas), gsize):
+            gb = betas[g0:g0 + gsize]
+            t = time.perf_counter()
+            probs = [hz.Problem(k, 1.0 / n, p, 1 + 1j * b, nu=cfg["nu"], omega=cfg["omega"],
+                                restart=cfg["restart"], tol=tol, prec=prec, timing=record)
+                     for b in gb]
+            setup_s += time.perf_counter() - t
+            if Fs is None:
+                Fs = [probs[0].planewave_rhs(th) for th in thetas]   # independent of the shift
+            t = time.perf_counter()
+            us, rs = hz.solve_batched(probs, [F for _ in gb for F in Fs], nr, tol=tol)
+            gi = [x["iterations"] for x in rs]
+            log(f"  shifts beta {gb[0]:.3f}..{gb[-1]:.3f}: iterations {min(gi)}..{max(gi)}, "
+                f"batched solve {time.perf_counter() - t:.2f}s")
+            for i in range(len(gb)):
+                for r in range(nr):
+                    x = rs[i * nr + r]
+                    its[g0 + i][r] = x["iterations"]
+                    rhos[g0 + i][r] = x["rel_res_true"] ** (1.0 / max(x["iterations"], 1))
+                    conv = conv and bool(x["converged"])
+            if record:
+                stats += [pr.stats() for pr in probs]
+            for pr in probs:
+                pr.close()
+            del us
+        return its, rhos, stats, setup_s, conv
+
+    for i in range(warmup):
+        sweep(False)
+        log(f"warmup {i} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        its, rhos, stats, setup_s, conv = sweep(True)
+        log(f"sweep {i}: mean iterations {np.mean(its):.1f}, setup {setup_s:.2f}s, "
+            f"converged={conv}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    bstar = near_optimal_beta(betas, its, rhos)
+    launches = sum(x["coarse_solves"] for x in stats)
+    cs_ms = sum(x["coarse_solve_ms"] for x in stats) / max(launches, 1)
+    vcyc = sum(x["vcycles"] for x in stats)
+    nrhs_per_launch = vcyc / max(launches, 1)
+    return dict(seconds=dt, solves=steps * len(betas) * nr, its=its, bstar=bstar,
+                sigma=2 + math.log(bstar) / math.log(k), group=gsize, setup_s=setup_s,
+                coarse_ms=cs_ms, coarse_launches=launches, nrhs_per_launch=nrhs_per_launch,
+                coarse_bytes=coarse_solve_bytes(n, p, item, round(nrhs_per_launch)),
+                factor_ms=sum(x["factor_ms"] for x in stats) / max(len(stats), 1),
+                betas=betas, thetas=thetas, converged=conv)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +254,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     from paper_2104_01439_amd import inputs
+    if a.workload == inputs.CFG_SWEEP["name"]:
+        return main_sweep(a, inputs.CFG_SWEEP)
     cfgs = {c["name"]: c for c in (inputs.CFG_SMALL, inputs.CFG_P1_LARGE, inputs.CFG_MIXED)}
     cfg = cfgs[a.workload]
     g = run_gpu(cfg, a.steps, a.warmup, a.prec)
@@ -204,6 +292,49 @@ def main():
         "setup_factor_ms": g["factor_ms"],
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def main_sweep(a, cfg):
+    g = run_sweep(cfg, a.steps, a.warmup, a.prec)
+    cs_gbs = g["coarse_bytes"] / (g["coarse_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "FGMRES solves/s",
+        "value": g["solves"] / g["seconds"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * g["seconds"] / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if a.prec == "fp64" else "f32-precond/f64-outer",
+        "data": "synthetic plane-wave impedance data",
+        "config": {"workload": cfg["name"], "k": cfg["k"], "n": cfg["n"], "p": cfg["p"],
+                   "shifts": len(g["betas"]), "angles": len(g["thetas"]), "tol": cfg["tol"],
+                   "restart": cfg["restart"], "nu": cfg["nu"], "omega": cfg["omega"],
+                   "precision": a.prec, "shifts_per_batch": g["group"]},
+        "roofline": {"kernel": "coarse block triangular solve, multi-RHS (k_csolve)",
+                     "bound": "hbm", "achieved": cs_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": cs_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": g["coarse_bytes"], "avg_launch_ms": g["coarse_ms"],
+                     "launches": g["coarse_launches"],
+                     "rhs_per_launch": g["nrhs_per_launch"]},
+        "setup_factor_ms": g["factor_ms"],
+        "sweep": {"beta_star": g["bstar"], "sigma_star": g["sigma"],
+                  "mean_iterations_per_beta": [float(np.mean(x)) for x in g["its"]],
+                  "betas": g["betas"], "converged": g["converged"],
+                  "setup_s_per_sweep": g["setup_s"]},
+        "cpu_baseline": None,
+    }
+    if not a.no_cpu:
+        log("cpu baseline: timing the oracle on a bounded sample ...")
+        its = float(np.mean(g["its"]))
+        one = dict(cfg, s=1 + 1j * g["bstar"], theta=g["thetas"][0])
+        cpu = cpu_baseline(one, int(round(its)))
+        cpu["sample"] += f"; one solve at beta*={g['bstar']:.3f} with the sweep's mean iterations"
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -433,153 +433,209 @@ __device__ __forceinline__ V2<T> coupling(int c, int j, int jn, int nc, int Mc,
   return acc;
 }
 
-// Polls block jn of src (stride sstride per right-hand side) until no value is the
-// sentinel, staging it into yv[h * nmax + .]; executed by the 128 exchange threads.
-template <int P, typename T, int ENT>
+// Polls lattice block jn of src (right-hand side h at src + h * sstride) until no value is
+// the sentinel, staging it into yv[h * nmax + .]; executed by the 128 exchange threads. Entry
+// (h, q) of a thread is column c0 + xl + 128 q of right-hand side h: every pending load of a
+// slice of 128 * EH columns, for all right-hand sides, is in flight at once.
+template <int P, typename T, int NR, int EH>
 __device__ __forceinline__ void gather_block(const V2<T>* src, long sstride, int jn, int nc,
                                              int Mc, int nrhs, int nmax, V2<T>* yv, int xl,
                                              int* err) {
   const int nn = (jn < nc ? P : 1) * Mc;
   const long d0 = long(P) * jn * Mc;
-  for (int h = 0; h < nrhs; ++h) {
-    const V2<T>* sh = src + h * sstride + d0;
-    V2<T>* yh = yv + h * nmax;
-    for (int i0 = 0; i0 < nn; i0 += 128 * ENT) {
-      unsigned pending = 0;
+  for (int c0 = 0; c0 < nn; c0 += 128 * EH) {
+    unsigned long long pending = 0;
 #pragma unroll
-      for (int q = 0; q < ENT; ++q)
-        if (i0 + xl + 128 * q < nn) pending |= 1u << q;
-      unsigned rounds = 0;
-      while (pending) {
-        V2<T> v[ENT];
+    for (int h = 0; h < NR; ++h)
 #pragma unroll
-        for (int q = 0; q < ENT; ++q)
-          if (pending & (1u << q)) v[q] = ld_coh<T>(sh + i0 + xl + 128 * q);
+      for (int q = 0; q < EH; ++q)
+        if (h < nrhs && c0 + xl + 128 * q < nn) pending |= 1ull << (h * EH + q);
+    unsigned rounds = 0;
+    while (pending) {
+      V2<T> v[NR][EH];
 #pragma unroll
-        for (int q = 0; q < ENT; ++q)
-          if ((pending & (1u << q)) && !is_sentinel(v[q].x) && !is_sentinel(v[q].y)) {
-            yh[i0 + xl + 128 * q] = v[q];
-            pending &= ~(1u << q);
+      for (int h = 0; h < NR; ++h)
+#pragma unroll
+        for (int q = 0; q < EH; ++q)
+          if ((pending >> (h * EH + q)) & 1ull)
+            v[h][q] = ld_coh<T>(src + h * sstride + d0 + c0 + xl + 128 * q);
+#pragma unroll
+      for (int h = 0; h < NR; ++h)
+#pragma unroll
+        for (int q = 0; q < EH; ++q)
+          if (((pending >> (h * EH + q)) & 1ull) && !is_sentinel(v[h][q].x) &&
+              !is_sentinel(v[h][q].y)) {
+            yv[h * nmax + c0 + xl + 128 * q] = v[h][q];
+            pending &= ~(1ull << (h * EH + q));
           }
-        if (pending) {
-          ++rounds;
-          if ((rounds & 255u) == 0) {
-            if (rounds > (1u << 20)) {
-              __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              break;
-            }
-            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      if (pending) {
+        ++rounds;
+        if ((rounds & 255u) == 0) {
+          if (rounds > (1u << 20)) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
           }
-          if (rounds > 8) __builtin_amdgcn_s_sleep(1);
+          if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
         }
+        if (rounds > 8) __builtin_amdgcn_s_sleep(1);
       }
     }
   }
 }
 
-// 512 threads. Waves 0-1 ("exchange waves") gather neighbour results (polling) and the
-// right-hand side into LDS, combine the row sums and publish the results; they never hold
-// prefetched data, so their loads are never ordered behind the stream. Waves 2-7 ("stream
-// waves") split the columns of the workgroup's rows of S_j: each lane forms the coupling
-// values of its own columns from LDS, accumulates partial row sums and, right after
-// consuming its last chunk, issues the loads of its first chunk of the next step.
-constexpr int NSW = 6;   // stream waves
+// 512 threads. Waves 0-1 ("exchange waves") gather neighbour results (polling) into LDS and
+// publish the results; while a step computes they stage the next step's right-hand side
+// (or zeros) into the LDS buffer the step no longer needs, so the two buffers swap roles from
+// step to step. After a workgroup barrier all eight waves fold the coupling to the neighbour
+// block into t. Waves 2-7 ("stream waves") form rows of S_j t: stream wave sw owns row group
+// sw / CG (RW rows of each chunk of RG * RW rows) and column half sw % CG, each lane QW
+// columns per chunk, so that one chunk covers the block rows of a workgroup and all of its
+// factor loads are in flight at once; they are issued right after the previous step's last
+// chunk was consumed. Per row the sum runs over the lane's columns in ascending order, then
+// across the wave, then over the column halves, for any number of right-hand sides.
+constexpr int NSW = 6;                 // stream waves
+constexpr int CSOL_CG = 2, CSOL_RG = 3, CSOL_RW = 3, CSOL_QW = 9;
 
-template <int P, typename T, int NR, int RCH, int QCH>
+template <int P, typename T, int NR>
 __global__ void __launch_bounds__(512)
 k_csolve(int s_begin, int s_end, int nc, int Mc, const V2<T>* __restrict__ coef,
          const V2<T>* __restrict__ S, const V2<T>* __restrict__ b, V2<T>* __restrict__ y,
          V2<T>* __restrict__ gbuf, int nrhs, long cstride, int* __restrict__ err) {
   constexpr int W = 2 * P + 1, W2 = W * W, NCOEF = P * P * 9 * W2;
-  constexpr int ENT = 12;                      // polled entries per lane and round
+  constexpr int CG = CSOL_CG, RG = CSOL_RG, RW = CSOL_RW, QW = CSOL_QW;
+  constexpr int RCH = RG * RW;                 // rows per chunk
+  // polled columns per exchange thread and right-hand side in one slice (registers: the
+  // stream waves' prefetched factor entries stay live across the exchange phase)
+  constexpr int EH = sizeof(T) == 8 ? (NR >= 4 ? 3 : NR == 2 ? 5 : 9) : (NR >= 4 ? 5 : 9);
   extern __shared__ char smem[];
   const int nmax = P * Mc;
   V2<T>* cl = reinterpret_cast<V2<T>*>(smem);  // coefficient table
-  V2<T>* t = cl + NCOEF;                       // [NR][nmax] b_j (or 0) minus the pre-pass term
-  V2<T>* yn = t + NR * nmax;                   // [NR][nmax] neighbour block (on-the-fly term)
-  __shared__ T red[2][NSW][RCH][NR];
+  V2<T>* buf0 = cl + NCOEF;                    // two [NR][nmax] buffers: t and neighbour
+  V2<T>* buf1 = buf0 + NR * nmax;
+  __shared__ T red[2][CG][RCH][NR];
   const int G = gridDim.x, g = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int sw = wave - 2;                     // stream wave index (valid for wave >= 2)
+  const int sw = wave - 2, rg = sw / CG, cg = sw - (sw / CG) * CG;
   const size_t bsz = size_t(P * Mc) * size_t(P * Mc);
   const long Nc = long(Mc) * Mc;
   for (int i = threadIdx.x; i < NCOEF; i += 512) cl[i] = coef[i];
 
-  V2<T> sv[RCH][QCH];
+  V2<T> sv[RW][QW];                            // stream waves: factor entries of a chunk
   bool have = false;                           // sv holds the first chunk of this step
+  bool staged = false;                         // t already holds this step's start value
+  int par = 0;
+
+  // exchange waves: dst[h][c] = b_j (forward steps) or 0, c < nj, in slices of 128 EH
+  auto stage = [&](const StepPlan& q, V2<T>* dst) {
+    const long d0 = long(P) * q.j * Mc;
+    for (int c0 = 0; c0 < q.nj; c0 += 128 * EH) {
+      V2<T> v[NR][EH];
+#pragma unroll
+      for (int h = 0; h < NR; ++h)
+#pragma unroll
+        for (int e = 0; e < EH; ++e) {
+          const int c = c0 + threadIdx.x + 128 * e;
+          v[h][e] = (q.fwd && h < nrhs && c < q.nj) ? b[h * cstride + d0 + c] : czero<T>();
+        }
+#pragma unroll
+      for (int h = 0; h < NR; ++h)
+#pragma unroll
+        for (int e = 0; e < EH; ++e) {
+          const int c = c0 + threadIdx.x + 128 * e;
+          if (h < nrhs && c < q.nj) dst[h * nmax + c] = v[h][e];
+        }
+    }
+  };
 
   for (int s = s_begin; s < s_end; ++s) {
     const StepPlan pl = make_plan<P>(s, g, G, nc, Mc);
     const int j = pl.j, nj = pl.nj;
     const long dof0 = long(P) * j * Mc;
-    // 1. exchange waves: right-hand side and the polled neighbour(s). The middle step couples
-    // two neighbours: the first is folded into t by all waves (LDS only) between two
-    // workgroup barriers; every barrier is reached by all waves (pl is uniform per workgroup).
+    V2<T>* t = par ? buf1 : buf0;
+    V2<T>* yn = par ? buf0 : buf1;
+    // 1. exchange waves: t = b_j (forward, middle) or 0 (backward) unless staged during the
+    // previous step; neighbour blocks. The middle step couples two neighbours: the first is
+    // folded in between two workgroup barriers (every barrier is reached by all waves: the
+    // plan is uniform per workgroup).
     if (wave < 2 && pl.active) {
-      const int xl = threadIdx.x;
-      for (int idx = xl; idx < nj * nrhs; idx += 128) {
-        const int h = idx / nj, c = idx - h * nj;
-        t[h * nmax + c] = pl.fwd ? b[h * cstride + dof0 + c] : czero<T>();
-      }
-      if (pl.jpre >= 0) gather_block<P, T, ENT>(gbuf, Nc, pl.jpre, nc, Mc, nrhs, nmax, yn, xl, err);
+      if (!staged) stage(pl, t);
+      if (pl.jpre >= 0)
+        gather_block<P, T, NR, EH>(gbuf, Nc, pl.jpre, nc, Mc, nrhs, nmax, yn, threadIdx.x, err);
     }
     if (pl.jpre >= 0) {
       __syncthreads();
-      for (int idx = threadIdx.x; idx < nj * nrhs; idx += 512) {
-        const int h = idx / nj, c = idx - h * nj;
-        const V2<T> cp = coupling<P, T>(c, j, pl.jpre, nc, Mc, cl, yn + h * nmax);
-        t[h * nmax + c] = csub<T>(t[h * nmax + c], cp);
-      }
+      for (int h = 0; h < nrhs; ++h)
+        for (int c = threadIdx.x; c < nj; c += 512) {
+          const V2<T> cp = coupling<P, T>(c, j, pl.jpre, nc, Mc, cl, yn + h * nmax);
+          t[h * nmax + c] = csub<T>(t[h * nmax + c], cp);
+        }
       __syncthreads();
     }
     if (wave < 2 && pl.active && pl.jfly >= 0) {
       const bool from_g = pl.fwd;              // forward/middle neighbours are in gbuf
-      gather_block<P, T, ENT>(from_g ? gbuf : y, from_g ? Nc : cstride, pl.jfly, nc, Mc, nrhs,
-                              nmax, yn, threadIdx.x, err);
+      gather_block<P, T, NR, EH>(from_g ? gbuf : y, from_g ? Nc : cstride, pl.jfly, nc, Mc,
+                                 nrhs, nmax, yn, threadIdx.x, err);
     }
     __syncthreads();
-    // 2. rows [r0, r1) of S_j t in chunks of RCH rows; stream wave sw owns columns [c0, c1)
+    // 2. fold the neighbour: t += sgn * A_{j,jfly} y_jfly
+    if (pl.active && pl.jfly >= 0) {
+      const T sgn = pl.fwd ? T(-1) : T(1);
+      for (int h = 0; h < nrhs; ++h)
+        for (int c = threadIdx.x; c < nj; c += 512) {
+          const V2<T> cp = coupling<P, T>(c, j, pl.jfly, nc, Mc, cl, yn + h * nmax);
+          V2<T> tv = t[h * nmax + c];
+          tv.x += sgn * cp.x;
+          tv.y += sgn * cp.y;
+          t[h * nmax + c] = tv;
+        }
+      __syncthreads();
+    }
+    // the neighbour buffer is free: the exchange waves stage the next step's start value
+    staged = false;
+    if (s + 1 < s_end) {
+      const StepPlan pn = make_plan<P>(s + 1, g, G, nc, Mc);
+      if (pn.active) {
+        if (wave < 2) stage(pn, yn);
+        staged = true;
+      }
+    }
+    // 3. rows [r0, r1) of S_j t in chunks of RCH rows
     const int r0 = pl.r0, r1 = pl.r1;
-    const int c0 = (nj * sw) / NSW, c1 = (nj * (sw + 1)) / NSW;
+    const int c0 = (nj * cg) / CG, c1 = (nj * (cg + 1)) / CG;
     const V2<T>* Sj = S + size_t(j) * bsz;
-    const T sgn = pl.fwd ? T(-1) : T(1);
     const bool pre = have;
     have = false;
     for (int rb = r0; rb < r1; rb += RCH) {
       if (wave >= 2) {
-        T ar[RCH][NR], ai[RCH][NR];
+        const int rw0 = rb + rg * RW;
+        T ar[RW][NR], ai[RW][NR];
 #pragma unroll
-        for (int rr = 0; rr < RCH; ++rr)
+        for (int i = 0; i < RW; ++i)
 #pragma unroll
-          for (int h = 0; h < NR; ++h) { ar[rr][h] = T(0); ai[rr][h] = T(0); }
+          for (int h = 0; h < NR; ++h) { ar[i][h] = T(0); ai[i][h] = T(0); }
         const int qn = (c1 - c0 + 63) / 64;
-        for (int q0 = 0; q0 < qn; q0 += QCH) {
+        for (int q0 = 0; q0 < qn; q0 += QW) {
           if (!(pre && rb == r0 && q0 == 0)) {
 #pragma unroll
-            for (int rr = 0; rr < RCH; ++rr)
+            for (int i = 0; i < RW; ++i)
 #pragma unroll
-              for (int q = 0; q < QCH; ++q) {
+              for (int q = 0; q < QW; ++q) {
                 const int c = c0 + lane + 64 * (q0 + q);
-                sv[rr][q] = (rb + rr < r1 && c < c1) ? Sj[size_t(rb + rr) * nj + c] : czero<T>();
+                sv[i][q] = (rw0 + i < r1 && c < c1) ? Sj[size_t(rw0 + i) * nj + c] : czero<T>();
               }
           }
 #pragma unroll
-          for (int q = 0; q < QCH; ++q) {
+          for (int q = 0; q < QW; ++q) {
             const int c = c0 + lane + 64 * (q0 + q);
             if (c >= c1) continue;
 #pragma unroll
             for (int h = 0; h < NR; ++h) {
               if (h >= nrhs) continue;
-              V2<T> tv = t[h * nmax + c];
-              if (pl.jfly >= 0) {
-                const V2<T> cp = coupling<P, T>(c, j, pl.jfly, nc, Mc, cl, yn + h * nmax);
-                tv.x += sgn * cp.x;
-                tv.y += sgn * cp.y;
-              }
+              const V2<T> tv = t[h * nmax + c];
 #pragma unroll
-              for (int rr = 0; rr < RCH; ++rr) {
-                ar[rr][h] += sv[rr][q].x * tv.x - sv[rr][q].y * tv.y;
-                ai[rr][h] += sv[rr][q].x * tv.y + sv[rr][q].y * tv.x;
+              for (int i = 0; i < RW; ++i) {
+                ar[i][h] += sv[i][q].x * tv.x - sv[i][q].y * tv.y;
+                ai[i][h] += sv[i][q].x * tv.y + sv[i][q].y * tv.x;
               }
             }
           }
@@ -589,25 +645,26 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, const V2<T>* __restrict__ coef,
           const StepPlan pn = make_plan<P>(s + 1, g, G, nc, Mc);
           if (pn.active && pn.r1 > pn.r0) {
             const int nj2 = pn.nj;
-            const int c02 = (nj2 * sw) / NSW, c12 = (nj2 * (sw + 1)) / NSW;
+            const int c02 = (nj2 * cg) / CG, c12 = (nj2 * (cg + 1)) / CG;
+            const int rn0 = pn.r0 + rg * RW;
             const V2<T>* Sj2 = S + size_t(pn.j) * bsz;
 #pragma unroll
-            for (int rr = 0; rr < RCH; ++rr)
+            for (int i = 0; i < RW; ++i)
 #pragma unroll
-              for (int q = 0; q < QCH; ++q) {
+              for (int q = 0; q < QW; ++q) {
                 const int c = c02 + lane + 64 * q;
-                sv[rr][q] = (pn.r0 + rr < pn.r1 && c < c12) ? Sj2[size_t(pn.r0 + rr) * nj2 + c]
-                                                            : czero<T>();
+                sv[i][q] = (rn0 + i < pn.r1 && c < c12) ? Sj2[size_t(rn0 + i) * nj2 + c]
+                                                       : czero<T>();
               }
             have = true;
           }
         }
 #pragma unroll
-        for (int rr = 0; rr < RCH; ++rr)
+        for (int i = 0; i < RW; ++i)
 #pragma unroll
           for (int h = 0; h < NR; ++h) {
-            const T sr = wave_sum(ar[rr][h]), si = wave_sum(ai[rr][h]);
-            if (lane == 0) { red[0][sw][rr][h] = sr; red[1][sw][rr][h] = si; }
+            const T sr = wave_sum(ar[i][h]), si = wave_sum(ai[i][h]);
+            if (lane == 0) { red[0][cg][rg * RW + i][h] = sr; red[1][cg][rg * RW + i][h] = si; }
           }
       }
       __syncthreads();
@@ -617,9 +674,9 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, const V2<T>* __restrict__ coef,
         if (r < r1 && h < nrhs) {
           T sr = red[0][0][rr][h], si = red[1][0][rr][h];
 #pragma unroll
-          for (int w2 = 1; w2 < NSW; ++w2) {
-            sr += red[0][w2][rr][h];
-            si += red[1][w2][rr][h];
+          for (int k = 1; k < CG; ++k) {
+            sr += red[0][k][rr][h];
+            si += red[1][k][rr][h];
           }
           V2<T> o;
           if (pl.fwd) {
@@ -636,28 +693,31 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, const V2<T>* __restrict__ coef,
       }
       __syncthreads();
     }
+    // a step without rows of this workgroup still needs the staged buffer to be complete
+    if (r1 <= r0) __syncthreads();
+    par ^= 1;
   }
 }
 
 constexpr size_t kLdsPerWorkgroup = 160 * 1024;   // gfx950
 
 // Dynamic plus static LDS bytes of one k_csolve workgroup.
-template <int P, typename T, int NR, int RCH>
+template <int P, typename T, int NR>
 constexpr size_t csolve_lds(int Mc) {
   return (size_t(P * P * 9 * (2 * P + 1) * (2 * P + 1)) + 2 * size_t(P) * Mc * NR) * sizeof(V2<T>) +
-         sizeof(T) * 2 * NSW * RCH * NR;
+         sizeof(T) * 2 * CSOL_CG * CSOL_RG * CSOL_RW * NR;
 }
 
-template <int P, typename T, int NR, int RCH, int QCH>
+template <int P, typename T, int NR>
 void csolve_launch(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b,
                    V2<T>* y, int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st) {
-  auto kern = k_csolve<P, T, NR, RCH, QCH>;
+  auto kern = k_csolve<P, T, NR>;
   const int nb = L.nblocks(), m = nb / 2;
   const int F = std::max(m, nb - 1 - m);
   const int nsteps = 2 * F + 1;
   constexpr int NCOEF = P * P * 9 * (2 * P + 1) * (2 * P + 1);
   const size_t lds = (NCOEF + 2 * size_t(L.size(0)) * NR) * sizeof(V2<T>);
-  if (csolve_lds<P, T, NR, RCH>(L.Mc) > kLdsPerWorkgroup)
+  if (csolve_lds<P, T, NR>(L.Mc) > kLdsPerWorkgroup)
     throw std::runtime_error("coarse solve staging exceeds the LDS of a workgroup");
   // dynamic LDS beyond the default limit must be requested; the static part counts too
   static size_t configured = 0;
@@ -706,19 +766,19 @@ template <int P, typename T>
 int csolve_p(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b, V2<T>* y,
              int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st) {
   if (nrhs == 1) {
-    csolve_launch<P, T, 1, 9, 3>(L, cop, S, b, y, 1, cstride, w, st);
+    csolve_launch<P, T, 1>(L, cop, S, b, y, 1, cstride, w, st);
     return 1;
   }
-  const int group = csolve_lds<P, T, 4, 3>(L.Mc) <= kLdsPerWorkgroup ? 4
-                    : csolve_lds<P, T, 2, 4>(L.Mc) <= kLdsPerWorkgroup ? 2 : 1;
+  const int group = csolve_lds<P, T, 4>(L.Mc) <= kLdsPerWorkgroup ? 4
+                    : csolve_lds<P, T, 2>(L.Mc) <= kLdsPerWorkgroup ? 2 : 1;
   int launches = 0;
   for (int r0 = 0; r0 < nrhs; r0 += group) {
     const int nr = std::min(group, nrhs - r0);
     const V2<T>* br = b + r0 * cstride;
     V2<T>* yr = y + r0 * cstride;
-    if (nr == 1) csolve_launch<P, T, 1, 9, 3>(L, cop, S, br, yr, 1, cstride, w, st);
-    else if (nr == 2) csolve_launch<P, T, 2, 4, 3>(L, cop, S, br, yr, 2, cstride, w, st);
-    else csolve_launch<P, T, 4, 3, 3>(L, cop, S, br, yr, nr, cstride, w, st);
+    if (nr == 1) csolve_launch<P, T, 1>(L, cop, S, br, yr, 1, cstride, w, st);
+    else if (nr == 2) csolve_launch<P, T, 2>(L, cop, S, br, yr, 2, cstride, w, st);
+    else csolve_launch<P, T, 4>(L, cop, S, br, yr, nr, cstride, w, st);
     ++launches;
   }
   return launches;
