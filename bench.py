@@ -239,6 +239,98 @@ def run_sweep(cfg, steps, warmup, prec):
                 betas=betas, thetas=thetas, converged=conv)
 
 
+def run_serving(count, rate, prec, max_active, tol=1e-8, restart=50):
+    """The serving stream: requests arrive at their (seeded) times, the engine admits them by
+    memory and slots and solves them with continuous batching; latency = submission to
+    completion."""
+    import torch
+    from paper_2104_01439_amd import hz, inputs
+
+    torch.cuda.set_device(0)
+    reqs = inputs.serving_requests(count, seed=1, rate=rate)
+    eng = hz.Engine(max_active=max_active, setup_threads=2, tol=tol, restart=restart, prec=prec)
+    done = {}
+    t0 = time.perf_counter()
+    nxt = 0
+    last_log = t0
+    while len(done) < len(reqs):
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and reqs[nxt]["t"] <= now:
+            r = reqs[nxt]
+            eng.submit(r["id"], r["k"], 1.0 / r["n"], r["p"], 1 + 1j * r["beta"], theta=r["theta"])
+            nxt += 1
+        wait = 200 if nxt >= len(reqs) else max(1, int(1e3 * (reqs[nxt]["t"] - now)))
+        for d, u in eng.poll(wait_ms=min(wait, 200)):
+            done[d["id"]] = d
+        if time.perf_counter() - last_log > 20:
+            last_log = time.perf_counter()
+            inf = eng.info()
+            log(f"  serving: {len(done)}/{len(reqs)} done, {inf['admitted']} admitted, "
+                f"{inf['queued']} queued, {inf['bytes_in_use'] / 1e9:.1f} GB in use")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    eng.close()
+    lat = np.array([done[r["id"]]["latency_s"] for r in reqs])
+    its = np.array([done[r["id"]]["iterations"] for r in reqs])
+    ok = all(done[r["id"]]["status"] == 0 and done[r["id"]]["converged"] == 1 for r in reqs)
+    worst = max(done[r["id"]]["rel_res_true"] for r in reqs)
+    return dict(seconds=dt, solves=len(reqs), p50=float(np.percentile(lat, 50)),
+                p99=float(np.percentile(lat, 99)), mean_its=float(its.mean()), ok=ok,
+                worst_rel_res=worst, classes=sorted({(r["p"], r["n"]) for r in reqs}))
+
+
+def run_sequential_fp64(count, tol=1e-8, restart=50):
+    """The plain FP64 path on the same requests, one after the other (create, solve, free)."""
+    import torch
+    from paper_2104_01439_amd import hz, inputs
+
+    torch.cuda.set_device(0)
+    reqs = inputs.serving_requests(count, seed=1, rate=None)
+    t0 = time.perf_counter()
+    for r in reqs:
+        pr = hz.Problem(r["k"], 1.0 / r["n"], r["p"], 1 + 1j * r["beta"], tol=tol, restart=restart)
+        pr.solve(pr.planewave_rhs(r["theta"]), tol=tol, history=False)
+        pr.close()
+    torch.cuda.synchronize()
+    return dict(seconds=time.perf_counter() - t0, solves=len(reqs))
+
+
+def main_serving(a):
+    g = run_serving(a.requests, a.rate if a.rate > 0 else None, a.prec, a.max_active)
+    value = g["solves"] / g["seconds"]
+    out = {
+        "metric": "FGMRES solves/s",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": 1e3 * g["seconds"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if a.prec == "fp64" else "f32-precond/f64-outer",
+        "data": "synthetic plane-wave impedance data",
+        "config": {"workload": "serving_stream", "requests": a.requests,
+                   "arrivals": "saturated (all at t=0)" if a.rate <= 0 else f"Poisson {a.rate}/s",
+                   "seed": 1, "tol": 1e-8, "restart": 50, "precision": a.prec,
+                   "max_active": a.max_active, "classes": [list(c) for c in g["classes"]]},
+        "latency_s": {"p50": g["p50"], "p99": g["p99"]},
+        "mean_iterations": g["mean_its"],
+        "all_converged": g["ok"],
+        "worst_true_rel_res": g["worst_rel_res"],
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    if a.baseline:
+        log("plain FP64 path, sequential, same requests ...")
+        sq = run_sequential_fp64(a.requests)
+        out["plain_fp64_sequential"] = {"value": sq["solves"] / sq["seconds"], "unit": "solves/s",
+                                        "seconds": sq["seconds"]}
+        out["speedup_vs_plain_fp64"] = value / out["plain_fp64_sequential"]["value"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +339,10 @@ def main():
     ap.add_argument("--workload", default="p1_k400_n2048")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--requests", type=int, default=200, help="serving: stream prefix length")
+    ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per s (0: all at once)")
+    ap.add_argument("--max-active", type=int, default=32, help="serving: engine slots")
+    ap.add_argument("--baseline", action="store_true", help="serving: also time the plain FP64 path")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
@@ -254,6 +350,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     from paper_2104_01439_amd import inputs
+    if a.workload == "serving":
+        return main_serving(a)
     if a.workload == inputs.CFG_SWEEP["name"]:
         return main_sweep(a, inputs.CFG_SWEEP)
     cfgs = {c["name"]: c for c in (inputs.CFG_SMALL, inputs.CFG_P1_LARGE, inputs.CFG_MIXED)}

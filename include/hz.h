@@ -159,9 +159,9 @@ hz_status hz_apply(const hz_problem* pr, int op, const hz_c64* d_x, const hz_c64
  * right-hand sides; A_0 and the Arnoldi kernels are launched once for all solves; the host
  * reads back once per round. Solves finish (or restart) independently. Every result is
  * bitwise what hz_solve gives for that solve alone (same kernels' arithmetic, same order).
- * Requirements: the problems are distinct, share (k, h, p), were created with
- * restart >= o->restart and, for HZ_FP64, with HZ_FP64; at most 4096 solves; d_F and d_u are
- * fine vectors (d_u may not alias any d_F). The call allocates a workspace of
+ * Requirements: the problems are distinct, share (h, p) (the wavenumbers may differ), were
+ * created with restart >= o->restart and, for HZ_FP64, with HZ_FP64; at most 4096 solves;
+ * d_F and d_u are fine vectors (d_u may not alias any d_F). The call allocates a workspace of
  * hz_batch_workspace_bytes(...) device bytes and frees it before returning. Errors as
  * hz_solve, HZ_EBUSY if a problem is in use, HZ_ENOMEM if the workspace does not fit.
  * Synchronises hip_stream. */
@@ -174,6 +174,64 @@ hz_status hz_solve_batched(hz_problem* const* probs, int nprob, const hz_c64* co
  * = defaults); 0 for invalid parameters. */
 size_t hz_batch_workspace_bytes(double h, int p, int nprob, int nrhs_per_prob,
                                 const hz_options* o);
+
+/* ---------------------------------------------------------------------------------------
+ * Serving engine (the many-sample form of Sec. 5): requests of any (k, h, p, shift) are
+ * queued, admitted in arrival order while a slot and the device-memory budget allow, set up
+ * (tables, coarse factor) on setup threads with their own streams while the admitted
+ * requests iterate, and solved by continuous batching: every round performs one FGMRES
+ * iteration of each active request and synchronises once; finished requests leave between
+ * rounds and free their memory, new ones join. Each request runs exactly the arithmetic of
+ * hz_solve (its result is the same alone and in any mix). Options (restart, tol, maxit,
+ * precision, nu, omega) are the engine's, fixed at creation.
+ * --------------------------------------------------------------------------------------- */
+typedef struct {
+  size_t hbm_budget;   /* device bytes the engine may hold; 0 = 85 % of the free memory    */
+  int max_active;      /* requests admitted at once (set up or iterating); default 64      */
+  int setup_threads;   /* host threads preparing admitted requests; default 2              */
+} hz_engine_config;
+
+typedef struct {
+  long id;              /* the req_id given to hz_engine_submit                            */
+  int status;           /* HZ_OK, or the error that ended the request (then see message)   */
+  hz_result result;     /* iterations, residuals; setup_s = creation, solve_s = iterations */
+  double queue_s;       /* wall seconds from submission to admission                       */
+  double latency_s;     /* wall seconds from submission to completion                      */
+  char message[120];    /* error text when status != HZ_OK                                  */
+} hz_engine_result;
+
+typedef struct {
+  int queued, admitted;        /* waiting for admission; admitted and not finished          */
+  size_t bytes_in_use, hbm_budget;
+  long submitted, completed;
+} hz_engine_info_t;
+
+hz_status hz_engine_default_config(hz_engine_config* c);
+
+/* Starts an engine on the calling thread's current device (its own streams and threads).
+ * o: solver options for every request (NULL = defaults). Errors: HZ_EINVAL, HZ_EDEVICE. */
+hz_status hz_engine_create(const hz_engine_config* c, const hz_options* o, hz_engine** out);
+
+/* Queues one solve of A_0(k, h, p) u = F preconditioned with shift s. F is the plane-wave
+ * load for angle theta when d_F is NULL, else a copy of the fine vector d_F taken at setup
+ * (d_F must stay valid until the request is reported). The solution is written to d_u (a
+ * caller-owned fine vector that must stay valid and untouched until the request is
+ * reported; it is complete when hz_engine_poll returns it). Thread-safe, non-blocking.
+ * Errors: HZ_EINVAL (bad parameters), HZ_ENOMEM (the request alone exceeds the budget),
+ * HZ_EBUSY (the engine is being destroyed). */
+hz_status hz_engine_submit(hz_engine* e, double k, double h, int p, hz_c64 s, double theta,
+                           const hz_c64* d_F, hz_c64* d_u, long req_id);
+
+/* Moves up to max finished requests into out (in completion order) and sets *ndone. Waits up
+ * to wait_ms milliseconds for one when none is ready (0 = do not wait). Thread-safe. */
+hz_status hz_engine_poll(hz_engine* e, hz_engine_result* out, int max, int* ndone, int wait_ms);
+
+/* Queue and memory state. */
+hz_status hz_engine_info(hz_engine* e, hz_engine_info_t* info);
+
+/* Stops the engine: waits for the current round, drops queued and unfinished requests (they
+ * are not reported) and frees everything. NULL is a no-op. */
+void hz_engine_destroy(hz_engine* e);
 
 /* Copies the problem's counters into *out (waiting for pending timed launches) and, if
  * reset is nonzero, zeroes them. Without timing the device times stay 0. */

@@ -11,8 +11,12 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <condition_variable>
+#include <deque>
 #include <memory>
+#include <mutex>
 #include <new>
+#include <thread>
 
 #include "hz_internal.h"
 
@@ -533,82 +537,113 @@ struct SolveState {
   cd& Hat(int i, int jj) { return H[size_t(i) * m + jj]; }
 };
 
-// Runs nsol = nprob * nrhs FGMRES(o.restart) solves in lockstep: every round performs one
-// Arnoldi step of each unfinished solve, with the fine kernels and the Arnoldi kernels
+// nsol = nprob * nrhs FGMRES(o.restart) solves advancing in lockstep: every round performs
+// one Arnoldi step of each unfinished solve, with the fine kernels and the Arnoldi kernels
 // launched once for all of them and the V-cycles of one problem's right-hand sides sharing
 // each read of its coarse factor. Solve q belongs to problem q / nrhs; its right-hand side
 // and solution are at Fb + foff[q] and Ub + uoff[q]. Each solve follows exactly the steps
-// (and floating-point order) it would follow alone.
-hz_status lockstep(hz_problem* const* probs, int nprob, int nrhs, const double2* Fb,
-                   const long* foff, double2* Ub, const long* uoff, Workspace& ws,
-                   const hz_options& o, hz_result* res, double* const* hist, hipStream_t st) {
-  const auto t0 = clk::now();
-  const int nsol = nprob * nrhs;
-  const bool mixed = o.prec == HZ_MIXED;
-  const long N = ws.N;
-  const int m = o.restart, nblk = ws.nblk;
-  const long vstr = long(ws.m + 1) * N, zstr = long(ws.m) * N;
-  hz_problem* pr0 = probs[0];
-  const DevOp<double> a0{pr0->cA0, nullptr, pr0->M};
-  const int p = pr0->p;
-  char* hreg[2] = {ws.up, ws.up + ws.up_bytes};
-  char* dreg[2] = {ws.dreg, ws.dreg + ws.up_bytes};
-  auto upload = [&](int k) {
-    HZ_HIP(hipMemcpyAsync(dreg[k], hreg[k], ws.up_bytes, hipMemcpyHostToDevice, st));
-  };
-  auto sync_read = [&](int count) {
-    HZ_HIP(hipMemcpyAsync(ws.pin, ws.hbuf, size_t(count) * 192 * 16, hipMemcpyDeviceToHost, st));
-    HZ_HIP(hipStreamSynchronize(st));
+// (and floating-point order) it would follow alone. The phases are separate so that a
+// caller can interleave the rounds of several groups on one stream:
+//   start()   norms of F, u = 0, r = F                                  (synchronises)
+//   issue()   queue one round: v_j, V-cycles, A_0 z_j, CGS2, read-back   (asynchronous)
+//   complete() after the stream is synchronised: Hessenberg column, rotations, estimate;
+//             cycle ends (u += Z y, true residual)                      (synchronises)
+struct Lockstep {
+  hz_problem* const* probs = nullptr;
+  int nprob = 0, nrhs = 0, nsol = 0;
+  const double2* Fb = nullptr;
+  const long* foff = nullptr;
+  double2* Ub = nullptr;
+  const long* uoff = nullptr;
+  Workspace* ws = nullptr;
+  hz_options o{};
+  std::vector<SolveState> S;
+  std::vector<int> act, end;
+  std::vector<cd> y;
+  clk::time_point t0;
+  bool issued = false;
+
+  Lockstep(hz_problem* const* probs_, int nprob_, int nrhs_, const double2* Fb_,
+           const long* foff_, double2* Ub_, const long* uoff_, Workspace& ws_,
+           const hz_options& o_)
+      : probs(probs_), nprob(nprob_), nrhs(nrhs_), nsol(nprob_ * nrhs_), Fb(Fb_), foff(foff_),
+        Ub(Ub_), uoff(uoff_), ws(&ws_), o(o_) {}
+
+  char* hreg(int k) const { return ws->up + k * ws->up_bytes; }
+  char* dreg(int k) const { return ws->dreg + k * ws->up_bytes; }
+  void upload(int k, hipStream_t st) {
+    HZ_HIP(hipMemcpyAsync(dreg(k), hreg(k), ws->up_bytes, hipMemcpyHostToDevice, st));
+  }
+  void read_back(int count, hipStream_t st) {
+    HZ_HIP(hipMemcpyAsync(ws->pin, ws->hbuf, size_t(count) * 192 * 16, hipMemcpyDeviceToHost, st));
+  }
+  void after_sync() {
     for (int i = 0; i < nprob; ++i)
       if (probs[i]->timing) collect_timing(probs[i], false);
-  };
-  const long cap = ws.cap;
-  // ---- norms of the right-hand sides; u = 0, r = F ----
-  {
-    Region h = region_at(hreg[0], ws.cap);
-    const Region d = region_at(dreg[0], ws.cap);
+  }
+  bool finished() const {
+    for (const auto& x : S)
+      if (!x.done) return false;
+    return true;
+  }
+
+  hz_status start(double* const* hist, hipStream_t st) {
+    t0 = clk::now();
+    const long N = ws->N, cap = ws->cap;
+    const int m = o.restart;
+    Region h = region_at(hreg(0), ws->cap);
+    const Region d = region_at(dreg(0), ws->cap);
     for (int q = 0; q < nsol; ++q) { h.tab[q] = foff[q]; h.tab[cap + q] = uoff[q]; }
-    upload(0);
-    launch_mdot_b(Fb, Addr(0, d.tab), 0, 1, nullptr, Fb, Addr(0, d.tab), N, ws.partial, nblk, nsol, st);
-    launch_reduce_b(ws.partial, nblk, 1, nullptr, ws.hbuf, 192, nsol, st);
+    upload(0, st);
+    launch_mdot_b(Fb, Addr(0, d.tab), 0, 1, nullptr, Fb, Addr(0, d.tab), N, ws->partial,
+                  ws->nblk, nsol, st);
+    launch_reduce_b(ws->partial, ws->nblk, 1, nullptr, ws->hbuf, 192, nsol, st);
     launch_fill_zero_b(Ub, Addr(0, d.tab + cap), N, nsol, st);
-    launch_copy_b(Fb, Addr(0, d.tab), ws.RW, Addr(N), N, nsol, st);
-    sync_read(nsol);
-  }
-  std::vector<SolveState> S(nsol);
-  for (int q = 0; q < nsol; ++q) {
-    SolveState& x = S[q];
-    x.prob = q / nrhs;
-    x.m = m;
-    x.hist = hist ? hist[q] : nullptr;
-    x.normF = std::sqrt(ws.pin[size_t(q) * 192].x);
-    if (!std::isfinite(x.normF)) return fail(HZ_EINVAL, "right-hand side is not finite");
-    x.H.assign(size_t(m + 1) * m, cd(0, 0));
-    x.g.assign(m + 1, cd(0, 0));
-    x.cs.assign(m, 0.0);
-    x.sn.assign(m, cd(0, 0));
-    if (x.normF == 0.0) {
-      x.done = true;
-      x.conv = true;
-      x.est = 0;
-      x.true_rel = 0;
-      continue;
+    launch_copy_b(Fb, Addr(0, d.tab), ws->RW, Addr(N), N, nsol, st);
+    read_back(nsol, st);
+    HZ_HIP(hipStreamSynchronize(st));
+    after_sync();
+    S.assign(nsol, SolveState());
+    y.assign(m, cd(0, 0));
+    for (int q = 0; q < nsol; ++q) {
+      SolveState& x = S[q];
+      x.prob = q / nrhs;
+      x.m = m;
+      x.hist = hist ? hist[q] : nullptr;
+      x.normF = std::sqrt(ws->pin[size_t(q) * 192].x);
+      if (!std::isfinite(x.normF)) return fail(HZ_EINVAL, "right-hand side is not finite");
+      x.H.assign(size_t(m + 1) * m, cd(0, 0));
+      x.g.assign(m + 1, cd(0, 0));
+      x.cs.assign(m, 0.0);
+      x.sn.assign(m, cd(0, 0));
+      if (x.normF == 0.0) {
+        x.done = true;
+        x.conv = true;
+        x.est = 0;
+        x.true_rel = 0;
+        continue;
+      }
+      x.beta = x.normF;
+      x.scale = 1.0 / x.beta;
+      x.g[0] = x.beta;
     }
-    x.beta = x.normF;
-    x.scale = 1.0 / x.beta;
-    x.g[0] = x.beta;
+    return HZ_OK;
   }
-  std::vector<int> act, end;
-  std::vector<cd> y(m);
-  while (true) {
+
+  // Queues one Arnoldi step of every unfinished solve; false when none is left.
+  bool issue(hipStream_t st) {
     act.clear();
     for (int q = 0; q < nsol; ++q)
       if (!S[q].done) act.push_back(q);
-    if (act.empty()) break;
+    issued = !act.empty();
+    if (!issued) return false;
     const int na = int(act.size());
-    // ---- tables of this round ----
-    Region h = region_at(hreg[0], ws.cap);
-    const Region d = region_at(dreg[0], ws.cap);
+    const bool mixed = o.prec == HZ_MIXED;
+    const long N = ws->N, cap = ws->cap;
+    const long vstr = long(ws->m + 1) * N, zstr = long(ws->m) * N;
+    const int p = probs[0]->p, nblk = ws->nblk;
+    Region h = region_at(hreg(0), ws->cap);
+    const Region d = region_at(dreg(0), ws->cap);
     long* t_src = h.tab;               // scale source (r or w) in RW
     long* t_vj = h.tab + cap;          // v_j in V
     long* t_vb = h.tab + 2 * cap;      // basis of the solve in V
@@ -627,53 +662,84 @@ hz_status lockstep(hz_problem* const* probs, int nprob, int nrhs, const double2*
       h.scl[z] = x.scale;
       maxnv = std::max(maxnv, x.j + 1);
     }
-    upload(0);
+    upload(0, st);
     const long* d_src = d.tab;
     const long* d_vj = d.tab + cap;
     const long* d_vb = d.tab + 2 * cap;
     const long* d_zj = d.tab + 3 * cap;
     const long* d_w = d.tab + 4 * cap;
     // v_j = r / beta (cycle start) or w / h_{j,j-1}
-    launch_scale_b(ws.RW, Addr(0, d_src), d.scl, ws.V, Addr(0, d_vj), N, na, st);
-    // z_j = V-cycle(v_j): one batch per problem (its unfinished right-hand sides)
+    launch_scale_b(ws->RW, Addr(0, d_src), d.scl, ws->V, Addr(0, d_vj), N, na, st);
+    // z_j = V-cycle(v_j), then w = A_0 z_j: one batch per problem (its unfinished
+    // right-hand sides)
     for (int z0 = 0; z0 < na;) {
       const int i = S[act[z0]].prob;
       int z1 = z0;
       while (z1 < na && S[act[z1]].prob == i) ++z1;
       hz_problem* pi = probs[i];
+      const int nb = z1 - z0;
       if (!mixed) {
-        vcycle<double>(pi, level64(pi, ws.s64), pi->opt.nu, ws.V, Addr(0, d_vj + z0), ws.Zd,
-                       Addr(0, d_zj + z0), z1 - z0, st);
+        vcycle<double>(pi, level64(pi, ws->s64), pi->opt.nu, ws->V, Addr(0, d_vj + z0), ws->Zd,
+                       Addr(0, d_zj + z0), nb, st);
       } else {
-        launch_d2f_b(ws.V, Addr(0, d_vj + z0), ws.s32.ff, Addr(N), N, z1 - z0, st);
-        vcycle<float>(pi, level32(pi, ws.s32), pi->opt.nu, ws.s32.ff, Addr(N), ws.Zf,
-                      Addr(0, d_zj + z0), z1 - z0, st);
+        launch_d2f_b(ws->V, Addr(0, d_vj + z0), ws->s32.ff, Addr(N), N, nb, st);
+        vcycle<float>(pi, level32(pi, ws->s32), pi->opt.nu, ws->s32.ff, Addr(N), ws->Zf,
+                      Addr(0, d_zj + z0), nb, st);
       }
       z0 = z1;
     }
-    // w = A_0 z_j (A_0 is the same for every problem of the group)
-    if (!mixed)
-      launch_stencil<double, double, double, double>(p, ST_APPLY, a0, ws.Zd, Addr(0, d_zj), nullptr,
-                                                     Addr(), ws.RW, Addr(0, d_w), na, st);
-    else
-      launch_stencil<double, float, double, double>(p, ST_APPLY, a0, ws.Zf, Addr(0, d_zj), nullptr,
-                                                    Addr(), ws.RW, Addr(0, d_w), na, st);
+    if (shared_a0()) {
+      const DevOp<double> a0{probs[0]->cA0, nullptr, probs[0]->M};
+      apply_a0(a0, p, Addr(0, d_zj), Addr(0, d_w), na, st);
+    } else {
+      for (int z0 = 0; z0 < na;) {
+        const int i = S[act[z0]].prob;
+        int z1 = z0;
+        while (z1 < na && S[act[z1]].prob == i) ++z1;
+        const DevOp<double> a0{probs[i]->cA0, nullptr, probs[i]->M};
+        apply_a0(a0, p, Addr(0, d_zj + z0), Addr(0, d_w + z0), z1 - z0, st);
+        z0 = z1;
+      }
+    }
     // CGS2: two passes of h = V^H w, w -= V h; then |w|^2
-    launch_mdot_b(ws.V, Addr(0, d_vb), N, 64, d.itab, ws.RW, Addr(0, d_w), N, ws.partial, nblk, na, st);
-    launch_reduce_b(ws.partial, nblk, maxnv, d.itab, ws.hbuf, 192, na, st);
-    launch_maxpy_b(ws.V, Addr(0, d_vb), N, 64, d.itab, ws.hbuf, 192, ws.RW, Addr(0, d_w), N,
+    launch_mdot_b(ws->V, Addr(0, d_vb), N, 64, d.itab, ws->RW, Addr(0, d_w), N, ws->partial, nblk, na, st);
+    launch_reduce_b(ws->partial, nblk, maxnv, d.itab, ws->hbuf, 192, na, st);
+    launch_maxpy_b(ws->V, Addr(0, d_vb), N, 64, d.itab, ws->hbuf, 192, ws->RW, Addr(0, d_w), N,
                    nullptr, nblk, na, st);
-    launch_mdot_b(ws.V, Addr(0, d_vb), N, 64, d.itab, ws.RW, Addr(0, d_w), N, ws.partial, nblk, na, st);
-    launch_reduce_b(ws.partial, nblk, maxnv, d.itab, ws.hbuf + 64, 192, na, st);
-    launch_maxpy_b(ws.V, Addr(0, d_vb), N, 64, d.itab, ws.hbuf + 64, 192, ws.RW, Addr(0, d_w), N,
-                   ws.partial, nblk, na, st);
-    launch_reduce_b(ws.partial, nblk, 1, nullptr, ws.hbuf + 128, 192, na, st);
-    sync_read(na);
-    // ---- Hessenberg column, rotations, residual estimate (host, per solve) ----
+    launch_mdot_b(ws->V, Addr(0, d_vb), N, 64, d.itab, ws->RW, Addr(0, d_w), N, ws->partial, nblk, na, st);
+    launch_reduce_b(ws->partial, nblk, maxnv, d.itab, ws->hbuf + 64, 192, na, st);
+    launch_maxpy_b(ws->V, Addr(0, d_vb), N, 64, d.itab, ws->hbuf + 64, 192, ws->RW, Addr(0, d_w), N,
+                   ws->partial, nblk, na, st);
+    launch_reduce_b(ws->partial, nblk, 1, nullptr, ws->hbuf + 128, 192, na, st);
+    read_back(na, st);
+    return true;
+  }
+
+  bool shared_a0() const {
+    for (int i = 1; i < nprob; ++i)
+      if (probs[i]->k != probs[0]->k) return false;
+    return true;
+  }
+  void apply_a0(const DevOp<double>& a0, int p, Addr az, Addr aw, int nb, hipStream_t st) {
+    if (o.prec != HZ_MIXED)
+      launch_stencil<double, double, double, double>(p, ST_APPLY, a0, ws->Zd, az, nullptr, Addr(),
+                                                     ws->RW, aw, nb, st);
+    else
+      launch_stencil<double, float, double, double>(p, ST_APPLY, a0, ws->Zf, az, nullptr, Addr(),
+                                                    ws->RW, aw, nb, st);
+  }
+
+  // After the round's read-back has landed (the caller synchronised the stream).
+  hz_status complete(hipStream_t st) {
+    if (!issued) return HZ_OK;
+    issued = false;
+    after_sync();
+    const int na = int(act.size());
+    const int m = o.restart;
     end.clear();
     for (int z = 0; z < na; ++z) {
       SolveState& x = S[act[z]];
-      const double2* hb = ws.pin + size_t(z) * 192;
+      const double2* hb = ws->pin + size_t(z) * 192;
       const int j = x.j;
       x.its += 1;
       for (int i = 0; i <= j; ++i)
@@ -704,11 +770,14 @@ hz_status lockstep(hz_problem* const* probs, int nprob, int nrhs, const double2*
         x.j = j + 1;
       }
     }
-    if (end.empty()) continue;
+    if (end.empty()) return HZ_OK;
     // ---- cycle ends: u += Z y, r = F - A_0 u, ||r|| ----
+    const bool mixed = o.prec == HZ_MIXED;
+    const long N = ws->N, cap = ws->cap;
+    const long zstr = long(ws->m) * N;
     const int ne = int(end.size());
-    Region h2 = region_at(hreg[1], ws.cap);
-    const Region d2 = region_at(dreg[1], ws.cap);
+    Region h2 = region_at(hreg(1), ws->cap);
+    const Region d2 = region_at(dreg(1), ws->cap);
     for (int e = 0; e < ne; ++e) {
       SolveState& x = S[end[e]];
       const long q = end[e];
@@ -725,23 +794,34 @@ hz_status lockstep(hz_problem* const* probs, int nprob, int nrhs, const double2*
       h2.tab[3 * cap + e] = q * N;
       h2.itab[e] = jend;
     }
-    upload(1);
+    upload(1, st);
     if (!mixed)
-      launch_update_b<double>(ws.Zd, Addr(0, d2.tab), N, 64, d2.itab, d2.y, 64, Ub,
+      launch_update_b<double>(ws->Zd, Addr(0, d2.tab), N, 64, d2.itab, d2.y, 64, Ub,
                               Addr(0, d2.tab + cap), N, ne, st);
     else
-      launch_update_b<float>(ws.Zf, Addr(0, d2.tab), N, 64, d2.itab, d2.y, 64, Ub,
+      launch_update_b<float>(ws->Zf, Addr(0, d2.tab), N, 64, d2.itab, d2.y, 64, Ub,
                              Addr(0, d2.tab + cap), N, ne, st);
-    launch_stencil<double, double, double, double>(p, ST_RESID, a0, Ub, Addr(0, d2.tab + cap), Fb,
-                                                   Addr(0, d2.tab + 2 * cap), ws.RW,
-                                                   Addr(0, d2.tab + 3 * cap), ne, st);
-    launch_mdot_b(ws.RW, Addr(0, d2.tab + 3 * cap), 0, 1, nullptr, ws.RW, Addr(0, d2.tab + 3 * cap),
-                  N, ws.partial, nblk, ne, st);
-    launch_reduce_b(ws.partial, nblk, 1, nullptr, ws.hbuf, 192, ne, st);
-    sync_read(ne);
+    for (int e0 = 0; e0 < ne;) {
+      // r = F - A_0 u, one launch per run of solves of one wavenumber
+      const int i = S[end[e0]].prob;
+      int e1 = e0;
+      while (e1 < ne && (shared_a0() || S[end[e1]].prob == i)) ++e1;
+      const DevOp<double> a0{probs[i]->cA0, nullptr, probs[i]->M};
+      launch_stencil<double, double, double, double>(probs[0]->p, ST_RESID, a0, Ub,
+                                                     Addr(0, d2.tab + cap + e0), Fb,
+                                                     Addr(0, d2.tab + 2 * cap + e0), ws->RW,
+                                                     Addr(0, d2.tab + 3 * cap + e0), e1 - e0, st);
+      e0 = e1;
+    }
+    launch_mdot_b(ws->RW, Addr(0, d2.tab + 3 * cap), 0, 1, nullptr, ws->RW, Addr(0, d2.tab + 3 * cap),
+                  N, ws->partial, ws->nblk, ne, st);
+    launch_reduce_b(ws->partial, ws->nblk, 1, nullptr, ws->hbuf, 192, ne, st);
+    read_back(ne, st);
+    HZ_HIP(hipStreamSynchronize(st));
+    after_sync();
     for (int e = 0; e < ne; ++e) {
       SolveState& x = S[end[e]];
-      x.beta = std::sqrt(ws.pin[size_t(e) * 192].x);
+      x.beta = std::sqrt(ws->pin[size_t(e) * 192].x);
       x.true_rel = x.beta / x.normF;
       if (x.true_rel <= o.tol) {
         x.done = true;
@@ -757,14 +837,20 @@ hz_status lockstep(hz_problem* const* probs, int nprob, int nrhs, const double2*
         x.g[0] = x.beta;
       }
     }
+    return HZ_OK;
   }
-  for (int i = 0; i < nprob; ++i) {
-    int e = 0;
-    HZ_HIP(hipMemcpy(&e, probs[i]->cw.err, sizeof(int), hipMemcpyDeviceToHost));
-    if (e) return fail(HZ_EDEVICE, "coarse solve: a wait for another workgroup timed out");
+
+  hz_status check_device() {
+    for (int i = 0; i < nprob; ++i) {
+      int e = 0;
+      HZ_HIP(hipMemcpy(&e, probs[i]->cw.err, sizeof(int), hipMemcpyDeviceToHost));
+      if (e) return fail(HZ_EDEVICE, "coarse solve: a wait for another workgroup timed out");
+    }
+    return HZ_OK;
   }
-  const double solve_s = secs(t0);
-  if (res)
+
+  void results(hz_result* res) const {
+    const double solve_s = secs(t0);
     for (int q = 0; q < nsol; ++q) {
       hz_result r{};
       r.iterations = S[q].its;
@@ -775,6 +861,23 @@ hz_status lockstep(hz_problem* const* probs, int nprob, int nrhs, const double2*
       r.solve_s = solve_s;
       res[q] = r;
     }
+  }
+};
+
+hz_status lockstep(hz_problem* const* probs, int nprob, int nrhs, const double2* Fb,
+                   const long* foff, double2* Ub, const long* uoff, Workspace& ws,
+                   const hz_options& o, hz_result* res, double* const* hist, hipStream_t st) {
+  Lockstep L(probs, nprob, nrhs, Fb, foff, Ub, uoff, ws, o);
+  hz_status r = L.start(hist, st);
+  if (r != HZ_OK) return r;
+  while (L.issue(st)) {
+    HZ_HIP(hipStreamSynchronize(st));
+    r = L.complete(st);
+    if (r != HZ_OK) return r;
+  }
+  r = L.check_device();
+  if (r != HZ_OK) return r;
+  if (res) L.results(res);
   return HZ_OK;
 }
 
@@ -1043,8 +1146,8 @@ hz_status hz_solve_batched(hz_problem* const* probs, int nprob, const hz_c64* co
   if (nsol > 4096) return fail(HZ_EINVAL, "at most 4096 solves per batch");
   for (int i = 0; i < nprob; ++i) {
     if (!probs[i]) return fail(HZ_EINVAL, "null problem");
-    if (probs[i]->n != probs[0]->n || probs[i]->p != probs[0]->p || probs[i]->k != probs[0]->k)
-      return fail(HZ_EINVAL, "batched problems must share (k, h, p)");
+    if (probs[i]->n != probs[0]->n || probs[i]->p != probs[0]->p)
+      return fail(HZ_EINVAL, "batched problems must share (h, p)");
     for (int i2 = 0; i2 < i; ++i2)
       if (probs[i2] == probs[i]) return fail(HZ_EINVAL, "a problem appears twice in the batch");
   }
@@ -1126,5 +1229,389 @@ hz_status hz_problem_stats(hz_problem* pr, hz_stats* out, int reset) {
 }
 
 void hz_destroy_problem(hz_problem* pr) { delete pr; }
+
+}  // extern "C"
+
+// =========================================================================================
+// Serving engine: continuous batching of independent solves
+// =========================================================================================
+
+namespace {
+
+struct EngineRequest {
+  long id = 0;
+  double k = 0, h = 0, theta = 0;
+  int p = 1;
+  cd s;
+  const double2* F = nullptr;     // caller's right-hand side, or null: plane-wave load
+  double2* u = nullptr;           // caller's solution buffer
+  clk::time_point t_submit, t_admit, t_start;
+  size_t bytes_setup = 0, bytes = 0;
+  hz_problem* pr = nullptr;
+  std::unique_ptr<Workspace> ws;
+  std::unique_ptr<Lockstep> ls;
+  hz_problem* probs[1] = {nullptr};
+  long off0 = 0;
+  hz_status status = HZ_OK;
+  std::string err;
+  bool admitted = false, setup_done = false;
+  ~EngineRequest() {
+    ls.reset();
+    ws.reset();
+    if (pr) hz_destroy_problem(pr);
+  }
+};
+
+size_t request_bytes(int n, int p, int m, int prec, size_t* setup) {
+  const Sizes z = sizes_of(n, p);
+  const size_t steady = resident_bytes(n, p, m, prec) + 2 * size_t(z.N) * 16;
+  // a mixed problem holds the FP64 factor and its FP32 copy while it is set up
+  *setup = steady + (prec == HZ_MIXED ? z.factor_elems * 16 : 0);
+  return steady;
+}
+
+}  // namespace
+
+struct hz_engine {
+  hz_engine_config cfg{};
+  hz_options opt{};
+  int device = 0;
+  hipStream_t st_solve = nullptr;
+  std::vector<hipStream_t> st_setup;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_setup, cv_done;
+  std::deque<EngineRequest*> pending, setup_q, ready, trash;
+  std::vector<EngineRequest*> active;   // owned by the loop thread
+  std::condition_variable cv_trash;
+  std::deque<hz_engine_result> done;
+  size_t used = 0;
+  int admitted = 0;                     // admitted and not yet retired
+  long submitted = 0, completed = 0;
+  bool stop = false;
+  std::thread loop, reaper;
+  std::vector<std::thread> setup;
+  ~hz_engine() {
+    for (auto* r : trash) delete r;
+    for (auto* r : pending) delete r;
+    for (auto* r : setup_q) delete r;
+    for (auto* r : ready) delete r;
+    for (auto* r : active) delete r;
+    if (st_solve) (void)hipStreamDestroy(st_solve);
+    for (auto s : st_setup) (void)hipStreamDestroy(s);
+  }
+};
+
+namespace {
+
+void engine_finish(hz_engine* e, EngineRequest* r, const hz_result* res) {
+  hz_engine_result out{};
+  out.id = r->id;
+  out.status = r->status;
+  if (res) out.result = *res;
+  const auto now = clk::now();
+  out.queue_s = std::chrono::duration<double>(r->t_admit - r->t_submit).count();
+  out.latency_s = std::chrono::duration<double>(now - r->t_submit).count();
+  if (r->status != HZ_OK) {
+    out.queue_s = std::max(0.0, out.queue_s);
+    std::snprintf(out.message, sizeof(out.message), "%s", r->err.c_str());
+  }
+  {
+    std::lock_guard<std::mutex> g(e->mu);
+    if (r->admitted) {
+      e->used -= r->setup_done ? r->bytes : r->bytes_setup;
+      e->admitted -= 1;
+    }
+    e->done.push_back(out);
+    e->completed += 1;
+    // device memory is released by the reaper thread: a free may wait for the device
+    e->trash.push_back(r);
+  }
+  e->cv_trash.notify_one();
+  e->cv_done.notify_all();
+  e->cv_work.notify_all();
+}
+
+void engine_reaper_main(hz_engine* e) {
+  (void)hipSetDevice(e->device);
+  while (true) {
+    EngineRequest* r = nullptr;
+    {
+      std::unique_lock<std::mutex> g(e->mu);
+      e->cv_trash.wait(g, [&] { return e->stop || !e->trash.empty(); });
+      if (e->trash.empty()) return;
+      r = e->trash.front();
+      e->trash.pop_front();
+    }
+    delete r;
+  }
+}
+
+// Setup thread: create the problem (tables, coarse factor) and the solve workspace on its
+// own stream, so that factorisations overlap the solve rounds of admitted requests.
+void engine_setup_main(hz_engine* e, int tid) {
+  (void)hipSetDevice(e->device);
+  hipStream_t st = e->st_setup[tid];
+  while (true) {
+    EngineRequest* r = nullptr;
+    {
+      std::unique_lock<std::mutex> g(e->mu);
+      e->cv_setup.wait(g, [&] { return e->stop || !e->setup_q.empty(); });
+      if (e->stop) return;
+      r = e->setup_q.front();
+      e->setup_q.pop_front();
+    }
+    hz_options o = e->opt;
+    o.timing = 0;
+    hz_status stt = hz_create_problem(r->k, r->h, r->p, hz_c64{r->s.real(), r->s.imag()}, &o, st, &r->pr);
+    if (stt == HZ_OK) {
+      try {
+        hz_problem* pr = r->pr;
+        r->ws = make_workspace(1, pr->m, o.prec, pr->N, pr->Nc, 0, true);
+        r->ws->s64 = pr->s64;
+        r->ws->s32 = pr->s32;
+        if (r->F)
+          HZ_HIP(hipMemcpyAsync(r->ws->Fs, r->F, size_t(pr->N) * 16, hipMemcpyDeviceToDevice, st));
+        else
+          launch_planewave(pr->p, pr->n, pr->k, r->theta, pr->gl_t, pr->gl_w, pr->lag, r->ws->Fs, st);
+        HZ_HIP(hipStreamSynchronize(st));
+      } catch (...) {
+        stt = map_exception();
+      }
+    }
+    if (stt != HZ_OK) {
+      r->status = stt;
+      r->err = hz_last_error();
+      engine_finish(e, r, nullptr);
+      continue;
+    }
+    {
+      std::lock_guard<std::mutex> g(e->mu);
+      e->used -= r->bytes_setup - r->bytes;      // transient setup memory returned
+      r->setup_done = true;
+      e->ready.push_back(r);
+    }
+    e->cv_work.notify_all();
+  }
+}
+
+// Admits queued requests in arrival order while a slot and the memory budget allow.
+void engine_admit(hz_engine* e) {
+  while (!e->pending.empty() && e->admitted < e->cfg.max_active) {
+    EngineRequest* r = e->pending.front();
+    if (e->used + r->bytes_setup > e->cfg.hbm_budget && e->admitted > 0) break;
+    e->pending.pop_front();
+    r->admitted = true;
+    r->t_admit = clk::now();
+    e->used += r->bytes_setup;
+    e->admitted += 1;
+    e->setup_q.push_back(r);
+    e->cv_setup.notify_one();
+  }
+}
+
+// Loop thread: every round performs one Arnoldi step of each active request (all on one
+// stream: the coarse solves are cooperative launches and must not run concurrently with
+// each other), synchronises once, then updates every request on the host; finished requests
+// leave and free their memory, new ones join between rounds.
+void engine_loop_main(hz_engine* e) {
+  (void)hipSetDevice(e->device);
+  hipStream_t st = e->st_solve;
+  std::vector<EngineRequest*> joining;
+  while (true) {
+    {
+      std::unique_lock<std::mutex> g(e->mu);
+      engine_admit(e);
+      if (e->active.empty())
+        e->cv_work.wait(g, [&] {
+          engine_admit(e);
+          return e->stop || !e->ready.empty();
+        });
+      if (e->stop) return;
+      joining.assign(e->ready.begin(), e->ready.end());
+      e->ready.clear();
+    }
+    for (EngineRequest* r : joining) {
+      r->t_start = clk::now();
+      r->probs[0] = r->pr;
+      hz_options o = e->opt;
+      r->ls.reset(new Lockstep(r->probs, 1, 1, r->ws->Fs, &r->off0, r->u, &r->off0, *r->ws, o));
+      hz_status stt;
+      try {
+        stt = r->ls->start(nullptr, st);
+      } catch (...) {
+        stt = map_exception();
+      }
+      if (stt != HZ_OK) {
+        r->status = stt;
+        r->err = hz_last_error();
+        engine_finish(e, r, nullptr);
+        continue;
+      }
+      e->active.push_back(r);
+    }
+    joining.clear();
+    std::vector<EngineRequest*> failed;
+    try {
+      for (EngineRequest* r : e->active) r->ls->issue(st);
+      HZ_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      const hz_status stt = map_exception();
+      for (EngineRequest* r : e->active) {
+        r->status = stt;
+        r->err = hz_last_error();
+        engine_finish(e, r, nullptr);
+      }
+      e->active.clear();
+      continue;
+    }
+    std::vector<EngineRequest*> keep;
+    for (EngineRequest* r : e->active) {
+      hz_status stt;
+      try {
+        stt = r->ls->complete(st);
+        if (stt == HZ_OK && r->ls->finished()) stt = r->ls->check_device();
+      } catch (...) {
+        stt = map_exception();
+      }
+      if (stt != HZ_OK) {
+        r->status = stt;
+        r->err = hz_last_error();
+        engine_finish(e, r, nullptr);
+        continue;
+      }
+      if (r->ls->finished()) {
+        hz_result res;
+        r->ls->results(&res);
+        res.solve_s = std::chrono::duration<double>(clk::now() - r->t_start).count();
+        engine_finish(e, r, &res);
+        continue;
+      }
+      keep.push_back(r);
+    }
+    e->active.swap(keep);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+hz_status hz_engine_default_config(hz_engine_config* c) {
+  if (!c) return fail(HZ_EINVAL, "null config");
+  c->hbm_budget = 0;
+  c->max_active = 64;
+  c->setup_threads = 2;
+  return HZ_OK;
+}
+
+hz_status hz_engine_create(const hz_engine_config* c, const hz_options* o, hz_engine** out) {
+  if (!out) return fail(HZ_EINVAL, "null output pointer");
+  *out = nullptr;
+  hz_engine_config cfg;
+  hz_engine_default_config(&cfg);
+  if (c) cfg = *c;
+  hz_options opt;
+  hz_default_options(&opt);
+  if (o) opt = *o;
+  std::string why;
+  if (!valid_options(opt, why)) return fail(HZ_EINVAL, why);
+  if (cfg.max_active < 1 || cfg.max_active > 1024) return fail(HZ_EINVAL, "max_active must be in [1, 1024]");
+  if (cfg.setup_threads < 1 || cfg.setup_threads > 8) return fail(HZ_EINVAL, "setup_threads must be in [1, 8]");
+  hz_engine* e = nullptr;
+  try {
+    e = new hz_engine();
+    e->opt = opt;
+    HZ_HIP(hipGetDevice(&e->device));
+    if (cfg.hbm_budget == 0) {
+      size_t fr = 0, tot = 0;
+      HZ_HIP(hipMemGetInfo(&fr, &tot));
+      cfg.hbm_budget = size_t(0.85 * double(fr));
+    }
+    e->cfg = cfg;
+    HZ_HIP(hipStreamCreateWithFlags(&e->st_solve, hipStreamNonBlocking));
+    e->st_setup.resize(cfg.setup_threads);
+    for (auto& s : e->st_setup) HZ_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    e->loop = std::thread(engine_loop_main, e);
+    e->reaper = std::thread(engine_reaper_main, e);
+    for (int i = 0; i < cfg.setup_threads; ++i) e->setup.emplace_back(engine_setup_main, e, i);
+    *out = e;
+    return HZ_OK;
+  } catch (...) {
+    const hz_status stt = map_exception();
+    if (e) hz_engine_destroy(e);
+    return stt;
+  }
+}
+
+hz_status hz_engine_submit(hz_engine* e, double k, double h, int p, hz_c64 s, double theta,
+                           const hz_c64* d_F, hz_c64* d_u, long req_id) {
+  if (!e || !d_u) return fail(HZ_EINVAL, "null argument");
+  int n = 0;
+  std::string why;
+  const cd sc(s.re, s.im);
+  if (!valid_problem(k, h, p, sc, n, why)) return fail(HZ_EINVAL, why);
+  if (!d_F && !std::isfinite(theta)) return fail(HZ_EINVAL, "theta must be finite");
+  std::unique_ptr<EngineRequest> r(new EngineRequest());
+  r->id = req_id;
+  r->k = k; r->h = h; r->p = p; r->s = sc; r->theta = theta;
+  r->F = reinterpret_cast<const double2*>(d_F);
+  r->u = reinterpret_cast<double2*>(d_u);
+  r->bytes = request_bytes(n, p, e->opt.restart, e->opt.prec, &r->bytes_setup);
+  if (r->bytes_setup > e->cfg.hbm_budget)
+    return fail(HZ_ENOMEM, "request needs more device memory than the engine budget");
+  r->t_submit = clk::now();
+  {
+    std::lock_guard<std::mutex> g(e->mu);
+    if (e->stop) return fail(HZ_EBUSY, "engine is shutting down");
+    e->pending.push_back(r.release());
+    e->submitted += 1;
+  }
+  e->cv_work.notify_all();
+  return HZ_OK;
+}
+
+hz_status hz_engine_poll(hz_engine* e, hz_engine_result* out, int max, int* ndone, int wait_ms) {
+  if (!e || !ndone || (max > 0 && !out)) return fail(HZ_EINVAL, "null argument");
+  std::unique_lock<std::mutex> g(e->mu);
+  if (e->done.empty() && wait_ms > 0)
+    e->cv_done.wait_for(g, std::chrono::milliseconds(wait_ms), [&] { return !e->done.empty(); });
+  int k = 0;
+  while (k < max && !e->done.empty()) {
+    out[k++] = e->done.front();
+    e->done.pop_front();
+  }
+  *ndone = k;
+  return HZ_OK;
+}
+
+hz_status hz_engine_info(hz_engine* e, hz_engine_info_t* info) {
+  if (!e || !info) return fail(HZ_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(e->mu);
+  info->queued = int(e->pending.size());
+  info->admitted = e->admitted;
+  info->bytes_in_use = e->used;
+  info->hbm_budget = e->cfg.hbm_budget;
+  info->submitted = e->submitted;
+  info->completed = e->completed;
+  return HZ_OK;
+}
+
+void hz_engine_destroy(hz_engine* e) {
+  if (!e) return;
+  {
+    std::lock_guard<std::mutex> g(e->mu);
+    e->stop = true;
+  }
+  e->cv_work.notify_all();
+  e->cv_setup.notify_all();
+  e->cv_trash.notify_all();
+  if (e->loop.joinable()) e->loop.join();
+  for (auto& t : e->setup)
+    if (t.joinable()) t.join();
+  if (e->reaper.joinable()) e->reaper.join();
+  if (e->st_solve) (void)hipStreamSynchronize(e->st_solve);
+  for (auto s : e->st_setup) (void)hipStreamSynchronize(s);
+  delete e;
+}
 
 }  // extern "C"

@@ -53,6 +53,32 @@ class C64(ctypes.Structure):
     _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
 
 
+class EngineConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active", ctypes.c_int),
+                ("setup_threads", ctypes.c_int)]
+
+
+class EngineResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_long), ("status", ctypes.c_int), ("result", Result),
+                ("queue_s", ctypes.c_double), ("latency_s", ctypes.c_double),
+                ("message", ctypes.c_char * 120)]
+
+    def as_dict(self):
+        d = self.result.as_dict()
+        d.update(id=self.id, status=self.status, queue_s=self.queue_s,
+                 latency_s=self.latency_s, message=self.message.decode())
+        return d
+
+
+class EngineInfo(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int), ("admitted", ctypes.c_int),
+                ("bytes_in_use", ctypes.c_size_t), ("hbm_budget", ctypes.c_size_t),
+                ("submitted", ctypes.c_long), ("completed", ctypes.c_long)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _P = ctypes.c_void_p
 _SIGS = {
     "hz_default_options": (ctypes.c_int, [ctypes.POINTER(Options)]),
@@ -73,6 +99,15 @@ _SIGS = {
                                                    ctypes.c_int, ctypes.POINTER(Options)]),
     "hz_problem_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats), ctypes.c_int]),
     "hz_destroy_problem": (None, [_P]),
+    "hz_engine_default_config": (ctypes.c_int, [ctypes.POINTER(EngineConfig)]),
+    "hz_engine_create": (ctypes.c_int, [ctypes.POINTER(EngineConfig), ctypes.POINTER(Options),
+                                        ctypes.POINTER(_P)]),
+    "hz_engine_submit": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int, C64,
+                                        ctypes.c_double, _P, _P, ctypes.c_long]),
+    "hz_engine_poll": (ctypes.c_int, [_P, ctypes.POINTER(EngineResult), ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
+    "hz_engine_info": (ctypes.c_int, [_P, ctypes.POINTER(EngineInfo)]),
+    "hz_engine_destroy": (None, [_P]),
     "hz_last_error": (ctypes.c_char_p, []),
 }
 
@@ -231,3 +266,57 @@ def solve_batched(problems, Fs, nrhs_per_prob, us=None, tol=None, restart=None, 
     _check(lib().hz_solve_batched(P, len(problems), FF, nrhs_per_prob, UU, ctypes.byref(o), res,
                                   _stream()))
     return us, [r.as_dict() for r in res]
+
+
+class Engine:
+    """Serving engine (continuous batching of independent solves, admission by device
+    memory); see hz_engine_* in include/hz.h. Solutions land in complex128 CUDA tensors
+    that the caller provides or that submit() allocates; they are complete once poll()
+    has returned the request."""
+
+    def __init__(self, hbm_budget=0, max_active=64, setup_threads=2, **opts):
+        self.opts = options(**opts)
+        c = EngineConfig()
+        _check(lib().hz_engine_default_config(ctypes.byref(c)))
+        c.hbm_budget, c.max_active, c.setup_threads = int(hbm_budget), max_active, setup_threads
+        self._h = ctypes.c_void_p()
+        _check(lib().hz_engine_create(ctypes.byref(c), ctypes.byref(self.opts), ctypes.byref(self._h)))
+        self._out = {}
+
+    def submit(self, req_id, k, h, p, s, theta=0.0, F=None, u=None):
+        n = int(round(1.0 / h))
+        if u is None:
+            u = torch.empty(sizes(n, p)[1], dtype=torch.complex128, device="cuda")
+        self._out[req_id] = (u, F)
+        _check(lib().hz_engine_submit(self._h, float(k), float(h), int(p),
+                                      C64(complex(s).real, complex(s).imag), float(theta),
+                                      _ptr(F), _ptr(u), int(req_id)))
+        return u
+
+    def poll(self, max_results=256, wait_ms=0):
+        """[(result dict, u tensor)] of finished requests."""
+        buf = (EngineResult * max_results)()
+        n = ctypes.c_int()
+        _check(lib().hz_engine_poll(self._h, buf, max_results, ctypes.byref(n), int(wait_ms)))
+        out = []
+        for i in range(n.value):
+            d = buf[i].as_dict()
+            u, _ = self._out.pop(d["id"], (None, None))
+            out.append((d, u))
+        return out
+
+    def info(self):
+        i = EngineInfo()
+        _check(lib().hz_engine_info(self._h, ctypes.byref(i)))
+        return i.as_dict()
+
+    def close(self):
+        if self._h:
+            lib().hz_engine_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
