@@ -287,12 +287,93 @@ def run_sequential_fp64(count, tol=1e-8, restart=50):
     torch.cuda.set_device(0)
     reqs = inputs.serving_requests(count, seed=1, rate=None)
     t0 = time.perf_counter()
-    for r in reqs:
+    last_log = t0
+    for i, r in enumerate(reqs):
         pr = hz.Problem(r["k"], 1.0 / r["n"], r["p"], 1 + 1j * r["beta"], tol=tol, restart=restart)
         pr.solve(pr.planewave_rhs(r["theta"]), tol=tol, history=False)
         pr.close()
+        if time.perf_counter() - last_log > 20:
+            last_log = time.perf_counter()
+            log(f"  plain fp64: {i + 1}/{len(reqs)} done")
     torch.cuda.synchronize()
     return dict(seconds=time.perf_counter() - t0, solves=len(reqs))
+
+
+def run_precision(cfg, steps, warmup):
+    """FP64 and mixed-precision solves of the same problem on the GPU; the oracle checks both
+    on a reduced mesh of the same resolution (k h / p fixed) where it finishes in seconds."""
+    import torch
+    from paper_2104_01439_amd import hz
+    from oracle import Problem as OProblem
+
+    torch.cuda.set_device(0)
+    k, n, p, s, th, tol = cfg["k"], cfg["n"], cfg["p"], cfg["s"], cfg["theta"], cfg["tol"]
+    out = {}
+    sols = {}
+    for prec in ("fp64", "mixed"):
+        times, its = [], []
+        for i in range(warmup + steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            pr = hz.Problem(k, 1.0 / n, p, s, nu=cfg["nu"], omega=cfg["omega"],
+                            restart=cfg["restart"], tol=tol, prec=prec)
+            u, r = pr.solve(pr.planewave_rhs(th), tol=tol, history=False)
+            torch.cuda.synchronize()
+            if i >= warmup:
+                times.append(time.perf_counter() - t)
+                its.append(r["iterations"])
+            pr.close()
+            log(f"{prec} step {i}: {r['iterations']} iterations, {time.perf_counter() - t:.2f}s")
+        sols[prec] = u
+        out[prec] = {"solves_s": len(times) / sum(times), "iterations": its,
+                     "true_rel_res": r["rel_res_true"]}
+    d = (sols["mixed"] - sols["fp64"]).norm().item() / sols["fp64"].norm().item()
+    out["iteration_delta"] = out["mixed"]["iterations"][0] - out["fp64"]["iterations"][0]
+    out["rel_diff_mixed_vs_fp64"] = d
+    # oracle on the reduced mesh
+    ns = 64
+    ks = k * ns / n
+    op = OProblem(ks, ns, p, s, nu=cfg["nu"], omega=cfg["omega"])
+    F = op.planewave_rhs(th)
+    ro = op.solve(F, tol=tol, m=cfg["restart"])
+    chk = {"k": ks, "n": ns, "p": p, "oracle_iterations": ro["iterations"]}
+    for prec in ("fp64", "mixed"):
+        pr = hz.Problem(ks, 1.0 / ns, p, s, nu=cfg["nu"], omega=cfg["omega"],
+                        restart=cfg["restart"], prec=prec)
+        u, r = pr.solve(torch.from_numpy(F).cuda(), tol=tol, history=False)
+        uo = u.cpu().numpy()
+        chk[prec] = {"iterations": r["iterations"],
+                     "u_rel_err_vs_oracle": float(np.linalg.norm(uo - ro["u"]) / np.linalg.norm(ro["u"]))}
+        pr.close()
+    out["oracle_check"] = chk
+    return out
+
+
+def main_precision(a, cfg):
+    g = run_precision(cfg, a.steps, a.warmup)
+    value = g["mixed"]["solves_s"]
+    out = {
+        "metric": "FGMRES solves/s",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 / value,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-precond/f64-outer",
+        "data": "synthetic plane-wave impedance data",
+        "config": {"workload": cfg["name"], "k": cfg["k"], "n": cfg["n"], "p": cfg["p"],
+                   "shift": str(cfg["s"]), "tol": cfg["tol"], "restart": cfg["restart"],
+                   "nu": cfg["nu"], "omega": cfg["omega"], "precision": "mixed vs fp64"},
+        "precision": g,
+        "speedup_mixed_vs_fp64": value / g["fp64"]["solves_s"],
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def main_serving(a):
@@ -337,7 +418,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="p1_k400_n2048")
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed", "compare"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--requests", type=int, default=200, help="serving: stream prefix length")
     ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per s (0: all at once)")
@@ -352,6 +433,8 @@ def main():
     from paper_2104_01439_amd import inputs
     if a.workload == "serving":
         return main_serving(a)
+    if a.workload == inputs.CFG_MIXED["name"] and a.prec == "compare":
+        return main_precision(a, inputs.CFG_MIXED)
     if a.workload == inputs.CFG_SWEEP["name"]:
         return main_sweep(a, inputs.CFG_SWEEP)
     cfgs = {c["name"]: c for c in (inputs.CFG_SMALL, inputs.CFG_P1_LARGE, inputs.CFG_MIXED)}
