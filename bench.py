@@ -150,8 +150,7 @@ def run_gpu(cfg, steps, warmup, prec):
     launches = sum(x["coarse_solves"] for x in stats)
     cs_ms = sum(x["coarse_solve_ms"] for x in stats) / max(launches, 1)
     factor_ms = sum(x["factor_ms"] for x in stats) / max(len(stats), 1)
-    item = 8 if prec == "mixed" else 16
-    cs_bytes = coarse_solve_bytes(n, p, item)
+    cs_bytes = sum(x["coarse_bytes"] for x in stats) / max(launches, 1)
     return dict(seconds=dt, iterations=its, info=info, coarse_ms=cs_ms, coarse_bytes=cs_bytes,
                 coarse_launches=launches, factor_ms=factor_ms)
 
@@ -234,7 +233,7 @@ def run_sweep(cfg, steps, warmup, prec):
     return dict(seconds=dt, solves=steps * len(betas) * nr, its=its, bstar=bstar,
                 sigma=2 + math.log(bstar) / math.log(k), group=gsize, setup_s=setup_s,
                 coarse_ms=cs_ms, coarse_launches=launches, nrhs_per_launch=nrhs_per_launch,
-                coarse_bytes=coarse_solve_bytes(n, p, item, round(nrhs_per_launch)),
+                coarse_bytes=sum(x["coarse_bytes"] for x in stats) / max(launches, 1),
                 factor_ms=sum(x["factor_ms"] for x in stats) / max(len(stats), 1),
                 betas=betas, thetas=thetas, converged=conv)
 
@@ -496,12 +495,12 @@ def main_sweep(a, cfg):
                    "shifts": len(g["betas"]), "angles": len(g["thetas"]), "tol": cfg["tol"],
                    "restart": cfg["restart"], "nu": cfg["nu"], "omega": cfg["omega"],
                    "precision": a.prec, "shifts_per_batch": g["group"]},
-        "roofline": {"kernel": "coarse block triangular solve, multi-RHS (k_csolve)",
+        "roofline": {"kernel": "coarse block triangular solves, several shifts x RHS per launch (k_csolve)",
                      "bound": "hbm", "achieved": cs_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": cs_gbs / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": g["coarse_bytes"], "avg_launch_ms": g["coarse_ms"],
                      "launches": g["coarse_launches"],
-                     "rhs_per_launch": g["nrhs_per_launch"]},
+                     "solves_per_launch": g["nrhs_per_launch"]},
         "setup_factor_ms": g["factor_ms"],
         "sweep": {"beta_star": g["bstar"], "sigma_star": g["sigma"],
                   "mean_iterations_per_beta": [float(np.mean(x)) for x in g["its"]],

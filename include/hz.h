@@ -81,12 +81,16 @@ typedef struct {
   double solve_s;       /* wall seconds of this solve                                        */
 } hz_result;
 
-/* Device-time counters of one problem (filled when created with timing != 0). */
+/* Counters of one problem (device times filled when created with timing != 0). A batched
+ * solve books the coarse-solve launches of all its problems on its first problem. */
 typedef struct {
   long vcycles;              /* V-cycles run by solves and by hz_apply(HZ_OP_VCYCLE)      */
   long coarse_solves;        /* launches of the coarse block-triangular solve kernel       */
   double coarse_solve_ms;    /* their summed device time (HIP events around each launch)  */
   double factor_ms;          /* device time of the coarse assembly and factorisation       */
+  double coarse_bytes;       /* algorithmic bytes of those launches: each solved system's
+                                factor read twice (last block once) plus 3 coarse vectors
+                                per right-hand side                                         */
 } hz_stats;
 
 /* Operators exposed by hz_apply (parity hooks; all act on the problem's own data). */

@@ -90,6 +90,7 @@ struct Workspace {
   double2* partial = nullptr;   // [cap][nblk][64]
   double2* hbuf = nullptr;      // [cap][192]: CGS2 pass 1, pass 2, |w|^2
   char* dreg = nullptr;         // device copies of the two upload regions
+  void* gb = nullptr;           // [cap][Nc] coarse forward-sweep buffers (per solve)
   Scratch<double> s64;
   Scratch<float> s32;
   double2* pin = nullptr;       // pinned read-back [cap][192]
@@ -252,7 +253,8 @@ Sizes sizes_of(int n, int p) {
 // Bytes of the V-cycle scratch for `cap` right-hand sides.
 size_t scratch_bytes(long N, long Nc, int cap, int prec) {
   const size_t it = prec == HZ_MIXED ? 8 : 16;
-  return size_t(cap) * ((prec == HZ_MIXED ? 4 : 3) * size_t(N) + 2 * size_t(Nc)) * it;
+  return size_t(cap) * ((prec == HZ_MIXED ? 4 : 3) * size_t(N) + 2 * size_t(Nc)) * it +
+         size_t(cap) * Nc * 16;   // forward-sweep buffers
 }
 
 // Bytes of a Krylov workspace for `cap` solves with restart capacity m (staged: with room
@@ -264,7 +266,7 @@ size_t workspace_bytes(long N, int nblk, int cap, int m, int prec, bool staged) 
   b += 2 * size_t(cap) * N * 16;                                // r, w
   if (staged) b += 2 * size_t(cap) * N * 16;                    // F, u
   b += size_t(cap) * (size_t(nblk) * 64 * 16 + 192 * 16 + 64 * 16 + 8);
-  b += 2 * size_t(cap) * (Workspace::kTabs * 8 + 2 * 4 + 8 + 64 * 16) + 4096;
+  b += 2 * size_t(cap) * (Workspace::kTabs * 8 + 2 * 4 + 8 + 3 * 8 + 64 * 16) + 4096;
   return b;
 }
 
@@ -356,25 +358,30 @@ void ensure_apply32(hz_problem* pr) {
 
 // Upload staging of one phase: offset tables, counts, scale factors, Hessenberg solutions.
 struct Region {
-  long* tab;
-  int* itab;
-  double* scl;
-  double2* y;
+  long* tab;        // [kTabs][cap] element offsets
+  int* itab;        // [2][cap] counts
+  double* scl;      // [cap] scale factors
+  const void** ptab;  // [kPtrTabs][cap] per-element operator tables
+  double2* y;       // [cap][64] Hessenberg solutions
 };
+constexpr int kPtrTabs = 3;
 size_t region_bytes(int cap) {
-  const size_t a = size_t(Workspace::kTabs) * cap * 8, b = (size_t(2) * cap * 4 + 15) / 16 * 16;
-  const size_t c = (size_t(cap) * 8 + 15) / 16 * 16;
-  return (a + 15) / 16 * 16 + b + c + size_t(cap) * 64 * 16;
+  auto al = [](size_t b) { return (b + 15) / 16 * 16; };
+  return al(size_t(Workspace::kTabs) * cap * 8) + al(size_t(2) * cap * 4) + al(size_t(cap) * 8) +
+         al(size_t(kPtrTabs) * cap * 8) + size_t(cap) * 64 * 16;
 }
 Region region_at(char* base, int cap) {
+  auto al = [](size_t b) { return (b + 15) / 16 * 16; };
   Region r;
   size_t o = 0;
   r.tab = reinterpret_cast<long*>(base + o);
-  o += (size_t(Workspace::kTabs) * cap * 8 + 15) / 16 * 16;
+  o += al(size_t(Workspace::kTabs) * cap * 8);
   r.itab = reinterpret_cast<int*>(base + o);
-  o += (size_t(2) * cap * 4 + 15) / 16 * 16;
+  o += al(size_t(2) * cap * 4);
   r.scl = reinterpret_cast<double*>(base + o);
-  o += (size_t(cap) * 8 + 15) / 16 * 16;
+  o += al(size_t(cap) * 8);
+  r.ptab = reinterpret_cast<const void**>(base + o);
+  o += al(size_t(kPtrTabs) * cap * 8);
   r.y = reinterpret_cast<double2*>(base + o);
   return r;
 }
@@ -399,6 +406,7 @@ std::unique_ptr<Workspace> make_workspace(int cap, int m, int prec, long N, long
   if (rcap > 0) {
     if (prec == HZ_MIXED) alloc_scratch<float>(w->mem, w->s32, rcap, N, Nc, true);
     else alloc_scratch<double>(w->mem, w->s64, rcap, N, Nc, false);
+    w->gb = w->mem.alloc<double2>(size_t(rcap) * Nc);
   }
   HZ_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->pin), size_t(cap) * 192 * 16, hipHostMallocDefault));
   HZ_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->up), 2 * w->up_bytes, hipHostMallocDefault));
@@ -455,59 +463,124 @@ void collect_timing(hz_problem* pr, bool wait) {
   pr->ev_pending.swap(keep);
 }
 
-template <typename T>
-void timed_coarse_solve(hz_problem* pr, const Level<T>& lv, const V2<T>* b, V2<T>* y, int nrhs,
-                        hipStream_t st) {
-  if (!pr->timing) {
-    pr->stats.coarse_solves += coarse_solve<T>(pr->L, lv.coarse, lv.S, b, y, nrhs, pr->Nc, lv.cw, st);
-    return;
-  }
-  auto e = take_events(pr);
-  HZ_HIP(hipEventRecord(e.first, st));
-  pr->stats.coarse_solves += coarse_solve<T>(pr->L, lv.coarse, lv.S, b, y, nrhs, pr->Nc, lv.cw, st);
-  HZ_HIP(hipEventRecord(e.second, st));
-  pr->ev_pending.push_back(e);
-  if (pr->ev_pending.size() > 64) collect_timing(pr, true);
+// Algorithmic bytes of one coarse solve job: the stored factor read twice (the last block
+// once) plus, per right-hand side, the coarse vector read and the solution written and
+// re-read.
+double csolve_job_bytes(const CoarseLayout& L, size_t item, int nrhs) {
+  const double mc2 = double(L.Mc) * L.Mc;
+  return (2.0 * double(L.total()) - mc2) * item + 3.0 * mc2 * item * nrhs;
 }
 
-// One twogrid V(nu, nu)-cycle from a zero initial guess (Algorithm 1, two levels) for nb
-// right-hand sides at once: nu damped Jacobi sweeps, r_c = P^T (f - A_eps u),
-// e_c = A_c^{-1} r_c, u += P e_c, nu sweeps. Input b at f + af.at(b), output at z + az.at(b);
-// the iterates live in the level's scratch (stride N, coarse stride Nc).
+// Coarse solves of jobs (timed with HIP events on the stream when the first problem was
+// created with timing; counters accumulate in that problem).
 template <typename T>
-void vcycle(hz_problem* pr, const Level<T>& lv, int nu, const V2<T>* f, Addr af, V2<T>* z,
-            Addr az, int nb, hipStream_t st) {
-  pr->stats.vcycles += nb;
-  const int p = pr->p;
-  const long N = pr->N, Nc = pr->Nc;
-  const Scratch<T>& sc = lv.sc;
+void timed_coarse_jobs(hz_problem* pr, const CoarseJob<T>* jobs, int njobs, hipStream_t st) {
+  double bytes = 0;
+  for (int i = 0; i < njobs; ++i) bytes += csolve_job_bytes(pr->L, sizeof(V2<T>), jobs[i].nrhs);
+  std::pair<hipEvent_t, hipEvent_t> e{};
+  if (pr->timing) {
+    e = take_events(pr);
+    HZ_HIP(hipEventRecord(e.first, st));
+  }
+  pr->stats.coarse_solves += coarse_solve_jobs<T>(pr->L, jobs, njobs, pr->Nc, pr->cw.err,
+                                                  pr->cw.persistent, st);
+  pr->stats.coarse_bytes += bytes;
+  if (pr->timing) {
+    HZ_HIP(hipEventRecord(e.second, st));
+    pr->ev_pending.push_back(e);
+    if (pr->ev_pending.size() > 64) collect_timing(pr, true);
+  }
+}
+
+template <typename T> const V2<T>* factor_of(const hz_problem* pr);
+template <> const double2* factor_of<double>(const hz_problem* pr) { return pr->S; }
+template <> const float2* factor_of<float>(const hz_problem* pr) { return pr->Sf; }
+template <typename T> const V2<T>* coarse_coef_of(const hz_problem* pr);
+template <> const double2* coarse_coef_of<double>(const hz_problem* pr) { return pr->cAc; }
+template <> const float2* coarse_coef_of<float>(const hz_problem* pr) { return pr->fcAc; }
+
+// One twogrid V(nu, nu)-cycle from a zero initial guess (Algorithm 1, two levels) for nb
+// solves of one mesh class at once: nu damped Jacobi sweeps, r_c = P^T (f - A_eps u),
+// e_c = A_c^{-1} r_c, u += P e_c, nu sweeps. Solve b uses problem probs[zp[b]] (consecutive
+// solves of one problem form one coarse job of up to 4 right-hand sides), input f + af.at(b),
+// output z + az.at(b); fine gives the per-solve operators. The iterates live in scratch
+// (stride N, coarse stride Nc); gb holds nb coarse forward-sweep buffers (stride Nc).
+template <typename T>
+void vcycle_group(hz_problem* const* probs, const int* zp, int nb, const DevOp<T>& fine,
+                  const T* rw, const Scratch<T>& sc, V2<T>* gb, const V2<T>* f, Addr af,
+                  V2<T>* z, Addr az, hipStream_t st) {
+  hz_problem* pr0 = probs[zp[0]];
+  const int p = pr0->p, nu = pr0->opt.nu;
+  const long N = pr0->N, Nc = pr0->Nc;
   if (nb > sc.cap) throw std::runtime_error("V-cycle batch exceeds its scratch");
+  // coarse jobs: runs of solves of one problem, at most the LDS group size per job
+  const int grp = coarse_group<T>(pr0->L);
+  std::vector<CoarseJob<T>> jobs;
+  for (int b0 = 0; b0 < nb;) {
+    int b1 = b0;
+    while (b1 < nb && zp[b1] == zp[b0] && b1 - b0 < grp) ++b1;
+    hz_problem* pi = probs[zp[b0]];
+    pi->stats.vcycles += b1 - b0;
+    CoarseJob<T> j;
+    j.S = factor_of<T>(pi);
+    j.coef = coarse_coef_of<T>(pi);
+    j.b = sc.rc + b0 * Nc;
+    j.y = sc.ec + b0 * Nc;
+    j.gbuf = gb + b0 * Nc;
+    j.nrhs = b1 - b0;
+    jobs.push_back(j);
+    b0 = b1;
+  }
   if (nu == 0) {
     // u = 0: the cycle is the coarse correction alone, z = P A_c^{-1} P^T f
-    launch_restrict<T>(p, pr->M, pr->Mc, lv.rw, f, sc.rc, nb, af, Addr(Nc), st);
-    timed_coarse_solve<T>(pr, lv, sc.rc, sc.ec, nb, st);
-    launch_prolong<T>(p, pr->M, pr->Mc, lv.rw, sc.ec, z, false, nb, az, Addr(Nc), st);
+    launch_restrict<T>(p, pr0->M, pr0->Mc, rw, f, sc.rc, nb, af, Addr(Nc), st);
+    timed_coarse_jobs<T>(pr0, jobs.data(), int(jobs.size()), st);
+    launch_prolong<T>(p, pr0->M, pr0->Mc, rw, sc.ec, z, false, nb, az, Addr(Nc), st);
     return;
   }
   V2<T>* cur = sc.ua;
   V2<T>* nxt = sc.ub;
-  launch_jacobi0<T, T>(p, lv.fine, f, af, cur, Addr(N), nb, st);
+  launch_jacobi0<T, T>(p, fine, f, af, cur, Addr(N), nb, st);
   for (int sw = 1; sw < nu; ++sw) {
-    launch_stencil<T, T, T, T>(p, ST_SMOOTH, lv.fine, cur, Addr(N), f, af, nxt, Addr(N), nb, st);
+    launch_stencil<T, T, T, T>(p, ST_SMOOTH, fine, cur, Addr(N), f, af, nxt, Addr(N), nb, st);
     std::swap(cur, nxt);
   }
-  launch_stencil<T, T, T, T>(p, ST_RESID, lv.fine, cur, Addr(N), f, af, sc.rf, Addr(N), nb, st);
-  launch_restrict<T>(p, pr->M, pr->Mc, lv.rw, sc.rf, sc.rc, nb, Addr(N), Addr(Nc), st);
-  timed_coarse_solve<T>(pr, lv, sc.rc, sc.ec, nb, st);
-  launch_prolong<T>(p, pr->M, pr->Mc, lv.rw, sc.ec, cur, true, nb, Addr(N), Addr(Nc), st);
+  launch_stencil<T, T, T, T>(p, ST_RESID, fine, cur, Addr(N), f, af, sc.rf, Addr(N), nb, st);
+  launch_restrict<T>(p, pr0->M, pr0->Mc, rw, sc.rf, sc.rc, nb, Addr(N), Addr(Nc), st);
+  timed_coarse_jobs<T>(pr0, jobs.data(), int(jobs.size()), st);
+  launch_prolong<T>(p, pr0->M, pr0->Mc, rw, sc.ec, cur, true, nb, Addr(N), Addr(Nc), st);
   for (int sw = 0; sw < nu; ++sw) {
     if (sw == nu - 1) {
-      launch_stencil<T, T, T, T>(p, ST_SMOOTH, lv.fine, cur, Addr(N), f, af, z, az, nb, st);
+      launch_stencil<T, T, T, T>(p, ST_SMOOTH, fine, cur, Addr(N), f, af, z, az, nb, st);
     } else {
-      launch_stencil<T, T, T, T>(p, ST_SMOOTH, lv.fine, cur, Addr(N), f, af, nxt, Addr(N), nb, st);
+      launch_stencil<T, T, T, T>(p, ST_SMOOTH, fine, cur, Addr(N), f, af, nxt, Addr(N), nb, st);
       std::swap(cur, nxt);
     }
   }
+}
+
+// Single-problem forms used by hz_apply.
+template <typename T>
+void vcycle(hz_problem* pr, const Level<T>& lv, int nu, const V2<T>* f, Addr af, V2<T>* z,
+            Addr az, int nb, hipStream_t st) {
+  (void)nu;
+  hz_problem* const probs[1] = {pr};
+  const int zp[1] = {0};
+  vcycle_group<T>(probs, zp, nb, lv.fine, lv.rw, lv.sc, reinterpret_cast<V2<T>*>(pr->cw.g), f,
+                  af, z, az, st);
+}
+template <typename T>
+void timed_coarse_solve(hz_problem* pr, const Level<T>& lv, const V2<T>* b, V2<T>* y, int nrhs,
+                        hipStream_t st) {
+  (void)nrhs;
+  CoarseJob<T> j;
+  j.S = lv.S;
+  j.coef = lv.coarse.coef;
+  j.b = b;
+  j.y = y;
+  j.gbuf = reinterpret_cast<V2<T>*>(pr->cw.g);
+  j.nrhs = 1;
+  timed_coarse_jobs<T>(pr, &j, 1, st);
 }
 
 // Complex Givens rotation with c real: [c s; -conj(s) c] [a; b] = [r; 0].
@@ -558,7 +631,7 @@ struct Lockstep {
   Workspace* ws = nullptr;
   hz_options o{};
   std::vector<SolveState> S;
-  std::vector<int> act, end;
+  std::vector<int> act, end, zp;
   std::vector<cd> y;
   clk::time_point t0;
   bool issued = false;
@@ -662,6 +735,15 @@ struct Lockstep {
       h.scl[z] = x.scale;
       maxnv = std::max(maxnv, x.j + 1);
     }
+    // per-solve operators: fine A_eps (coefficients, Jacobi multipliers) and A_0
+    zp.resize(na);
+    for (int z = 0; z < na; ++z) {
+      const hz_problem* pz = probs[S[act[z]].prob];
+      zp[z] = S[act[z]].prob;
+      h.ptab[z] = mixed ? static_cast<const void*>(pz->fcAe) : static_cast<const void*>(pz->cAe);
+      h.ptab[cap + z] = mixed ? static_cast<const void*>(pz->fwdAe) : static_cast<const void*>(pz->wdAe);
+      h.ptab[2 * cap + z] = pz->cA0;
+    }
     upload(0, st);
     const long* d_src = d.tab;
     const long* d_vj = d.tab + cap;
@@ -670,37 +752,28 @@ struct Lockstep {
     const long* d_w = d.tab + 4 * cap;
     // v_j = r / beta (cycle start) or w / h_{j,j-1}
     launch_scale_b(ws->RW, Addr(0, d_src), d.scl, ws->V, Addr(0, d_vj), N, na, st);
-    // z_j = V-cycle(v_j), then w = A_0 z_j: one batch per problem (its unfinished
-    // right-hand sides)
-    for (int z0 = 0; z0 < na;) {
-      const int i = S[act[z0]].prob;
-      int z1 = z0;
-      while (z1 < na && S[act[z1]].prob == i) ++z1;
-      hz_problem* pi = probs[i];
-      const int nb = z1 - z0;
-      if (!mixed) {
-        vcycle<double>(pi, level64(pi, ws->s64), pi->opt.nu, ws->V, Addr(0, d_vj + z0), ws->Zd,
-                       Addr(0, d_zj + z0), nb, st);
-      } else {
-        launch_d2f_b(ws->V, Addr(0, d_vj + z0), ws->s32.ff, Addr(N), N, nb, st);
-        vcycle<float>(pi, level32(pi, ws->s32), pi->opt.nu, ws->s32.ff, Addr(N), ws->Zf,
-                      Addr(0, d_zj + z0), nb, st);
-      }
-      z0 = z1;
-    }
-    if (shared_a0()) {
-      const DevOp<double> a0{probs[0]->cA0, nullptr, probs[0]->M};
-      apply_a0(a0, p, Addr(0, d_zj), Addr(0, d_w), na, st);
+    // z_j = V-cycle(v_j) for every unfinished solve at once
+    hz_problem* pr0 = probs[zp[0]];
+    if (!mixed) {
+      DevOp<double> fine{nullptr, nullptr, pr0->M,
+                         reinterpret_cast<const double2* const*>(d.ptab),
+                         reinterpret_cast<const double2* const*>(d.ptab + cap)};
+      vcycle_group<double>(probs, zp.data(), na, fine, pr0->rw, ws->s64,
+                           static_cast<double2*>(ws->gb), ws->V, Addr(0, d_vj), ws->Zd,
+                           Addr(0, d_zj), st);
     } else {
-      for (int z0 = 0; z0 < na;) {
-        const int i = S[act[z0]].prob;
-        int z1 = z0;
-        while (z1 < na && S[act[z1]].prob == i) ++z1;
-        const DevOp<double> a0{probs[i]->cA0, nullptr, probs[i]->M};
-        apply_a0(a0, p, Addr(0, d_zj + z0), Addr(0, d_w + z0), z1 - z0, st);
-        z0 = z1;
-      }
+      DevOp<float> fine{nullptr, nullptr, pr0->M,
+                        reinterpret_cast<const float2* const*>(d.ptab),
+                        reinterpret_cast<const float2* const*>(d.ptab + cap)};
+      launch_d2f_b(ws->V, Addr(0, d_vj), ws->s32.ff, Addr(N), N, na, st);
+      vcycle_group<float>(probs, zp.data(), na, fine, pr0->frw, ws->s32,
+                          static_cast<float2*>(ws->gb), ws->s32.ff, Addr(N), ws->Zf,
+                          Addr(0, d_zj), st);
     }
+    // w = A_0 z_j
+    const DevOp<double> a0{nullptr, nullptr, pr0->M, reinterpret_cast<const double2* const*>(d.ptab + 2 * cap),
+                           nullptr};
+    apply_a0(a0, p, Addr(0, d_zj), Addr(0, d_w), na, st);
     // CGS2: two passes of h = V^H w, w -= V h; then |w|^2
     launch_mdot_b(ws->V, Addr(0, d_vb), N, 64, d.itab, ws->RW, Addr(0, d_w), N, ws->partial, nblk, na, st);
     launch_reduce_b(ws->partial, nblk, maxnv, d.itab, ws->hbuf, 192, na, st);
@@ -715,11 +788,6 @@ struct Lockstep {
     return true;
   }
 
-  bool shared_a0() const {
-    for (int i = 1; i < nprob; ++i)
-      if (probs[i]->k != probs[0]->k) return false;
-    return true;
-  }
   void apply_a0(const DevOp<double>& a0, int p, Addr az, Addr aw, int nb, hipStream_t st) {
     if (o.prec != HZ_MIXED)
       launch_stencil<double, double, double, double>(p, ST_APPLY, a0, ws->Zd, az, nullptr, Addr(),
@@ -793,6 +861,7 @@ struct Lockstep {
       h2.tab[2 * cap + e] = foff[q];
       h2.tab[3 * cap + e] = q * N;
       h2.itab[e] = jend;
+      h2.ptab[e] = probs[x.prob]->cA0;
     }
     upload(1, st);
     if (!mixed)
@@ -801,17 +870,14 @@ struct Lockstep {
     else
       launch_update_b<float>(ws->Zf, Addr(0, d2.tab), N, 64, d2.itab, d2.y, 64, Ub,
                              Addr(0, d2.tab + cap), N, ne, st);
-    for (int e0 = 0; e0 < ne;) {
-      // r = F - A_0 u, one launch per run of solves of one wavenumber
-      const int i = S[end[e0]].prob;
-      int e1 = e0;
-      while (e1 < ne && (shared_a0() || S[end[e1]].prob == i)) ++e1;
-      const DevOp<double> a0{probs[i]->cA0, nullptr, probs[i]->M};
+    // r = F - A_0 u (each solve with its own A_0)
+    {
+      const DevOp<double> a0{nullptr, nullptr, probs[0]->M,
+                             reinterpret_cast<const double2* const*>(d2.ptab), nullptr};
       launch_stencil<double, double, double, double>(probs[0]->p, ST_RESID, a0, Ub,
-                                                     Addr(0, d2.tab + cap + e0), Fb,
-                                                     Addr(0, d2.tab + 2 * cap + e0), ws->RW,
-                                                     Addr(0, d2.tab + 3 * cap + e0), e1 - e0, st);
-      e0 = e1;
+                                                     Addr(0, d2.tab + cap), Fb,
+                                                     Addr(0, d2.tab + 2 * cap), ws->RW,
+                                                     Addr(0, d2.tab + 3 * cap), ne, st);
     }
     launch_mdot_b(ws->RW, Addr(0, d2.tab + 3 * cap), 0, 1, nullptr, ws->RW, Addr(0, d2.tab + 3 * cap),
                   N, ws->partial, ws->nblk, ne, st);
@@ -895,6 +961,7 @@ hz_status solve_impl(hz_problem* pr, const double2* F, double2* u, const hz_opti
     pr->ws1 = make_workspace(1, pr->m, o.prec, pr->N, pr->Nc, 0, false);
     pr->ws1->s64 = pr->s64;
     pr->ws1->s32 = pr->s32;
+    pr->ws1->gb = pr->cw.g;
   }
   const long off = 0;
   hz_problem* const probs[1] = {pr};
@@ -1148,6 +1215,8 @@ hz_status hz_solve_batched(hz_problem* const* probs, int nprob, const hz_c64* co
     if (!probs[i]) return fail(HZ_EINVAL, "null problem");
     if (probs[i]->n != probs[0]->n || probs[i]->p != probs[0]->p)
       return fail(HZ_EINVAL, "batched problems must share (h, p)");
+    if (probs[i]->opt.nu != probs[0]->opt.nu)
+      return fail(HZ_EINVAL, "batched problems must share nu");
     for (int i2 = 0; i2 < i; ++i2)
       if (probs[i2] == probs[i]) return fail(HZ_EINVAL, "a problem appears twice in the batch");
   }
@@ -1177,7 +1246,7 @@ hz_status hz_solve_batched(hz_problem* const* probs, int nprob, const hz_c64* co
       if (opt.prec == HZ_MIXED) ensure_mixed_work(probs[i], st);
     const long N = pr0->N;
     std::unique_ptr<Workspace> ws =
-        make_workspace(int(nsol), opt.restart, opt.prec, N, pr0->Nc, nrhs_per_prob, true);
+        make_workspace(int(nsol), opt.restart, opt.prec, N, pr0->Nc, int(nsol), true);
     std::vector<long> off(nsol);
     for (long q = 0; q < nsol; ++q) {
       off[q] = q * N;
@@ -1207,7 +1276,7 @@ size_t hz_batch_workspace_bytes(double h, int p, int nprob, int nrhs_per_prob, c
   const Sizes z = sizes_of(n, p);
   const int nsol = nprob * nrhs_per_prob;
   return workspace_bytes(z.N, z.nblk, nsol, oo.restart, oo.prec, true) +
-         scratch_bytes(z.N, z.Nc, nrhs_per_prob, oo.prec);
+         scratch_bytes(z.N, z.Nc, nsol, oo.prec);
 }
 
 hz_status hz_problem_stats(hz_problem* pr, hz_stats* out, int reset) {
@@ -1369,6 +1438,7 @@ void engine_setup_main(hz_engine* e, int tid) {
         r->ws = make_workspace(1, pr->m, o.prec, pr->N, pr->Nc, 0, true);
         r->ws->s64 = pr->s64;
         r->ws->s32 = pr->s32;
+        r->ws->gb = pr->cw.g;
         if (r->F)
           HZ_HIP(hipMemcpyAsync(r->ws->Fs, r->F, size_t(pr->N) * 16, hipMemcpyDeviceToDevice, st));
         else

@@ -346,15 +346,19 @@ template <typename T> __device__ __forceinline__ bool is_sentinel(T v) {
   return __builtin_bit_cast(typename Sentinel<T>::U, v) == Sentinel<T>::bits;
 }
 
-template <typename T> __global__ void k_fill_sentinel(V2<T>* a, long n, long stride, int nrhs) {
+// Result buffers of every job start as sentinels: gbuf (stride n) and y (stride cstride).
+template <typename T>
+__global__ void k_fill_sentinel(CsJobs<T> jobs, long n, long cstride) {
   const long i = long(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n) return;
+  const CoarseJob<T>* job = &jobs.j[blockIdx.y];
   const T sv = __builtin_bit_cast(T, Sentinel<T>::bits);
-  for (int h = 0; h < nrhs; ++h) {
-    V2<T> v;
-    v.x = sv;
-    v.y = sv;
-    a[h * stride + i] = v;
+  V2<T> v;
+  v.x = sv;
+  v.y = sv;
+  for (int h = 0; h < job->nrhs; ++h) {
+    job->gbuf[h * n + i] = v;
+    job->y[h * cstride + i] = v;
   }
 }
 
@@ -498,9 +502,17 @@ constexpr int CSOL_CG = 2, CSOL_RG = 3, CSOL_RW = 3, CSOL_QW = 9;
 
 template <int P, typename T, int NR>
 __global__ void __launch_bounds__(512)
-k_csolve(int s_begin, int s_end, int nc, int Mc, const V2<T>* __restrict__ coef,
-         const V2<T>* __restrict__ S, const V2<T>* __restrict__ b, V2<T>* __restrict__ y,
-         V2<T>* __restrict__ gbuf, int nrhs, long cstride, int* __restrict__ err) {
+k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cstride,
+         int* __restrict__ err) {
+  // workgroups [jb Gp, (jb + 1) Gp) serve job jb (one coarse system and its right-hand sides)
+  const int jb = blockIdx.x / Gp;
+  const CoarseJob<T>* job = &jobs.j[jb];
+  const V2<T>* __restrict__ coef = job->coef;
+  const V2<T>* __restrict__ S = job->S;
+  const V2<T>* __restrict__ b = job->b;
+  V2<T>* __restrict__ y = job->y;
+  V2<T>* __restrict__ gbuf = job->gbuf;
+  const int nrhs = job->nrhs;
   constexpr int W = 2 * P + 1, W2 = W * W, NCOEF = P * P * 9 * W2;
   constexpr int CG = CSOL_CG, RG = CSOL_RG, RW = CSOL_RW, QW = CSOL_QW;
   constexpr int RCH = RG * RW;                 // rows per chunk
@@ -513,7 +525,7 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, const V2<T>* __restrict__ coef,
   V2<T>* buf0 = cl + NCOEF;                    // two [NR][nmax] buffers: t and neighbour
   V2<T>* buf1 = buf0 + NR * nmax;
   __shared__ T red[2][CG][RCH][NR];
-  const int G = gridDim.x, g = blockIdx.x;
+  const int G = Gp, g = blockIdx.x - jb * Gp;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int sw = wave - 2, rg = sw / CG, cg = sw - (sw / CG) * CG;
   const size_t bsz = size_t(P * Mc) * size_t(P * Mc);
@@ -709,8 +721,8 @@ constexpr size_t csolve_lds(int Mc) {
 }
 
 template <int P, typename T, int NR>
-void csolve_launch(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b,
-                   V2<T>* y, int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st) {
+void csolve_launch(const CoarseLayout& L, const CsJobs<T>& jobs, int njobs, long cstride,
+                   int* err, bool allow_persistent, hipStream_t st) {
   auto kern = k_csolve<P, T, NR>;
   const int nb = L.nblocks(), m = nb / 2;
   const int F = std::max(m, nb - 1 - m);
@@ -734,51 +746,53 @@ void csolve_launch(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, c
   int per_cu = 0;
   HZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 512, lds));
   const int max_coresident = per_cu * cus;
-  // two chains, each with Gh workgroups holding R rows of a block (one per compute unit)
+  // each job: two chains of Gh workgroups holding R rows of a block; all jobs together
+  // occupy at most one workgroup per compute unit
   const int n0 = int(L.size(0));
-  const int half = std::max(1, cus / 2);
+  const int half = std::max(1, cus / 2 / njobs);
   const int R = (n0 + half - 1) / half;
   const int Gh = (n0 + R - 1) / R;
-  const int G = 2 * Gh;
-  const bool persistent = coop && w.persistent && max_coresident >= G;
+  int Gp = 2 * Gh;
+  const int G = njobs * Gp;
+  const bool persistent = coop && allow_persistent && max_coresident >= G;
   int s_begin = 0, s_end = nsteps;
-  V2<T>* gbuf = reinterpret_cast<V2<T>*>(w.g);
-  int* err = w.err;
-  int nr = nrhs;
   const long Nc = long(L.Mc) * L.Mc;
   const unsigned fb = unsigned((Nc + 255) / 256);
-  k_fill_sentinel<T><<<fb, 256, 0, st>>>(gbuf, Nc, Nc, nrhs);
-  k_fill_sentinel<T><<<fb, 256, 0, st>>>(y, Nc, cstride, nrhs);
+  k_fill_sentinel<T><<<dim3(fb, njobs), 256, 0, st>>>(jobs, Nc, cstride);
   if (persistent) {
-    void* args[] = {&s_begin, &s_end, (void*)&L.nc, (void*)&L.Mc, (void*)&cop.coef, (void*)&S,
-                    (void*)&b, (void*)&y, &gbuf, &nr, (void*)&cstride, &err};
+    void* args[] = {&s_begin, &s_end, (void*)&L.nc, (void*)&L.Mc, &Gp, (void*)&jobs,
+                    (void*)&cstride, &err};
     HZ_HIP(hipLaunchCooperativeKernel((const void*)kern, dim3(G), dim3(512), args, lds, st));
   } else {
     for (int s = 0; s < nsteps; ++s)
-      kern<<<G, 512, lds, st>>>(s, s + 1, L.nc, L.Mc, cop.coef, S, b, y, gbuf, nrhs, cstride, err);
+      kern<<<G, 512, lds, st>>>(s, s + 1, L.nc, L.Mc, Gp, jobs, cstride, err);
   }
   HZ_HIP(hipGetLastError());
 }
 
-// Right-hand sides go in groups of 4 (each factor read serves the group), or of 2 or 1 where
-// the group's staging does not fit in LDS.
+// Right-hand sides per job: groups of 4 share each factor read, or 2 / 1 where the group's
+// staging does not fit in LDS.
 template <int P, typename T>
-int csolve_p(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b, V2<T>* y,
-             int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st) {
-  if (nrhs == 1) {
-    csolve_launch<P, T, 1>(L, cop, S, b, y, 1, cstride, w, st);
-    return 1;
-  }
-  const int group = csolve_lds<P, T, 4>(L.Mc) <= kLdsPerWorkgroup ? 4
-                    : csolve_lds<P, T, 2>(L.Mc) <= kLdsPerWorkgroup ? 2 : 1;
+int csolve_group(const CoarseLayout& L) {
+  return csolve_lds<P, T, 4>(L.Mc) <= kLdsPerWorkgroup ? 4
+         : csolve_lds<P, T, 2>(L.Mc) <= kLdsPerWorkgroup ? 2 : 1;
+}
+
+template <int P, typename T>
+int csolve_jobs_p(const CoarseLayout& L, const CoarseJob<T>* jobs, int njobs, long cstride,
+                  int* err, bool persistent, hipStream_t st) {
   int launches = 0;
-  for (int r0 = 0; r0 < nrhs; r0 += group) {
-    const int nr = std::min(group, nrhs - r0);
-    const V2<T>* br = b + r0 * cstride;
-    V2<T>* yr = y + r0 * cstride;
-    if (nr == 1) csolve_launch<P, T, 1>(L, cop, S, br, yr, 1, cstride, w, st);
-    else if (nr == 2) csolve_launch<P, T, 2>(L, cop, S, br, yr, 2, cstride, w, st);
-    else csolve_launch<P, T, 4>(L, cop, S, br, yr, nr, cstride, w, st);
+  for (int j0 = 0; j0 < njobs; j0 += kMaxJobs) {
+    const int nj = std::min(kMaxJobs, njobs - j0);
+    CsJobs<T> t{};
+    int nr = 1;
+    for (int i = 0; i < nj; ++i) {
+      t.j[i] = jobs[j0 + i];
+      nr = std::max(nr, jobs[j0 + i].nrhs);
+    }
+    if (nr == 1) csolve_launch<P, T, 1>(L, t, nj, cstride, err, persistent, st);
+    else if (nr == 2) csolve_launch<P, T, 2>(L, t, nj, cstride, err, persistent, st);
+    else csolve_launch<P, T, 4>(L, t, nj, cstride, err, persistent, st);
     ++launches;
   }
   return launches;
@@ -857,13 +871,44 @@ hz_status coarse_factor(const CoarseLayout& L, const DevOp<double>& cop, double2
 }
 
 template <typename T>
+int coarse_group(const CoarseLayout& L) {
+  if (L.p == 1) return csolve_group<1, T>(L);
+  if (L.p == 2) return csolve_group<2, T>(L);
+  return csolve_group<3, T>(L);
+}
+
+template <typename T>
+int coarse_solve_jobs(const CoarseLayout& L, const CoarseJob<T>* jobs, int njobs, long cstride,
+                      int* err, bool persistent, hipStream_t st) {
+  if (njobs < 1) return 0;
+  const int grp = coarse_group<T>(L);
+  for (int i = 0; i < njobs; ++i)
+    if (jobs[i].nrhs < 1 || jobs[i].nrhs > grp) throw std::runtime_error("bad coarse job size");
+  if (L.p == 1) return csolve_jobs_p<1, T>(L, jobs, njobs, cstride, err, persistent, st);
+  if (L.p == 2) return csolve_jobs_p<2, T>(L, jobs, njobs, cstride, err, persistent, st);
+  return csolve_jobs_p<3, T>(L, jobs, njobs, cstride, err, persistent, st);
+}
+
+// One problem, nrhs right-hand sides with stride cstride: jobs of up to the LDS group size,
+// one launch each (the jobs of one problem share its forward-sweep buffer).
+template <typename T>
 int coarse_solve(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b,
                  V2<T>* y, int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st) {
   if (nrhs < 1) return 0;
   if (nrhs > 1 && cstride < long(L.Mc) * L.Mc) throw std::runtime_error("coarse stride too small");
-  if (L.p == 1) return csolve_p<1, T>(L, cop, S, b, y, nrhs, cstride, w, st);
-  if (L.p == 2) return csolve_p<2, T>(L, cop, S, b, y, nrhs, cstride, w, st);
-  return csolve_p<3, T>(L, cop, S, b, y, nrhs, cstride, w, st);
+  const int grp = nrhs == 1 ? 1 : coarse_group<T>(L);
+  int launches = 0;
+  for (int r0 = 0; r0 < nrhs; r0 += grp) {
+    CoarseJob<T> j;
+    j.S = S;
+    j.coef = cop.coef;
+    j.b = b + r0 * cstride;
+    j.y = y + r0 * cstride;
+    j.gbuf = reinterpret_cast<V2<T>*>(w.g);
+    j.nrhs = std::min(grp, nrhs - r0);
+    launches += coarse_solve_jobs<T>(L, &j, 1, cstride, w.err, w.persistent, st);
+  }
+  return launches;
 }
 
 void launch_factor_to_f32(const double2* S, float2* Sf, size_t n, hipStream_t st) {
@@ -877,5 +922,11 @@ template int coarse_solve<double>(const CoarseLayout&, const DevOp<double>&, con
 template int coarse_solve<float>(const CoarseLayout&, const DevOp<float>&, const float2*,
                                  const float2*, float2*, int, long, const CoarseSolveWork&,
                                  hipStream_t);
+template int coarse_solve_jobs<double>(const CoarseLayout&, const CoarseJob<double>*, int, long,
+                                       int*, bool, hipStream_t);
+template int coarse_solve_jobs<float>(const CoarseLayout&, const CoarseJob<float>*, int, long,
+                                      int*, bool, hipStream_t);
+template int coarse_group<double>(const CoarseLayout&);
+template int coarse_group<float>(const CoarseLayout&);
 
 }  // namespace hz

@@ -21,14 +21,16 @@ __device__ __forceinline__ int region(int a, int M) { return a == 0 ? 0 : (a == 
 
 template <int P, typename T, typename TX, typename TF, typename TY, int MODE>
 __global__ void __launch_bounds__(256)
-k_stencil(const V2<T>* __restrict__ coef, const V2<T>* __restrict__ wdinv, int M,
-          const V2<TX>* __restrict__ x, Addr ax, const V2<TF>* __restrict__ f, Addr af,
-          V2<TY>* __restrict__ y, Addr ay) {
+k_stencil(DevOp<T> op, const V2<TX>* __restrict__ x, Addr ax, const V2<TF>* __restrict__ f,
+          Addr af, V2<TY>* __restrict__ y, Addr ay) {
   constexpr int W = 2 * P + 1, W2 = W * W;
   constexpr int LW = P * BX + 2 * P, LH = P * BY + 2 * P;
   __shared__ V2<T> tile[LH][LW];
+  const int M = op.M;
   const int nmac = (M + P - 1) / P;
   const int bz = blockIdx.z;
+  const V2<T>* __restrict__ coef = op.ctab ? op.ctab[bz] : op.coef;
+  const V2<T>* __restrict__ wdinv = op.wtab ? op.wtab[bz] : op.wdinv;
   x += ax.at(bz);
   y += ay.at(bz);
   if (MODE != ST_APPLY) f += af.at(bz);
@@ -124,7 +126,8 @@ k_jacobi0(DevOp<T> op, const V2<TF>* __restrict__ f, Addr af, V2<T>* __restrict_
   const int b = int(i / M), a = int(i - long(b) * M);
   const int cls = (b % P) * P + (a % P);
   const int reg = region(b, M) * 3 + region(a, M);
-  y[ay.at(bz) + i] = cmul<T>(op.wdinv[cls * 9 + reg], cvt<T>(f[af.at(bz) + i]));
+  const V2<T>* wd = op.wtab ? op.wtab[bz] : op.wdinv;
+  y[ay.at(bz) + i] = cmul<T>(wd[cls * 9 + reg], cvt<T>(f[af.at(bz) + i]));
 }
 
 // yc(A, B) = sum over fine points (2A + dx, 2B + dy) of RW[cls(A,B)][dy][dx] r(...)
@@ -265,11 +268,11 @@ void stencil_p(int mode, const DevOp<T>& op, const V2<TX>* x, Addr xs, const V2<
   const int nmac = (op.M + P - 1) / P;
   dim3 grid((nmac + BX - 1) / BX, (nmac + BY - 1) / BY, nbatch);
   if (mode == ST_APPLY)
-    k_stencil<P, T, TX, TF, TY, ST_APPLY><<<grid, 256, 0, st>>>(op.coef, op.wdinv, op.M, x, xs, f, fs, y, ys);
+    k_stencil<P, T, TX, TF, TY, ST_APPLY><<<grid, 256, 0, st>>>(op, x, xs, f, fs, y, ys);
   else if (mode == ST_RESID)
-    k_stencil<P, T, TX, TF, TY, ST_RESID><<<grid, 256, 0, st>>>(op.coef, op.wdinv, op.M, x, xs, f, fs, y, ys);
+    k_stencil<P, T, TX, TF, TY, ST_RESID><<<grid, 256, 0, st>>>(op, x, xs, f, fs, y, ys);
   else
-    k_stencil<P, T, TX, TF, TY, ST_SMOOTH><<<grid, 256, 0, st>>>(op.coef, op.wdinv, op.M, x, xs, f, fs, y, ys);
+    k_stencil<P, T, TX, TF, TY, ST_SMOOTH><<<grid, 256, 0, st>>>(op, x, xs, f, fs, y, ys);
 }
 
 }  // namespace

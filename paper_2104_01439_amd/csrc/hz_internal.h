@@ -63,10 +63,15 @@ struct Addr {
 
 // One level's operator on the device: complex stencil coefficients and the Jacobi
 // multiplier omega / diag(A) per (class, region).
+// A batched launch may give every batch element its own operator (problems of one mesh
+// class with different k or shift): ctab / wtab are then device tables of per-element
+// pointers that replace coef / wdinv.
 template <typename T> struct DevOp {
   const V2<T>* coef = nullptr;   // [p*p*9][(2p+1)^2]
   const V2<T>* wdinv = nullptr;  // [p*p*9]
   int M = 0;                     // lattice points per side
+  const V2<T>* const* ctab = nullptr;
+  const V2<T>* const* wtab = nullptr;
 };
 
 // Coarse block-tridiagonal factor: block j (j < nc) holds lattice rows p j .. p j + p - 1,
@@ -130,6 +135,29 @@ struct CoarseSolveWork {
   int* err = nullptr;        // set to 1 if a wait for another workgroup's data timed out
   bool persistent = true;
 };
+// One coarse system of a multi-problem solve launch: the problem's factor and coarse stencil
+// table, nrhs right-hand sides at b + h cstride, solutions at y + h cstride and a forward-sweep
+// buffer at gbuf + h Nc (distinct per job). Up to kMaxJobs jobs of one mesh class share one
+// launch, each on its own set of workgroups; jobs are passed by value (kernel arguments).
+template <typename T> struct CoarseJob {
+  const V2<T>* S = nullptr;
+  const V2<T>* coef = nullptr;
+  const V2<T>* b = nullptr;
+  V2<T>* y = nullptr;
+  V2<T>* gbuf = nullptr;
+  int nrhs = 1;
+  int pad = 0;
+};
+constexpr int kMaxJobs = 16;
+template <typename T> struct CsJobs {
+  CoarseJob<T> j[kMaxJobs];
+};
+// Largest number of right-hand sides one job may carry for this layout (4, 2 or 1).
+template <typename T> int coarse_group(const CoarseLayout& L);
+// Solves every job (launches of up to kMaxJobs jobs); returns the number of launches.
+template <typename T>
+int coarse_solve_jobs(const CoarseLayout& L, const CoarseJob<T>* jobs, int njobs, long cstride,
+                      int* err, bool persistent, hipStream_t st);
 // Returns the number of solve launches (one reads the factor once for up to 4 right-hand
 // sides when their staging fits in LDS).
 template <typename T>

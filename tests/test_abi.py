@@ -61,11 +61,12 @@ def test_footprint_model(hz):
 def test_batch_workspace_model(hz):
     assert hz.batch_workspace_bytes(1 / 63, 1, 2, 4) == 0
     assert hz.batch_workspace_bytes(1 / 64, 1, 0, 4) == 0
-    # P2 n=512: per solve V (51) + Z (50) + r, w, F, u, FP64
-    N = 1025 ** 2
+    # P2 n=512: per solve V (51) + Z (50) + r, w, F, u, V-cycle scratch (3 fine, 2 coarse
+    # vectors) and a coarse forward-sweep buffer, FP64
+    N, Nc = 1025 ** 2, 513 ** 2
     b = hz.batch_workspace_bytes(1 / 512, 2, 8, 4, prec="fp64")
-    per = (51 + 50 + 4) * N * 16
-    assert 32 * per < b < 32 * per + 4 * 5 * N * 16 + 1e8
+    per = (51 + 50 + 4 + 3) * N * 16 + 3 * Nc * 16
+    assert 32 * per < b < 32 * per + 1e8
     assert hz.batch_workspace_bytes(1 / 512, 2, 8, 4, prec="mixed") < b
     assert hz.batch_workspace_bytes(1 / 512, 2, 8, 4) > hz.batch_workspace_bytes(1 / 512, 2, 4, 4)
 
