@@ -13,6 +13,7 @@
 #include <cstring>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -607,6 +608,7 @@ struct SolveState {
   std::vector<cd> sn;
   double* hist = nullptr;
   int m = 0;
+  clk::time_point t0;
   cd& Hat(int i, int jj) { return H[size_t(i) * m + jj]; }
 };
 
@@ -652,7 +654,7 @@ struct Lockstep {
   }
   void after_sync() {
     for (int i = 0; i < nprob; ++i)
-      if (probs[i]->timing) collect_timing(probs[i], false);
+      if (probs[i] && probs[i]->timing) collect_timing(probs[i], false);
   }
   bool finished() const {
     for (const auto& x : S)
@@ -660,31 +662,47 @@ struct Lockstep {
     return true;
   }
 
-  hz_status start(double* const* hist, hipStream_t st) {
-    t0 = clk::now();
+  // Every solve vacant (finished, nothing to do): a group whose members join later.
+  void init_vacant() {
+    S.assign(nsol, SolveState());
+    for (auto& x : S) x.done = true;
+    y.assign(o.restart, cd(0, 0));
+  }
+
+  // Starts the solves qs[0 .. nq): ||F||, u = 0, r = F (synchronises).
+  hz_status start_slots(const int* qs, int nq, double* const* hist, hipStream_t st) {
     const long N = ws->N, cap = ws->cap;
     const int m = o.restart;
     Region h = region_at(hreg(0), ws->cap);
     const Region d = region_at(dreg(0), ws->cap);
-    for (int q = 0; q < nsol; ++q) { h.tab[q] = foff[q]; h.tab[cap + q] = uoff[q]; }
+    for (int i = 0; i < nq; ++i) {
+      const int q = qs[i];
+      h.tab[i] = foff[q];
+      h.tab[cap + i] = uoff[q];
+      h.tab[2 * cap + i] = long(q) * N;
+    }
     upload(0, st);
     launch_mdot_b(Fb, Addr(0, d.tab), 0, 1, nullptr, Fb, Addr(0, d.tab), N, ws->partial,
-                  ws->nblk, nsol, st);
-    launch_reduce_b(ws->partial, ws->nblk, 1, nullptr, ws->hbuf, 192, nsol, st);
-    launch_fill_zero_b(Ub, Addr(0, d.tab + cap), N, nsol, st);
-    launch_copy_b(Fb, Addr(0, d.tab), ws->RW, Addr(N), N, nsol, st);
-    read_back(nsol, st);
+                  ws->nblk, nq, st);
+    launch_reduce_b(ws->partial, ws->nblk, 1, nullptr, ws->hbuf, 192, nq, st);
+    launch_fill_zero_b(Ub, Addr(0, d.tab + cap), N, nq, st);
+    launch_copy_b(Fb, Addr(0, d.tab), ws->RW, Addr(0, d.tab + 2 * cap), N, nq, st);
+    read_back(nq, st);
     HZ_HIP(hipStreamSynchronize(st));
     after_sync();
-    S.assign(nsol, SolveState());
-    y.assign(m, cd(0, 0));
-    for (int q = 0; q < nsol; ++q) {
-      SolveState& x = S[q];
-      x.prob = q / nrhs;
+    const auto now = clk::now();
+    for (int i = 0; i < nq; ++i) {
+      SolveState& x = S[qs[i]];
+      x = SolveState();
+      x.prob = qs[i] / nrhs;
       x.m = m;
-      x.hist = hist ? hist[q] : nullptr;
-      x.normF = std::sqrt(ws->pin[size_t(q) * 192].x);
-      if (!std::isfinite(x.normF)) return fail(HZ_EINVAL, "right-hand side is not finite");
+      x.t0 = now;
+      x.hist = hist ? hist[qs[i]] : nullptr;
+      x.normF = std::sqrt(ws->pin[size_t(i) * 192].x);
+      if (!std::isfinite(x.normF)) {
+        x.done = true;
+        return fail(HZ_EINVAL, "right-hand side is not finite");
+      }
       x.H.assign(size_t(m + 1) * m, cd(0, 0));
       x.g.assign(m + 1, cd(0, 0));
       x.cs.assign(m, 0.0);
@@ -703,6 +721,20 @@ struct Lockstep {
     return HZ_OK;
   }
 
+  hz_status start(double* const* hist, hipStream_t st) {
+    t0 = clk::now();
+    init_vacant();
+    std::vector<int> all(nsol);
+    for (int q = 0; q < nsol; ++q) all[q] = q;
+    return start_slots(all.data(), nsol, hist, st);
+  }
+
+  // The solve in slot q leaves the group (its slot may be started again).
+  void vacate(int q) {
+    S[q] = SolveState();
+    S[q].done = true;
+  }
+
   // Queues one Arnoldi step of every unfinished solve; false when none is left.
   bool issue(hipStream_t st) {
     act.clear();
@@ -714,7 +746,7 @@ struct Lockstep {
     const bool mixed = o.prec == HZ_MIXED;
     const long N = ws->N, cap = ws->cap;
     const long vstr = long(ws->m + 1) * N, zstr = long(ws->m) * N;
-    const int p = probs[0]->p, nblk = ws->nblk;
+    const int p = probs[S[act[0]].prob]->p, nblk = ws->nblk;
     Region h = region_at(hreg(0), ws->cap);
     const Region d = region_at(dreg(0), ws->cap);
     long* t_src = h.tab;               // scale source (r or w) in RW
@@ -872,9 +904,10 @@ struct Lockstep {
                              Addr(0, d2.tab + cap), N, ne, st);
     // r = F - A_0 u (each solve with its own A_0)
     {
-      const DevOp<double> a0{nullptr, nullptr, probs[0]->M,
+      const hz_problem* pe = probs[S[end[0]].prob];
+      const DevOp<double> a0{nullptr, nullptr, pe->M,
                              reinterpret_cast<const double2* const*>(d2.ptab), nullptr};
-      launch_stencil<double, double, double, double>(probs[0]->p, ST_RESID, a0, Ub,
+      launch_stencil<double, double, double, double>(pe->p, ST_RESID, a0, Ub,
                                                      Addr(0, d2.tab + cap), Fb,
                                                      Addr(0, d2.tab + 2 * cap), ws->RW,
                                                      Addr(0, d2.tab + 3 * cap), ne, st);
@@ -908,6 +941,7 @@ struct Lockstep {
 
   hz_status check_device() {
     for (int i = 0; i < nprob; ++i) {
+      if (!probs[i]) continue;
       int e = 0;
       HZ_HIP(hipMemcpy(&e, probs[i]->cw.err, sizeof(int), hipMemcpyDeviceToHost));
       if (e) return fail(HZ_EDEVICE, "coarse solve: a wait for another workgroup timed out");
@@ -915,18 +949,18 @@ struct Lockstep {
     return HZ_OK;
   }
 
+  hz_result result_of(int q) const {
+    hz_result r{};
+    r.iterations = S[q].its;
+    r.converged = S[q].conv ? 1 : 0;
+    r.rel_res_true = S[q].true_rel;
+    r.rel_res_est = S[q].est;
+    r.setup_s = probs[S[q].prob] ? probs[S[q].prob]->setup_s : 0.0;
+    r.solve_s = secs(S[q].t0);
+    return r;
+  }
   void results(hz_result* res) const {
-    const double solve_s = secs(t0);
-    for (int q = 0; q < nsol; ++q) {
-      hz_result r{};
-      r.iterations = S[q].its;
-      r.converged = S[q].conv ? 1 : 0;
-      r.rel_res_true = S[q].true_rel;
-      r.rel_res_est = S[q].est;
-      r.setup_s = probs[S[q].prob]->setup_s;
-      r.solve_s = solve_s;
-      res[q] = r;
-    }
+    for (int q = 0; q < nsol; ++q) res[q] = result_of(q);
   }
 };
 
@@ -1307,33 +1341,73 @@ void hz_destroy_problem(hz_problem* pr) { delete pr; }
 
 namespace {
 
+struct EnginePool;
+
 struct EngineRequest {
   long id = 0;
   double k = 0, h = 0, theta = 0;
-  int p = 1;
+  int p = 1, n = 0;
   cd s;
   const double2* F = nullptr;     // caller's right-hand side, or null: plane-wave load
   double2* u = nullptr;           // caller's solution buffer
-  clk::time_point t_submit, t_admit, t_start;
+  clk::time_point t_submit, t_admit;
   size_t bytes_setup = 0, bytes = 0;
   hz_problem* pr = nullptr;
-  std::unique_ptr<Workspace> ws;
-  std::unique_ptr<Lockstep> ls;
-  hz_problem* probs[1] = {nullptr};
-  long off0 = 0;
+  EnginePool* pool = nullptr;
+  int slot = -1;
   hz_status status = HZ_OK;
   std::string err;
   bool admitted = false, setup_done = false;
   ~EngineRequest() {
-    ls.reset();
-    ws.reset();
     if (pr) hz_destroy_problem(pr);
   }
 };
 
-size_t request_bytes(int n, int p, int m, int prec, size_t* setup) {
+// A lockstep group of one mesh class (n, p): a workspace of cap solve slots (right-hand
+// sides and solutions staged in it) whose members join and leave between rounds.
+struct EnginePool {
+  int n = 0, p = 0, cap = 0;
+  size_t bytes = 0;
+  std::unique_ptr<Workspace> ws;
+  std::vector<hz_problem*> probs;
+  std::vector<EngineRequest*> member;
+  std::vector<long> off;
+  std::unique_ptr<Lockstep> ls;
+  int members() const {
+    int c = 0;
+    for (auto* r : member) c += r != nullptr;
+    return c;
+  }
+};
+
+struct ClassKey {
+  int n, p;
+  bool operator<(const ClassKey& o) const { return n != o.n ? n < o.n : p < o.p; }
+};
+struct ClassState {
+  int slots_total = 0;     // slots of created pools plus reserved pools
+  int slots_used = 0;      // admitted requests of the class not yet retired
+  int reserved = 0;        // pools reserved at admission and not created yet
+};
+
+size_t slot_bytes(int n, int p, int m, int prec) {
   const Sizes z = sizes_of(n, p);
-  const size_t steady = resident_bytes(n, p, m, prec) + 2 * size_t(z.N) * 16;
+  return workspace_bytes(z.N, z.nblk, 1, m, prec, true) + scratch_bytes(z.N, z.Nc, 1, prec);
+}
+
+// Slots per pool: as many solves of the class as fit in about 8 GB of workspace (and a
+// quarter of the engine's budget), 1 .. 16.
+int pool_cap(int n, int p, int m, int prec, size_t budget) {
+  const double b = double(slot_bytes(n, p, m, prec));
+  const double lim = std::min(8e9, 0.25 * double(budget));
+  return int(std::max(1.0, std::min(16.0, std::floor(lim / b))));
+}
+
+size_t request_bytes(int n, int p, int prec, size_t* setup) {
+  const Sizes z = sizes_of(n, p);
+  // factor, stencil tables, the problem's own one-solve V-cycle scratch and sweep buffer
+  const size_t steady = z.factor_elems * (prec == HZ_MIXED ? 8 : 16) +
+                        scratch_bytes(z.N, z.Nc, 1, prec) + 4 * size_t(z.Nc) * 16 + 256 * 1024;
   // a mixed problem holds the FP64 factor and its FP32 copy while it is set up
   *setup = steady + (prec == HZ_MIXED ? z.factor_elems * 16 : 0);
   return steady;
@@ -1348,10 +1422,11 @@ struct hz_engine {
   hipStream_t st_solve = nullptr;
   std::vector<hipStream_t> st_setup;
   std::mutex mu;
-  std::condition_variable cv_work, cv_setup, cv_done;
+  std::condition_variable cv_work, cv_setup, cv_done, cv_trash;
   std::deque<EngineRequest*> pending, setup_q, ready, trash;
-  std::vector<EngineRequest*> active;   // owned by the loop thread
-  std::condition_variable cv_trash;
+  std::deque<std::unique_ptr<EnginePool>> dead_pools;
+  std::vector<std::unique_ptr<EnginePool>> pools;   // owned by the loop thread
+  std::map<ClassKey, ClassState> classes;           // guarded by mu
   std::deque<hz_engine_result> done;
   size_t used = 0;
   int admitted = 0;                     // admitted and not yet retired
@@ -1360,11 +1435,12 @@ struct hz_engine {
   std::thread loop, reaper;
   std::vector<std::thread> setup;
   ~hz_engine() {
+    pools.clear();
+    dead_pools.clear();
     for (auto* r : trash) delete r;
     for (auto* r : pending) delete r;
     for (auto* r : setup_q) delete r;
     for (auto* r : ready) delete r;
-    for (auto* r : active) delete r;
     if (st_solve) (void)hipStreamDestroy(st_solve);
     for (auto s : st_setup) (void)hipStreamDestroy(s);
   }
@@ -1372,24 +1448,34 @@ struct hz_engine {
 
 namespace {
 
+// Releases the memory of a retired request (and pool slots it reserved); caller holds mu.
+void engine_release_locked(hz_engine* e, EngineRequest* r) {
+  if (!r->admitted) return;
+  e->used -= r->setup_done ? r->bytes : r->bytes_setup;
+  e->admitted -= 1;
+  ClassState& c = e->classes[ClassKey{r->n, r->p}];
+  c.slots_used -= 1;
+  // a pool reserved for this class and never created is no longer needed
+  const int cap = pool_cap(r->n, r->p, e->opt.restart, e->opt.prec, e->cfg.hbm_budget);
+  while (c.reserved > 0 && c.slots_total - cap >= c.slots_used) {
+    c.reserved -= 1;
+    c.slots_total -= cap;
+    e->used -= size_t(cap) * slot_bytes(r->n, r->p, e->opt.restart, e->opt.prec);
+  }
+}
+
 void engine_finish(hz_engine* e, EngineRequest* r, const hz_result* res) {
   hz_engine_result out{};
   out.id = r->id;
   out.status = r->status;
   if (res) out.result = *res;
   const auto now = clk::now();
-  out.queue_s = std::chrono::duration<double>(r->t_admit - r->t_submit).count();
+  out.queue_s = r->admitted ? std::chrono::duration<double>(r->t_admit - r->t_submit).count() : 0.0;
   out.latency_s = std::chrono::duration<double>(now - r->t_submit).count();
-  if (r->status != HZ_OK) {
-    out.queue_s = std::max(0.0, out.queue_s);
-    std::snprintf(out.message, sizeof(out.message), "%s", r->err.c_str());
-  }
+  if (r->status != HZ_OK) std::snprintf(out.message, sizeof(out.message), "%s", r->err.c_str());
   {
     std::lock_guard<std::mutex> g(e->mu);
-    if (r->admitted) {
-      e->used -= r->setup_done ? r->bytes : r->bytes_setup;
-      e->admitted -= 1;
-    }
+    engine_release_locked(e, r);
     e->done.push_back(out);
     e->completed += 1;
     // device memory is released by the reaper thread: a free may wait for the device
@@ -1404,19 +1490,27 @@ void engine_reaper_main(hz_engine* e) {
   (void)hipSetDevice(e->device);
   while (true) {
     EngineRequest* r = nullptr;
+    std::unique_ptr<EnginePool> pool;
     {
       std::unique_lock<std::mutex> g(e->mu);
-      e->cv_trash.wait(g, [&] { return e->stop || !e->trash.empty(); });
-      if (e->trash.empty()) return;
-      r = e->trash.front();
-      e->trash.pop_front();
+      e->cv_trash.wait(g, [&] { return e->stop || !e->trash.empty() || !e->dead_pools.empty(); });
+      if (!e->trash.empty()) {
+        r = e->trash.front();
+        e->trash.pop_front();
+      } else if (!e->dead_pools.empty()) {
+        pool = std::move(e->dead_pools.front());
+        e->dead_pools.pop_front();
+      } else {
+        return;
+      }
     }
     delete r;
+    pool.reset();
   }
 }
 
-// Setup thread: create the problem (tables, coarse factor) and the solve workspace on its
-// own stream, so that factorisations overlap the solve rounds of admitted requests.
+// Setup thread: create the problem (tables, coarse factor) on its own stream, so that
+// factorisations overlap the solve rounds of the admitted requests.
 void engine_setup_main(hz_engine* e, int tid) {
   (void)hipSetDevice(e->device);
   hipStream_t st = e->st_setup[tid];
@@ -1431,23 +1525,8 @@ void engine_setup_main(hz_engine* e, int tid) {
     }
     hz_options o = e->opt;
     o.timing = 0;
-    hz_status stt = hz_create_problem(r->k, r->h, r->p, hz_c64{r->s.real(), r->s.imag()}, &o, st, &r->pr);
-    if (stt == HZ_OK) {
-      try {
-        hz_problem* pr = r->pr;
-        r->ws = make_workspace(1, pr->m, o.prec, pr->N, pr->Nc, 0, true);
-        r->ws->s64 = pr->s64;
-        r->ws->s32 = pr->s32;
-        r->ws->gb = pr->cw.g;
-        if (r->F)
-          HZ_HIP(hipMemcpyAsync(r->ws->Fs, r->F, size_t(pr->N) * 16, hipMemcpyDeviceToDevice, st));
-        else
-          launch_planewave(pr->p, pr->n, pr->k, r->theta, pr->gl_t, pr->gl_w, pr->lag, r->ws->Fs, st);
-        HZ_HIP(hipStreamSynchronize(st));
-      } catch (...) {
-        stt = map_exception();
-      }
-    }
+    const hz_status stt =
+        hz_create_problem(r->k, r->h, r->p, hz_c64{r->s.real(), r->s.imag()}, &o, st, &r->pr);
     if (stt != HZ_OK) {
       r->status = stt;
       r->err = hz_last_error();
@@ -1464,12 +1543,25 @@ void engine_setup_main(hz_engine* e, int tid) {
   }
 }
 
-// Admits queued requests in arrival order while a slot and the memory budget allow.
+// Admits queued requests in arrival order while a slot and the memory budget allow. The
+// memory of a new pool is reserved when the class has no free slot left.
 void engine_admit(hz_engine* e) {
   while (!e->pending.empty() && e->admitted < e->cfg.max_active) {
     EngineRequest* r = e->pending.front();
-    if (e->used + r->bytes_setup > e->cfg.hbm_budget && e->admitted > 0) break;
+    ClassState& c = e->classes[ClassKey{r->n, r->p}];
+    size_t need = r->bytes_setup;
+    const int cap = pool_cap(r->n, r->p, e->opt.restart, e->opt.prec, e->cfg.hbm_budget);
+    const size_t pool_b = size_t(cap) * slot_bytes(r->n, r->p, e->opt.restart, e->opt.prec);
+    const bool new_pool = c.slots_used >= c.slots_total;
+    if (new_pool) need += pool_b;
+    if (e->used + need > e->cfg.hbm_budget && e->admitted > 0) break;
     e->pending.pop_front();
+    if (new_pool) {
+      c.slots_total += cap;
+      c.reserved += 1;
+      e->used += pool_b;
+    }
+    c.slots_used += 1;
     r->admitted = true;
     r->t_admit = clk::now();
     e->used += r->bytes_setup;
@@ -1479,19 +1571,104 @@ void engine_admit(hz_engine* e) {
   }
 }
 
-// Loop thread: every round performs one Arnoldi step of each active request (all on one
-// stream: the coarse solves are cooperative launches and must not run concurrently with
-// each other), synchronises once, then updates every request on the host; finished requests
-// leave and free their memory, new ones join between rounds.
+// Joins a set-up request to a pool of its class (creating a reserved pool if needed).
+void engine_join(hz_engine* e, EngineRequest* r, hipStream_t st) {
+  EnginePool* pool = nullptr;
+  int slot = -1;
+  for (auto& pp : e->pools)
+    if (pp->n == r->n && pp->p == r->p)
+      for (int q = 0; q < pp->cap && slot < 0; ++q)
+        if (!pp->member[q]) {
+          pool = pp.get();
+          slot = q;
+        }
+  if (!pool) {
+    std::unique_ptr<EnginePool> np(new EnginePool());
+    const int cap = pool_cap(r->n, r->p, e->opt.restart, e->opt.prec, e->cfg.hbm_budget);
+    np->n = r->n;
+    np->p = r->p;
+    np->cap = cap;
+    np->bytes = size_t(cap) * slot_bytes(r->n, r->p, e->opt.restart, e->opt.prec);
+    const hz_problem* pr = r->pr;
+    np->ws = make_workspace(cap, e->opt.restart, e->opt.prec, pr->N, pr->Nc, cap, true);
+    np->probs.assign(cap, nullptr);
+    np->member.assign(cap, nullptr);
+    np->off.resize(cap);
+    for (int q = 0; q < cap; ++q) np->off[q] = long(q) * pr->N;
+    np->ls.reset(new Lockstep(np->probs.data(), cap, 1, np->ws->Fs, np->off.data(), np->ws->Us,
+                              np->off.data(), *np->ws, e->opt));
+    np->ls->init_vacant();
+    {
+      std::lock_guard<std::mutex> g(e->mu);
+      ClassState& c = e->classes[ClassKey{r->n, r->p}];
+      c.reserved = std::max(0, c.reserved - 1);
+    }
+    pool = np.get();
+    slot = 0;
+    e->pools.push_back(std::move(np));
+  }
+  hz_problem* pr = r->pr;
+  double2* Fq = pool->ws->Fs + size_t(slot) * pr->N;
+  if (r->F) HZ_HIP(hipMemcpyAsync(Fq, r->F, size_t(pr->N) * 16, hipMemcpyDeviceToDevice, st));
+  else launch_planewave(pr->p, pr->n, pr->k, r->theta, pr->gl_t, pr->gl_w, pr->lag, Fq, st);
+  pool->probs[slot] = pr;
+  pool->member[slot] = r;
+  r->pool = pool;
+  r->slot = slot;
+  const int qs[1] = {slot};
+  const hz_status stt = pool->ls->start_slots(qs, 1, nullptr, st);
+  if (stt != HZ_OK) throw std::runtime_error(hz_last_error());
+}
+
+void engine_leave(hz_engine* e, EngineRequest* r) {
+  EnginePool* pool = r->pool;
+  if (!pool) return;
+  pool->ls->vacate(r->slot);
+  pool->probs[r->slot] = nullptr;
+  pool->member[r->slot] = nullptr;
+  r->pool = nullptr;
+  // an empty pool is released unless an admitted request of its class still needs a slot
+  if (pool->members() == 0) {
+    std::lock_guard<std::mutex> g(e->mu);
+    ClassState& c = e->classes[ClassKey{pool->n, pool->p}];
+    // the leaving request still counts in slots_used
+    if (c.slots_total - pool->cap >= c.slots_used - 1) {
+      c.slots_total -= pool->cap;
+      e->used -= pool->bytes;
+      for (size_t i = 0; i < e->pools.size(); ++i)
+        if (e->pools[i].get() == pool) {
+          e->dead_pools.push_back(std::move(e->pools[i]));
+          e->pools.erase(e->pools.begin() + i);
+          break;
+        }
+    }
+  }
+  e->cv_trash.notify_one();
+}
+
+void engine_fail(hz_engine* e, EngineRequest* r, hz_status stt, const std::string& msg) {
+  r->status = stt;
+  r->err = msg;
+  engine_leave(e, r);
+  engine_finish(e, r, nullptr);
+}
+
+// Loop thread: every round performs one FGMRES iteration of each active request, one batch
+// of launches per pool (all on one stream: the coarse solves are cooperative launches and
+// must not run concurrently with each other), synchronises once, then updates every request
+// on the host; finished requests leave their pools and free their memory, new ones join
+// between rounds.
 void engine_loop_main(hz_engine* e) {
   (void)hipSetDevice(e->device);
   hipStream_t st = e->st_solve;
-  std::vector<EngineRequest*> joining;
+  std::vector<EngineRequest*> joining, finished;
   while (true) {
+    bool any = false;
+    for (auto& pp : e->pools) any = any || pp->members() > 0;
     {
       std::unique_lock<std::mutex> g(e->mu);
       engine_admit(e);
-      if (e->active.empty())
+      if (!any)
         e->cv_work.wait(g, [&] {
           engine_admit(e);
           return e->stop || !e->ready.empty();
@@ -1501,64 +1678,85 @@ void engine_loop_main(hz_engine* e) {
       e->ready.clear();
     }
     for (EngineRequest* r : joining) {
-      r->t_start = clk::now();
-      r->probs[0] = r->pr;
-      hz_options o = e->opt;
-      r->ls.reset(new Lockstep(r->probs, 1, 1, r->ws->Fs, &r->off0, r->u, &r->off0, *r->ws, o));
-      hz_status stt;
       try {
-        stt = r->ls->start(nullptr, st);
+        engine_join(e, r, st);
       } catch (...) {
-        stt = map_exception();
+        const hz_status stt = map_exception();
+        engine_fail(e, r, stt, hz_last_error());
       }
-      if (stt != HZ_OK) {
-        r->status = stt;
-        r->err = hz_last_error();
-        engine_finish(e, r, nullptr);
-        continue;
-      }
-      e->active.push_back(r);
     }
     joining.clear();
-    std::vector<EngineRequest*> failed;
+    // one round
+    bool issued = false;
     try {
-      for (EngineRequest* r : e->active) r->ls->issue(st);
+      for (auto& pp : e->pools)
+        if (pp->members() > 0) issued = pp->ls->issue(st) || issued;
       HZ_HIP(hipStreamSynchronize(st));
     } catch (...) {
       const hz_status stt = map_exception();
-      for (EngineRequest* r : e->active) {
-        r->status = stt;
-        r->err = hz_last_error();
-        engine_finish(e, r, nullptr);
-      }
-      e->active.clear();
+      const std::string msg = hz_last_error();
+      std::vector<EngineRequest*> all;
+      for (auto& pp : e->pools)
+        for (auto* r : pp->member)
+          if (r) all.push_back(r);
+      for (auto* r : all) engine_fail(e, r, stt, msg);   // may release pools
       continue;
     }
-    std::vector<EngineRequest*> keep;
-    for (EngineRequest* r : e->active) {
+    // host updates; finished solves copy their staged solution out
+    finished.clear();
+    std::vector<std::pair<EngineRequest*, std::pair<hz_status, std::string>>> failed;
+    for (size_t i = 0; i < e->pools.size(); ++i) {
+      EnginePool* pp = e->pools[i].get();
+      if (pp->members() == 0) continue;
       hz_status stt;
       try {
-        stt = r->ls->complete(st);
-        if (stt == HZ_OK && r->ls->finished()) stt = r->ls->check_device();
+        stt = pp->ls->complete(st);
       } catch (...) {
         stt = map_exception();
       }
       if (stt != HZ_OK) {
-        r->status = stt;
-        r->err = hz_last_error();
-        engine_finish(e, r, nullptr);
+        const std::string msg = hz_last_error();
+        for (auto* r : pp->member)
+          if (r) failed.push_back({r, {stt, msg}});
         continue;
       }
-      if (r->ls->finished()) {
-        hz_result res;
-        r->ls->results(&res);
-        res.solve_s = std::chrono::duration<double>(clk::now() - r->t_start).count();
-        engine_finish(e, r, &res);
-        continue;
+      for (int q = 0; q < pp->cap; ++q) {
+        EngineRequest* r = pp->member[q];
+        if (r && pp->ls->S[q].done) {
+          HZ_HIP(hipMemcpyAsync(r->u, pp->ws->Us + size_t(q) * pp->ws->N, size_t(pp->ws->N) * 16,
+                                hipMemcpyDeviceToDevice, st));
+          finished.push_back(r);
+        }
       }
-      keep.push_back(r);
     }
-    e->active.swap(keep);
+    for (auto& f : failed) engine_fail(e, f.first, f.second.first, f.second.second);
+    if (finished.empty()) continue;
+    try {
+      HZ_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      const hz_status stt = map_exception();
+      for (auto* r : finished) engine_fail(e, r, stt, hz_last_error());
+      continue;
+    }
+    for (EngineRequest* r : finished) {
+      EnginePool* pp = r->pool;
+      hz_status stt = HZ_OK;
+      std::string msg;
+      {
+        int ef = 0;
+        if (hipMemcpy(&ef, r->pr->cw.err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess || ef) {
+          stt = HZ_EDEVICE;
+          msg = "coarse solve: a wait for another workgroup timed out";
+        }
+      }
+      if (stt != HZ_OK) {
+        engine_fail(e, r, stt, msg);
+        continue;
+      }
+      const hz_result res = pp->ls->result_of(r->slot);
+      engine_leave(e, r);
+      engine_finish(e, r, &res);
+    }
   }
 }
 
@@ -1591,6 +1789,7 @@ hz_status hz_engine_create(const hz_engine_config* c, const hz_options* o, hz_en
   try {
     e = new hz_engine();
     e->opt = opt;
+    e->opt.timing = 0;
     HZ_HIP(hipGetDevice(&e->device));
     if (cfg.hbm_budget == 0) {
       size_t fr = 0, tot = 0;
@@ -1623,11 +1822,12 @@ hz_status hz_engine_submit(hz_engine* e, double k, double h, int p, hz_c64 s, do
   if (!d_F && !std::isfinite(theta)) return fail(HZ_EINVAL, "theta must be finite");
   std::unique_ptr<EngineRequest> r(new EngineRequest());
   r->id = req_id;
-  r->k = k; r->h = h; r->p = p; r->s = sc; r->theta = theta;
+  r->k = k; r->h = h; r->p = p; r->n = n; r->s = sc; r->theta = theta;
   r->F = reinterpret_cast<const double2*>(d_F);
   r->u = reinterpret_cast<double2*>(d_u);
-  r->bytes = request_bytes(n, p, e->opt.restart, e->opt.prec, &r->bytes_setup);
-  if (r->bytes_setup > e->cfg.hbm_budget)
+  r->bytes = request_bytes(n, p, e->opt.prec, &r->bytes_setup);
+  const int cap = pool_cap(n, p, e->opt.restart, e->opt.prec, e->cfg.hbm_budget);
+  if (r->bytes_setup + size_t(cap) * slot_bytes(n, p, e->opt.restart, e->opt.prec) > e->cfg.hbm_budget)
     return fail(HZ_ENOMEM, "request needs more device memory than the engine budget");
   r->t_submit = clk::now();
   {
@@ -1681,6 +1881,13 @@ void hz_engine_destroy(hz_engine* e) {
   if (e->reaper.joinable()) e->reaper.join();
   if (e->st_solve) (void)hipStreamSynchronize(e->st_solve);
   for (auto s : e->st_setup) (void)hipStreamSynchronize(s);
+  // requests still in pools
+  for (auto& pp : e->pools)
+    for (auto*& r : pp->member)
+      if (r) {
+        delete r;
+        r = nullptr;
+      }
   delete e;
 }
 
