@@ -182,6 +182,19 @@ def run_sweep(cfg, steps, warmup, prec):
     log(f"sweep: {len(betas)} shifts x {nr} angles, groups of {gsize} shifts "
         f"({per_shift / 1e9:.2f} GB per shift, {free / 1e9:.0f} GB free)")
 
+    # the coarse factorisations of a group are independent and latency-bound: several run at
+    # once, each from its own host thread on its own stream
+    from concurrent.futures import ThreadPoolExecutor
+    nsetup = 8
+    streams = [torch.cuda.Stream() for _ in range(nsetup)]
+
+    def create(ib):
+        i, b = ib
+        torch.cuda.set_device(0)
+        with torch.cuda.stream(streams[i % nsetup]):
+            return hz.Problem(k, 1.0 / n, p, 1 + 1j * b, nu=cfg["nu"], omega=cfg["omega"],
+                              restart=cfg["restart"], tol=tol, prec=prec, timing=True)
+
     def sweep(record):
         its = [[0] * nr for _ in betas]
         rhos = [[0.0] * nr for _ in betas]
@@ -190,9 +203,9 @@ def run_sweep(cfg, steps, warmup, prec):
         for g0 in range(0, len(betas), gsize):
             gb = betas[g0:g0 + gsize]
             t = time.perf_counter()
-            probs = [hz.Problem(k, 1.0 / n, p, 1 + 1j * b, nu=cfg["nu"], omega=cfg["omega"],
-                                restart=cfg["restart"], tol=tol, prec=prec, timing=record)
-                     for b in gb]
+            with ThreadPoolExecutor(nsetup) as ex:
+                probs = list(ex.map(create, enumerate(gb)))
+            torch.cuda.synchronize()
             setup_s += time.perf_counter() - t
             if Fs is None:
                 Fs = [probs[0].planewave_rhs(th) for th in thetas]   # independent of the shift
@@ -247,7 +260,7 @@ def run_serving(count, rate, prec, max_active, tol=1e-8, restart=50):
 
     torch.cuda.set_device(0)
     reqs = inputs.serving_requests(count, seed=1, rate=rate)
-    eng = hz.Engine(max_active=max_active, setup_threads=2, tol=tol, restart=restart, prec=prec)
+    eng = hz.Engine(max_active=max_active, setup_threads=4, tol=tol, restart=restart, prec=prec)
     done = {}
     t0 = time.perf_counter()
     nxt = 0

@@ -54,8 +54,33 @@ struct DevMem {
         return;
       }
   }
+  // Stream-ordered allocation for buffers that live only during setup: hipFree may wait for
+  // the whole device, which would serialise concurrent setups; hipFreeAsync does not.
+  template <typename T> T* alloc_async(size_t n, hipStream_t st) {
+    void* p = nullptr;
+    const size_t nb = std::max<size_t>(n, 1) * sizeof(T);
+    if (hipMallocAsync(&p, nb, st) != hipSuccess) {
+      (void)hipGetLastError();
+      return alloc<T>(n);
+    }
+    async.emplace_back(p, nb);
+    bytes += nb;
+    return static_cast<T*>(p);
+  }
+  void release_async(void* p, hipStream_t st) {
+    for (size_t i = 0; i < async.size(); ++i)
+      if (async[i].first == p) {
+        (void)hipFreeAsync(p, st);
+        bytes -= async[i].second;
+        async.erase(async.begin() + i);
+        return;
+      }
+    release(p);
+  }
+  std::vector<std::pair<void*, size_t>> async;
   ~DevMem() {
     for (auto& a : live) (void)hipFree(a.first);
+    for (auto& a : async) (void)hipFree(a.first);
   }
 };
 
@@ -281,7 +306,7 @@ size_t resident_bytes(int n, int p, int m, int prec) {
   return b;
 }
 
-void upload_tables(hz_problem* pr) {
+void upload_tables(hz_problem* pr, hipStream_t st) {
   const LevelTables ft = build_level_tables(pr->p, pr->n, 1.0 / pr->n);
   const LevelTables ct = build_level_tables(pr->p, pr->n / 2, 2.0 / pr->n);
   const std::vector<cd> a0 = combine_operator(ft, pr->k, cd(1.0, 0.0));
@@ -295,12 +320,13 @@ void upload_tables(hz_problem* pr) {
   }
   auto up2 = [&](const std::vector<cd>& v, double2*& d, float2*& f, bool want_f) {
     d = pr->mem.alloc<double2>(v.size());
-    HZ_HIP(hipMemcpy(d, v.data(), v.size() * 16, hipMemcpyHostToDevice));
+    HZ_HIP(hipMemcpyAsync(d, v.data(), v.size() * 16, hipMemcpyHostToDevice, st));
     if (want_f) {
       std::vector<float2> fv(v.size());
       for (size_t i = 0; i < v.size(); ++i) fv[i] = make_float2(float(v[i].real()), float(v[i].imag()));
       f = pr->mem.alloc<float2>(v.size());
-      HZ_HIP(hipMemcpy(f, fv.data(), v.size() * 8, hipMemcpyHostToDevice));
+      HZ_HIP(hipMemcpyAsync(f, fv.data(), v.size() * 8, hipMemcpyHostToDevice, st));
+      HZ_HIP(hipStreamSynchronize(st));   // fv is local
     }
   };
   float2* dummy = nullptr;
@@ -309,10 +335,11 @@ void upload_tables(hz_problem* pr) {
   up2(wd, pr->wdAe, pr->fwdAe, true);
   up2(ac, pr->cAc, pr->fcAc, true);
   pr->rw = pr->mem.alloc<double>(ft.RW.size());
-  HZ_HIP(hipMemcpy(pr->rw, ft.RW.data(), ft.RW.size() * 8, hipMemcpyHostToDevice));
+  HZ_HIP(hipMemcpyAsync(pr->rw, ft.RW.data(), ft.RW.size() * 8, hipMemcpyHostToDevice, st));
   std::vector<float> frw(ft.RW.begin(), ft.RW.end());
   pr->frw = pr->mem.alloc<float>(frw.size());
-  HZ_HIP(hipMemcpy(pr->frw, frw.data(), frw.size() * 4, hipMemcpyHostToDevice));
+  HZ_HIP(hipMemcpyAsync(pr->frw, frw.data(), frw.size() * 4, hipMemcpyHostToDevice, st));
+  HZ_HIP(hipStreamSynchronize(st));   // the host tables are local
   gauss_legendre10(pr->gl_t, pr->gl_w);
   for (int l = 0; l < 4; ++l)
     for (int q = 0; q < 10; ++q) {
@@ -1058,16 +1085,17 @@ hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_option
     pr->Nc = long(pr->Mc) * pr->Mc;
     pr->L = CoarseLayout{p, n / 2, pr->Mc};
     pr->m = opt.restart;
-    upload_tables(pr);
+    upload_tables(pr, st);
     // coarse factor (FP64), then the FP32 copy for mixed-precision problems
-    pr->S = pr->mem.alloc<double2>(pr->L.total());
+    pr->S = opt.prec == HZ_MIXED ? pr->mem.alloc_async<double2>(pr->L.total(), st)
+                                 : pr->mem.alloc<double2>(pr->L.total());
     {
       CoarseFactorWork wk;
       const size_t mb = size_t(pr->L.size(0));
-      wk.T = pr->mem.alloc<double2>(2 * mb * mb);     // one set per factorisation chain
-      wk.W = pr->mem.alloc<double2>(2 * mb * 32);
-      wk.R = pr->mem.alloc<double2>(2 * mb * 32);
-      wk.flag = pr->mem.alloc<int>(1);
+      wk.T = pr->mem.alloc_async<double2>(2 * mb * mb, st);     // one set per chain
+      wk.W = pr->mem.alloc_async<double2>(2 * mb * 32, st);
+      wk.R = pr->mem.alloc_async<double2>(2 * mb * 32, st);
+      wk.flag = pr->mem.alloc_async<int>(1, st);
       const DevOp<double> cop{pr->cAc, nullptr, pr->Mc};
       pr->timing = opt.timing != 0;
       hipEvent_t f0 = nullptr, f1 = nullptr;
@@ -1086,10 +1114,10 @@ hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_option
         (void)hipEventDestroy(f0);
         (void)hipEventDestroy(f1);
       }
-      pr->mem.release(wk.T);
-      pr->mem.release(wk.W);
-      pr->mem.release(wk.R);
-      pr->mem.release(wk.flag);
+      pr->mem.release_async(wk.T, st);
+      pr->mem.release_async(wk.W, st);
+      pr->mem.release_async(wk.R, st);
+      pr->mem.release_async(wk.flag, st);
       if (fs != HZ_OK) {
         delete pr;
         return fail(fs, "zero or non-finite pivot in the coarse block factorisation");
@@ -1104,8 +1132,7 @@ hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_option
     }
     if (opt.prec == HZ_MIXED) {
       ensure_mixed_work(pr, st);
-      HZ_HIP(hipStreamSynchronize(st));
-      pr->mem.release(pr->S);
+      pr->mem.release_async(pr->S, st);
       pr->S = nullptr;
     } else {
       ensure_fp64_work(pr);

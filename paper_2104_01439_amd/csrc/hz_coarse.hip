@@ -417,9 +417,17 @@ template <int P, typename T>
 __device__ __forceinline__ V2<T> coupling(int c, int j, int jn, int nc, int Mc,
                                           const V2<T>* __restrict__ cl, const V2<T>* yv) {
   constexpr int W = 2 * P + 1, W2 = W * W;
-  const int rl = c / Mc, ac = c - rl * Mc;
+  // c = rl Mc + ac with rl < P (a block holds at most P lattice rows); the class row of
+  // lattice row bc = P j + rl is rl
+  int rl = 0;
+  if constexpr (P >= 2) rl += c >= Mc;
+  if constexpr (P >= 3) rl += c >= 2 * Mc;
+  const int ac = c - rl * Mc;
   const int bc = P * j + rl;
-  const V2<T>* cc = cl + (((bc % P) * P + ac % P) * 9 + region(bc, Mc) * 3 + region(ac, Mc)) * W2;
+  const int cls = rl * P + (P == 1 ? 0 : ac % P);
+  const int ry = bc == 0 ? 0 : (bc == Mc - 1 ? 2 : 1);
+  const int rx = ac == 0 ? 0 : (ac == Mc - 1 ? 2 : 1);
+  const V2<T>* cc = cl + ((cls * 9 + ry * 3 + rx) * W2);
   const int lo = P * jn, hi = P * jn + (jn < nc ? P : 1);
   V2<T> acc = czero<T>();
 #pragma unroll
@@ -429,6 +437,7 @@ __device__ __forceinline__ V2<T> coupling(int c, int j, int jn, int nc, int Mc,
     const V2<T>* yr = yv + (bb - lo) * Mc;
 #pragma unroll
     for (int dx = -P; dx <= P; ++dx) {
+      if (P == 1 && !couples(1, 0, 0, dx, dy)) continue;   // the P1 stencil has 7 points
       const int aa = ac + dx;
       if (aa < 0 || aa >= Mc) continue;
       cfma(acc, cc[(dy + P) * W + dx + P], yr[aa]);
@@ -516,9 +525,7 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
   constexpr int W = 2 * P + 1, W2 = W * W, NCOEF = P * P * 9 * W2;
   constexpr int CG = CSOL_CG, RG = CSOL_RG, RW = CSOL_RW, QW = CSOL_QW;
   constexpr int RCH = RG * RW;                 // rows per chunk
-  // polled columns per exchange thread and right-hand side in one slice (registers: the
-  // stream waves' prefetched factor entries stay live across the exchange phase)
-  constexpr int EH = sizeof(T) == 8 ? (NR >= 4 ? 3 : NR == 2 ? 5 : 9) : (NR >= 4 ? 5 : 9);
+  constexpr int EH = (sizeof(T) == 8 && NR >= 4) ? 5 : 9;   // polled columns per thread and slice
   extern __shared__ char smem[];
   const int nmax = P * Mc;
   V2<T>* cl = reinterpret_cast<V2<T>*>(smem);  // coefficient table
@@ -526,16 +533,13 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
   V2<T>* buf1 = buf0 + NR * nmax;
   __shared__ T red[2][CG][RCH][NR];
   const int G = Gp, g = blockIdx.x - jb * Gp;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // wave-uniform (scalar) role index: the two roles run separate code
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
   const int sw = wave - 2, rg = sw / CG, cg = sw - (sw / CG) * CG;
   const size_t bsz = size_t(P * Mc) * size_t(P * Mc);
   const long Nc = long(Mc) * Mc;
   for (int i = threadIdx.x; i < NCOEF; i += 512) cl[i] = coef[i];
-
-  V2<T> sv[RW][QW];                            // stream waves: factor entries of a chunk
-  bool have = false;                           // sv holds the first chunk of this step
-  bool staged = false;                         // t already holds this step's start value
-  int par = 0;
 
   // exchange waves: dst[h][c] = b_j (forward steps) or 0, c < nj, in slices of 128 EH
   auto stage = [&](const StepPlan& q, V2<T>* dst) {
@@ -559,66 +563,122 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
     }
   };
 
-  for (int s = s_begin; s < s_end; ++s) {
-    const StepPlan pl = make_plan<P>(s, g, G, nc, Mc);
-    const int j = pl.j, nj = pl.nj;
-    const long dof0 = long(P) * j * Mc;
-    V2<T>* t = par ? buf1 : buf0;
-    V2<T>* yn = par ? buf0 : buf1;
-    // 1. exchange waves: t = b_j (forward, middle) or 0 (backward) unless staged during the
-    // previous step; neighbour blocks. The middle step couples two neighbours: the first is
-    // folded in between two workgroup barriers (every barrier is reached by all waves: the
-    // plan is uniform per workgroup).
-    if (wave < 2 && pl.active) {
-      if (!staged) stage(pl, t);
-      if (pl.jpre >= 0)
-        gather_block<P, T, NR, EH>(gbuf, Nc, pl.jpre, nc, Mc, nrhs, nmax, yn, threadIdx.x, err);
-    }
-    if (pl.jpre >= 0) {
-      __syncthreads();
-      for (int h = 0; h < nrhs; ++h)
-        for (int c = threadIdx.x; c < nj; c += 512) {
-          const V2<T> cp = coupling<P, T>(c, j, pl.jpre, nc, Mc, cl, yn + h * nmax);
-          t[h * nmax + c] = csub<T>(t[h * nmax + c], cp);
-        }
-      __syncthreads();
-    }
-    if (wave < 2 && pl.active && pl.jfly >= 0) {
-      const bool from_g = pl.fwd;              // forward/middle neighbours are in gbuf
-      gather_block<P, T, NR, EH>(from_g ? gbuf : y, from_g ? Nc : cstride, pl.jfly, nc, Mc,
-                                 nrhs, nmax, yn, threadIdx.x, err);
-    }
-    __syncthreads();
-    // 2. fold the neighbour: t += sgn * A_{j,jfly} y_jfly
-    if (pl.active && pl.jfly >= 0) {
-      const T sgn = pl.fwd ? T(-1) : T(1);
-      for (int h = 0; h < nrhs; ++h)
-        for (int c = threadIdx.x; c < nj; c += 512) {
-          const V2<T> cp = coupling<P, T>(c, j, pl.jfly, nc, Mc, cl, yn + h * nmax);
-          V2<T> tv = t[h * nmax + c];
-          tv.x += sgn * cp.x;
-          tv.y += sgn * cp.y;
-          t[h * nmax + c] = tv;
-        }
-      __syncthreads();
-    }
-    // the neighbour buffer is free: the exchange waves stage the next step's start value
-    staged = false;
-    if (s + 1 < s_end) {
-      const StepPlan pn = make_plan<P>(s + 1, g, G, nc, Mc);
-      if (pn.active) {
-        if (wave < 2) stage(pn, yn);
-        staged = true;
+  // t += sgn * A_{j,jn} y_jn for every right-hand side; run by all 512 threads (each role
+  // calls it from its own loop, so that the two roles never share a code path: a wait for
+  // outstanding loads at a shared join would hold the stream waves' prefetch)
+  auto fold = [&](const StepPlan& pl, int jn, T sgn, V2<T>* t, const V2<T>* yn) {
+    for (int h = 0; h < nrhs; ++h)
+      for (int c = threadIdx.x; c < pl.nj; c += 512) {
+        const V2<T> cp = coupling<P, T>(c, pl.j, jn, nc, Mc, cl, yn + h * nmax);
+        V2<T> tv = t[h * nmax + c];
+        tv.x += sgn * cp.x;
+        tv.y += sgn * cp.y;
+        t[h * nmax + c] = tv;
       }
+  };
+
+  if (wave < 2) {
+    // ---------------- exchange waves ----------------
+    bool staged = false;             // t already holds this step's start value
+    int par = 0;
+    for (int s = s_begin; s < s_end; ++s) {
+      const StepPlan pl = make_plan<P>(s, g, G, nc, Mc);
+      const int j = pl.j;
+      const long dof0 = long(P) * j * Mc;
+      V2<T>* t = par ? buf1 : buf0;
+      V2<T>* yn = par ? buf0 : buf1;
+      // t = b_j (forward, middle) or 0 (backward) unless staged during the previous step;
+      // the middle step couples two neighbours, the first folded between two barriers
+      if (pl.active) {
+        if (!staged) stage(pl, t);
+        if (pl.jpre >= 0)
+          gather_block<P, T, NR, EH>(gbuf, Nc, pl.jpre, nc, Mc, nrhs, nmax, yn, threadIdx.x, err);
+      }
+      if (pl.jpre >= 0) {
+        __syncthreads();
+        fold(pl, pl.jpre, T(-1), t, yn);
+        __syncthreads();
+      }
+      if (pl.active && pl.jfly >= 0) {
+        const bool from_g = pl.fwd;          // forward/middle neighbours are in gbuf
+        gather_block<P, T, NR, EH>(from_g ? gbuf : y, from_g ? Nc : cstride, pl.jfly, nc, Mc,
+                                   nrhs, nmax, yn, threadIdx.x, err);
+      }
+      __syncthreads();
+      if (pl.active && pl.jfly >= 0) {
+        fold(pl, pl.jfly, pl.fwd ? T(-1) : T(1), t, yn);
+        __syncthreads();
+      }
+      // the neighbour buffer is free: stage the next step's start value into it
+      staged = false;
+      if (s + 1 < s_end) {
+        const StepPlan pn = make_plan<P>(s + 1, g, G, nc, Mc);
+        if (pn.active) {
+          stage(pn, yn);
+          staged = true;
+        }
+      }
+      // combine the stream waves' partial row sums and publish the rows
+      for (int rb = pl.r0; rb < pl.r1; rb += RCH) {
+        __syncthreads();
+        if (threadIdx.x < RCH * NR) {
+          const int rr = threadIdx.x / NR, h = threadIdx.x % NR;
+          const int r = rb + rr;
+          if (r < pl.r1 && h < nrhs) {
+            T sr = red[0][0][rr][h], si = red[1][0][rr][h];
+#pragma unroll
+            for (int k = 1; k < CG; ++k) {
+              sr += red[0][k][rr][h];
+              si += red[1][k][rr][h];
+            }
+            V2<T> o;
+            if (pl.fwd) {
+              o.x = sr;
+              o.y = si;
+              st_coh<T>((pl.mid ? y + h * cstride : gbuf + h * Nc) + dof0 + r, o);
+            } else {
+              o = ld_coh<T>(gbuf + h * Nc + dof0 + r);
+              o.x -= sr;
+              o.y -= si;
+              st_coh<T>(y + h * cstride + dof0 + r, o);
+            }
+          }
+        }
+        // red is rewritten by the next chunk; after the last chunk the next write to red
+        // comes after this step's successor has passed two more barriers
+        if (rb + RCH < pl.r1) __syncthreads();
+      }
+      // a step without rows of this workgroup still needs the staged buffer to be complete
+      if (pl.r1 <= pl.r0) __syncthreads();
+      par ^= 1;
     }
-    // 3. rows [r0, r1) of S_j t in chunks of RCH rows
-    const int r0 = pl.r0, r1 = pl.r1;
-    const int c0 = (nj * cg) / CG, c1 = (nj * (cg + 1)) / CG;
-    const V2<T>* Sj = S + size_t(j) * bsz;
-    const bool pre = have;
-    have = false;
-    for (int rb = r0; rb < r1; rb += RCH) {
-      if (wave >= 2) {
+  } else {
+    // ---------------- stream waves ----------------
+    V2<T> sv[RW][QW];                  // factor entries of a chunk
+    bool have = false;                 // sv holds the first chunk of this step
+    int par = 0;
+    for (int s = s_begin; s < s_end; ++s) {
+      const StepPlan pl = make_plan<P>(s, g, G, nc, Mc);
+      const int j = pl.j, nj = pl.nj;
+      V2<T>* t = par ? buf1 : buf0;
+      V2<T>* yn = par ? buf0 : buf1;
+      if (pl.jpre >= 0) {
+        __syncthreads();
+        fold(pl, pl.jpre, T(-1), t, yn);
+        __syncthreads();
+      }
+      __syncthreads();
+      if (pl.active && pl.jfly >= 0) {
+        fold(pl, pl.jfly, pl.fwd ? T(-1) : T(1), t, yn);
+        __syncthreads();
+      }
+      // rows [r0, r1) of S_j t in chunks of RCH rows
+      const int r0 = pl.r0, r1 = pl.r1;
+      const int c0 = (nj * cg) / CG, c1 = (nj * (cg + 1)) / CG;
+      const V2<T>* Sj = S + size_t(j) * bsz;
+      const bool pre = have;
+      have = false;
+      for (int rb = r0; rb < r1; rb += RCH) {
         const int rw0 = rb + rg * RW;
         T ar[RW][NR], ai[RW][NR];
 #pragma unroll
@@ -652,8 +712,18 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
             }
           }
         }
-        // first chunk of the next step, issued as soon as this step's last chunk is consumed
-        if (rb + RCH >= r1 && s + 1 < s_end) {
+#pragma unroll
+        for (int i = 0; i < RW; ++i)
+#pragma unroll
+          for (int h = 0; h < NR; ++h) {
+            const T sr = wave_sum(ar[i][h]), si = wave_sum(ai[i][h]);
+            if (lane == 0) { red[0][cg][rg * RW + i][h] = sr; red[1][cg][rg * RW + i][h] = si; }
+          }
+        __syncthreads();                 // the exchange waves combine and publish ...
+        const bool last = rb + RCH >= r1;
+        // ... while the first chunk of the next step is requested (issuing the loads of a
+        // whole chunk takes longer than the exchange, so it stays off the critical path)
+        if (last && s + 1 < s_end) {
           const StepPlan pn = make_plan<P>(s + 1, g, G, nc, Mc);
           if (pn.active && pn.r1 > pn.r0) {
             const int nj2 = pn.nj;
@@ -671,43 +741,11 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
             have = true;
           }
         }
-#pragma unroll
-        for (int i = 0; i < RW; ++i)
-#pragma unroll
-          for (int h = 0; h < NR; ++h) {
-            const T sr = wave_sum(ar[i][h]), si = wave_sum(ai[i][h]);
-            if (lane == 0) { red[0][cg][rg * RW + i][h] = sr; red[1][cg][rg * RW + i][h] = si; }
-          }
+        if (!last) __syncthreads();      // red is rewritten by the next chunk
       }
-      __syncthreads();
-      if (threadIdx.x < RCH * NR) {
-        const int rr = threadIdx.x / NR, h = threadIdx.x % NR;
-        const int r = rb + rr;
-        if (r < r1 && h < nrhs) {
-          T sr = red[0][0][rr][h], si = red[1][0][rr][h];
-#pragma unroll
-          for (int k = 1; k < CG; ++k) {
-            sr += red[0][k][rr][h];
-            si += red[1][k][rr][h];
-          }
-          V2<T> o;
-          if (pl.fwd) {
-            o.x = sr;
-            o.y = si;
-            st_coh<T>((pl.mid ? y + h * cstride : gbuf + h * Nc) + dof0 + r, o);
-          } else {
-            o = ld_coh<T>(gbuf + h * Nc + dof0 + r);
-            o.x -= sr;
-            o.y -= si;
-            st_coh<T>(y + h * cstride + dof0 + r, o);
-          }
-        }
-      }
-      __syncthreads();
+      if (r1 <= r0) __syncthreads();
+      par ^= 1;
     }
-    // a step without rows of this workgroup still needs the staged buffer to be complete
-    if (r1 <= r0) __syncthreads();
-    par ^= 1;
   }
 }
 
