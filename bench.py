@@ -30,6 +30,23 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic(path="profiles/k_csolve_p1_k400_n2048_traffic.txt"):
+    """HBM bytes per launch of the coarse solve from the committed counter summary, or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, path)) as f:
+            kv = dict(l.split(": ", 1) for l in f.read().splitlines() if ": " in l and not l.startswith(" "))
+        src = os.path.join(ROOT, kv["kernel_source"].strip())
+        with open(src, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()[:16]
+        if h != kv["kernel_source_sha256_16"].strip():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(cfg, iterations):
     """The oracle (plain NumPy/SciPy FP64) timed on the host on a bounded sample of this
     workload and projected to one full solve.
@@ -479,7 +496,9 @@ def main():
                    "iterations": g["iterations"]},
         "roofline": {"kernel": "coarse block triangular solve (k_csolve)", "bound": "hbm",
                      "achieved": cs_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": cs_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": cs_gbs / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if (cfg["name"] == "p1_k400_n2048" and
+                                                       a.prec == "fp64") else None,
                      "bytes_per_launch": g["coarse_bytes"], "avg_launch_ms": g["coarse_ms"],
                      "launches": g["coarse_launches"]},
         "setup_factor_ms": g["factor_ms"],
