@@ -8,6 +8,13 @@
 // couplings that are structurally zero are removed at compile time. A workgroup stages its
 // tile of the input, with a halo of p lattice points, in LDS with coalesced loads.
 
+#include <cstdio>
+#include <cstdlib>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <string>
+
 #include "hz_common.h"
 
 namespace hz {
@@ -15,26 +22,37 @@ namespace hz {
 namespace {
 
 constexpr int BX = 64;   // macro points per tile along x (one wavefront)
-constexpr int BY = 4;    // macro rows per tile
 
 __device__ __forceinline__ int region(int a, int M) { return a == 0 ? 0 : (a == M - 1 ? 2 : 1); }
 
-template <int P, typename T, typename TX, typename TF, typename TY, int MODE>
+// A tile is BX x BYT macro points (each p x p lattice points) plus a p-halo, staged in LDS;
+// 256 threads = 64 columns x 4 rows, each thread BYT / 4 macro rows. XCD: the tiles are
+// renumbered so that workgroup b (dispatched round-robin over the 8 XCDs, each with its own
+// L2) takes the tiles of band b mod 8 in row order, so that the halo rows shared by
+// vertically adjacent tiles are read through the same L2.
+template <int P, typename T, typename TX, typename TF, typename TY, int MODE, int BYT, bool XCD>
 __global__ void __launch_bounds__(256)
 k_stencil(DevOp<T> op, const V2<TX>* __restrict__ x, Addr ax, const V2<TF>* __restrict__ f,
           Addr af, V2<TY>* __restrict__ y, Addr ay) {
   constexpr int W = 2 * P + 1, W2 = W * W;
-  constexpr int LW = P * BX + 2 * P, LH = P * BY + 2 * P;
+  constexpr int LW = P * BX + 2 * P, LH = P * BYT + 2 * P;
   __shared__ V2<T> tile[LH][LW];
   const int M = op.M;
   const int nmac = (M + P - 1) / P;
-  const int bz = blockIdx.z;
+  const int ntx = (nmac + BX - 1) / BX, nty = (nmac + BYT - 1) / BYT;
+  int tnum = blockIdx.x;
+  if (XCD) {
+    const int per = (ntx * nty + 7) / 8;
+    tnum = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (tnum >= ntx * nty) return;             // whole workgroup, before any barrier
+  }
+  const int bz = blockIdx.y;
   const V2<T>* __restrict__ coef = op.ctab ? op.ctab[bz] : op.coef;
   const V2<T>* __restrict__ wdinv = op.wtab ? op.wtab[bz] : op.wdinv;
   x += ax.at(bz);
   y += ay.at(bz);
   if (MODE != ST_APPLY) f += af.at(bz);
-  const int I0 = blockIdx.x * BX, J0 = blockIdx.y * BY;
+  const int I0 = (tnum % ntx) * BX, J0 = (tnum / ntx) * BYT;
   const int ax0 = P * I0 - P, by0 = P * J0 - P;
   for (int idx = threadIdx.x; idx < LW * LH; idx += 256) {
     const int ly = idx / LW, lx = idx - ly * LW;
@@ -44,9 +62,12 @@ k_stencil(DevOp<T> op, const V2<TX>* __restrict__ x, Addr ax, const V2<TF>* __re
     tile[ly][lx] = v;
   }
   __syncthreads();
-  const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
+  const int tx = threadIdx.x % BX;
+#pragma unroll
+  for (int rr = 0; rr < BYT / 4; ++rr) {
+  const int ty = threadIdx.x / BX + 4 * rr;
   const int I = I0 + tx, J = J0 + ty;
-  if (I >= nmac || J >= nmac) return;
+  if (I >= nmac || J >= nmac) continue;
 
   V2<T> acc[P][P];
 #pragma unroll
@@ -112,6 +133,7 @@ k_stencil(DevOp<T> op, const V2<TX>* __restrict__ x, Addr ax, const V2<TF>* __re
       }
       y[gi] = cvt<TY>(out);
     }
+  }
   }
 }
 
@@ -262,17 +284,104 @@ __global__ void k_f2d(const float2* __restrict__ x, double2* __restrict__ y, lon
   if (i < n) y[i] = make_double2(double(x[i].x), double(x[i].y));
 }
 
+// Launch variants of the stencil (tile height, tile order). Every variant computes every
+// output with the same arithmetic in the same order, so the choice never changes a result.
+struct StencilVariant {
+  int byt;
+  bool xcd;
+};
+constexpr StencilVariant kVariants[] = {{4, false}, {4, true}, {8, false}, {8, true}};
+
+template <int P, typename T, typename TX, typename TF, typename TY, int MODE, int BYT, bool XCD>
+void stencil_launch(const DevOp<T>& op, const V2<TX>* x, Addr xs, const V2<TF>* f, Addr fs,
+                    V2<TY>* y, Addr ys, int nbatch, hipStream_t st) {
+  const int nmac = (op.M + P - 1) / P;
+  const int ntiles = ((nmac + BX - 1) / BX) * ((nmac + BYT - 1) / BYT);
+  const int blocks = XCD ? 8 * ((ntiles + 7) / 8) : ntiles;
+  k_stencil<P, T, TX, TF, TY, MODE, BYT, XCD><<<dim3(blocks, nbatch), 256, 0, st>>>(op, x, xs, f, fs, y, ys);
+}
+
+template <int P, typename T, typename TX, typename TF, typename TY, int MODE>
+void stencil_variant(int v, const DevOp<T>& op, const V2<TX>* x, Addr xs, const V2<TF>* f,
+                     Addr fs, V2<TY>* y, Addr ys, int nbatch, hipStream_t st) {
+  // taller tiles only where their LDS stays small (P <= 2)
+  if (v == 1) stencil_launch<P, T, TX, TF, TY, MODE, 4, true>(op, x, xs, f, fs, y, ys, nbatch, st);
+  else if (v == 2 && P <= 2) stencil_launch<P, T, TX, TF, TY, MODE, (P <= 2 ? 8 : 4), false>(op, x, xs, f, fs, y, ys, nbatch, st);
+  else if (v == 3 && P <= 2) stencil_launch<P, T, TX, TF, TY, MODE, (P <= 2 ? 8 : 4), true>(op, x, xs, f, fs, y, ys, nbatch, st);
+  else stencil_launch<P, T, TX, TF, TY, MODE, 4, false>(op, x, xs, f, fs, y, ys, nbatch, st);
+}
+
+// Autotuner: the first launch of a (kernel, lattice size, batch bucket) times every variant
+// on the stream with HIP events (the launch is a pure function of its inputs, so repeating
+// it is harmless) and keeps the fastest for the rest of the process. HZ_TUNE=0 disables it.
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+
+int tuned_variant(const std::string& key, int nvar,
+                  const std::function<void(int)>& launch, hipStream_t st) {
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second;
+  }
+  static const bool enabled = [] {
+    const char* e = std::getenv("HZ_TUNE");
+    return !(e && e[0] == '0');
+  }();
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (!enabled || hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  hipEvent_t a, b;
+  HZ_HIP(hipEventCreate(&a));
+  HZ_HIP(hipEventCreate(&b));
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int v = 0; v < nvar; ++v) {
+    launch(v);                                 // warm
+    float tmin = 1e30f;
+    for (int r = 0; r < 3; ++r) {
+      HZ_HIP(hipEventRecord(a, st));
+      launch(v);
+      HZ_HIP(hipEventRecord(b, st));
+      HZ_HIP(hipEventSynchronize(b));
+      float ms = 0;
+      HZ_HIP(hipEventElapsedTime(&ms, a, b));
+      tmin = std::min(tmin, ms);
+    }
+    if (tmin < best_ms) {
+      best_ms = tmin;
+      best = v;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  static const bool verbose = [] {
+    const char* e = std::getenv("HZ_TUNE_LOG");
+    return e && e[0] == '1';
+  }();
+  if (verbose) std::fprintf(stderr, "hz tune %s: variant %d (%.3f ms)\n", key.c_str(), best, best_ms);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune[key] = best;
+  return best;
+}
+
 template <int P, typename T, typename TX, typename TF, typename TY>
 void stencil_p(int mode, const DevOp<T>& op, const V2<TX>* x, Addr xs, const V2<TF>* f, Addr fs,
                V2<TY>* y, Addr ys, int nbatch, hipStream_t st) {
-  const int nmac = (op.M + P - 1) / P;
-  dim3 grid((nmac + BX - 1) / BX, (nmac + BY - 1) / BY, nbatch);
-  if (mode == ST_APPLY)
-    k_stencil<P, T, TX, TF, TY, ST_APPLY><<<grid, 256, 0, st>>>(op, x, xs, f, fs, y, ys);
-  else if (mode == ST_RESID)
-    k_stencil<P, T, TX, TF, TY, ST_RESID><<<grid, 256, 0, st>>>(op, x, xs, f, fs, y, ys);
-  else
-    k_stencil<P, T, TX, TF, TY, ST_SMOOTH><<<grid, 256, 0, st>>>(op, x, xs, f, fs, y, ys);
+  auto launch = [&](int v) {
+    if (mode == ST_APPLY) stencil_variant<P, T, TX, TF, TY, ST_APPLY>(v, op, x, xs, f, fs, y, ys, nbatch, st);
+    else if (mode == ST_RESID) stencil_variant<P, T, TX, TF, TY, ST_RESID>(v, op, x, xs, f, fs, y, ys, nbatch, st);
+    else stencil_variant<P, T, TX, TF, TY, ST_SMOOTH>(v, op, x, xs, f, fs, y, ys, nbatch, st);
+  };
+  const int nvar = P <= 2 ? 4 : 2;
+  const int bucket = nbatch == 1 ? 1 : nbatch <= 4 ? 4 : nbatch <= 16 ? 16 : 64;
+  const std::string key = "st" + std::to_string(P) + "/" + std::to_string(sizeof(T)) +
+                          std::to_string(sizeof(TX)) + std::to_string(sizeof(TF)) +
+                          std::to_string(sizeof(TY)) + "/" + std::to_string(mode) + "/" +
+                          std::to_string(op.M) + "/" + std::to_string(bucket);
+  launch(tuned_variant(key, nvar, launch, st));
 }
 
 }  // namespace
