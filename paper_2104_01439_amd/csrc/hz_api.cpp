@@ -665,6 +665,9 @@ struct Lockstep {
   clk::time_point t0;
   bool issued = false;
 
+  ~Lockstep() { drop_graphs(); }
+  Lockstep(const Lockstep&) = delete;
+  Lockstep& operator=(const Lockstep&) = delete;
   Lockstep(hz_problem* const* probs_, int nprob_, int nrhs_, const double2* Fb_,
            const long* foff_, double2* Ub_, const long* uoff_, Workspace& ws_,
            const hz_options& o_)
@@ -803,6 +806,117 @@ struct Lockstep {
       h.ptab[cap + z] = mixed ? static_cast<const void*>(pz->fwdAe) : static_cast<const void*>(pz->wdAe);
       h.ptab[2 * cap + z] = pz->cA0;
     }
+    (void)maxnv;
+    if (!use_graphs()) {
+      enqueue_round(na, st);
+      return true;
+    }
+    // the launches of a round depend on its problems and their order only (everything that
+    // changes from round to round is in the uploaded tables): a repeated round replays a
+    // graph captured on its second occurrence
+    std::vector<uintptr_t> sig(1, uintptr_t(na));
+    for (int z = 0; z < na; ++z) sig.push_back(reinterpret_cast<uintptr_t>(probs[zp[z]]));
+    GraphEntry& ge = graphs[sig];
+    if (ge.exec) {
+      HZ_HIP(hipGraphLaunch(ge.exec, st));
+      for (auto& dlt : ge.delta) {
+        dlt.pr->stats.vcycles += dlt.vcycles;
+        dlt.pr->stats.coarse_solves += dlt.launches;
+        dlt.pr->stats.coarse_bytes += dlt.bytes;
+      }
+      return true;
+    }
+    if (ge.seen++ == 0 || !capture_round(ge, na, st)) enqueue_round(na, st);
+    return true;
+  }
+
+  // Graph replay of rounds (HIP stream capture); off when a member records per-launch
+  // device times, or when HZ_GRAPHS=0, or after a capture failed.
+  struct StatDelta {
+    hz_problem* pr;
+    long vcycles, launches;
+    double bytes;
+  };
+  struct GraphEntry {
+    int seen = 0;
+    hipGraphExec_t exec = nullptr;
+    std::vector<StatDelta> delta;
+  };
+  std::map<std::vector<uintptr_t>, GraphEntry> graphs;
+  bool graphs_failed = false;
+
+  bool use_graphs() const {
+    const char* e = std::getenv("HZ_GRAPHS");
+    if ((e && e[0] == '0') || graphs_failed) return false;
+    for (int i = 0; i < nprob; ++i)
+      if (probs[i] && probs[i]->timing) return false;
+    return true;
+  }
+
+  void drop_graphs() {
+    for (auto& g : graphs)
+      if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+    graphs.clear();
+  }
+
+  // Captures this round's launches (recording only: nothing runs during capture), keeps the
+  // executable graph and the counter increments of one round, then launches it.
+  bool capture_round(GraphEntry& ge, int na, hipStream_t st) {
+    if (graphs.size() > 32) {              // many distinct member sets: start over
+      drop_graphs();
+      return false;
+    }
+    std::vector<StatDelta> before;
+    for (int i = 0; i < nprob; ++i)
+      if (probs[i])
+        before.push_back({probs[i], probs[i]->stats.vcycles, probs[i]->stats.coarse_solves,
+                          probs[i]->stats.coarse_bytes});
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      graphs_failed = true;
+      return false;
+    }
+    bool ok = true;
+    try {
+      enqueue_round(na, st);
+    } catch (...) {
+      ok = false;
+    }
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(st, &g) != hipSuccess) ok = false;
+    hipGraphExec_t ex = nullptr;
+    if (ok && g && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) ok = false;
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    // counters were advanced once by the recording pass: keep that as this round's share
+    ge.delta.clear();
+    for (auto& b : before)
+      ge.delta.push_back({b.pr, b.pr->stats.vcycles - b.vcycles,
+                          b.pr->stats.coarse_solves - b.launches,
+                          b.pr->stats.coarse_bytes - b.bytes});
+    if (!ok) {
+      if (ex) (void)hipGraphExecDestroy(ex);
+      for (auto& b : before) {                // the eager round counts them again
+        b.pr->stats.vcycles = b.vcycles;
+        b.pr->stats.coarse_solves = b.launches;
+        b.pr->stats.coarse_bytes = b.bytes;
+      }
+      graphs_failed = true;
+      drop_graphs();
+      return false;
+    }
+    ge.exec = ex;
+    HZ_HIP(hipGraphLaunch(ex, st));
+    return true;
+  }
+
+  // Upload of this round's tables, the round's kernels and the read-back (as built by
+  // issue()).
+  void enqueue_round(int na, hipStream_t st) {
+    const bool mixed = o.prec == HZ_MIXED;
+    const long N = ws->N, cap = ws->cap;
+    const int p = probs[zp[0]]->p, nblk = ws->nblk;
+    const Region d = region_at(dreg(0), ws->cap);
     upload(0, st);
     const long* d_src = d.tab;
     const long* d_vj = d.tab + cap;
@@ -835,16 +949,15 @@ struct Lockstep {
     apply_a0(a0, p, Addr(0, d_zj), Addr(0, d_w), na, st);
     // CGS2: two passes of h = V^H w, w -= V h; then |w|^2
     launch_mdot_b(ws->V, Addr(0, d_vb), N, 64, d.itab, ws->RW, Addr(0, d_w), N, ws->partial, nblk, na, st);
-    launch_reduce_b(ws->partial, nblk, maxnv, d.itab, ws->hbuf, 192, na, st);
+    launch_reduce_b(ws->partial, nblk, 64, d.itab, ws->hbuf, 192, na, st);
     launch_maxpy_b(ws->V, Addr(0, d_vb), N, 64, d.itab, ws->hbuf, 192, ws->RW, Addr(0, d_w), N,
                    nullptr, nblk, na, st);
     launch_mdot_b(ws->V, Addr(0, d_vb), N, 64, d.itab, ws->RW, Addr(0, d_w), N, ws->partial, nblk, na, st);
-    launch_reduce_b(ws->partial, nblk, maxnv, d.itab, ws->hbuf + 64, 192, na, st);
+    launch_reduce_b(ws->partial, nblk, 64, d.itab, ws->hbuf + 64, 192, na, st);
     launch_maxpy_b(ws->V, Addr(0, d_vb), N, 64, d.itab, ws->hbuf + 64, 192, ws->RW, Addr(0, d_w), N,
                    ws->partial, nblk, na, st);
     launch_reduce_b(ws->partial, nblk, 1, nullptr, ws->hbuf + 128, 192, na, st);
     read_back(na, st);
-    return true;
   }
 
   void apply_a0(const DevOp<double>& a0, int p, Addr az, Addr aw, int nb, hipStream_t st) {

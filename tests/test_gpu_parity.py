@@ -295,6 +295,29 @@ def test_batched_edge_cases(hz, torch):
     assert all(r["iterations"] == 4 and r["converged"] == 0 for r in rs)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_graph_replay_equals_eager(hz, torch, prec, monkeypatch):
+    """Rounds replayed from captured HIP graphs give bitwise the eager results, through
+    restarts and through solves leaving a batch (the captured round changes)."""
+    k, n, p = 14.0, 24, 2
+    probs = [hz.Problem(k, 1.0 / n, p, 1 + 1j * b, prec=prec, restart=6) for b in (0.2, 1.1)]
+    Fs = [pr.planewave_rhs(t) for pr in probs for t in (0.4, 2.9)]
+    out = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("HZ_GRAPHS", mode)
+        us, rs = hz.solve_batched(probs, Fs, 2, tol=1e-10)
+        u1, r1 = probs[0].solve(Fs[0], tol=1e-10)
+        out[mode] = (us, rs, u1, r1)
+    monkeypatch.delenv("HZ_GRAPHS")
+    (ua, ra, va, sa), (ub, rb, vb, sb) = out["0"], out["1"]
+    assert len({r["iterations"] for r in ra}) > 1          # solves left the batch at different rounds
+    for q in range(4):
+        assert ra[q]["iterations"] == rb[q]["iterations"]
+        assert torch.equal(ua[q], ub[q])
+    assert sa["iterations"] == sb["iterations"] and sa["hist"] == sb["hist"]
+    assert torch.equal(va, vb)
+
+
 @pytest.mark.parametrize("c", [CASES[2], CASES[4], CASES[6]])
 def test_coarse_solve_per_step_launches(hz, torch, c, monkeypatch):
     """The non-persistent path (one launch per block row) gives the same coarse solve."""
