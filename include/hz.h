@@ -91,6 +91,7 @@ typedef struct {
   double coarse_bytes;       /* algorithmic bytes of those launches: each solved system's
                                 factor read twice (last block once) plus 3 coarse vectors
                                 per right-hand side                                         */
+  long graph_rounds;         /* FGMRES rounds replayed from a captured HIP graph           */
 } hz_stats;
 
 /* Operators exposed by hz_apply (parity hooks; all act on the problem's own data). */

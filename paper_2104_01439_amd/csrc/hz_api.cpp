@@ -9,6 +9,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <condition_variable>
@@ -533,56 +534,70 @@ template <> const float2* coarse_coef_of<float>(const hz_problem* pr) { return p
 // solves of one problem form one coarse job of up to 4 right-hand sides), input f + af.at(b),
 // output z + az.at(b); fine gives the per-solve operators. The iterates live in scratch
 // (stride N, coarse stride Nc); gb holds nb coarse forward-sweep buffers (stride Nc).
+enum VcPhase { VC_PRE = 1, VC_COARSE = 2, VC_POST = 4, VC_ALL = 7 };
+
 template <typename T>
 void vcycle_group(hz_problem* const* probs, const int* zp, int nb, const DevOp<T>& fine,
                   const T* rw, const Scratch<T>& sc, V2<T>* gb, const V2<T>* f, Addr af,
-                  V2<T>* z, Addr az, hipStream_t st) {
+                  V2<T>* z, Addr az, hipStream_t st, int phases = VC_ALL) {
   hz_problem* pr0 = probs[zp[0]];
   const int p = pr0->p, nu = pr0->opt.nu;
   const long N = pr0->N, Nc = pr0->Nc;
   if (nb > sc.cap) throw std::runtime_error("V-cycle batch exceeds its scratch");
-  // coarse jobs: runs of solves of one problem, at most the LDS group size per job
-  const int grp = coarse_group<T>(pr0->L);
-  std::vector<CoarseJob<T>> jobs;
-  for (int b0 = 0; b0 < nb;) {
-    int b1 = b0;
-    while (b1 < nb && zp[b1] == zp[b0] && b1 - b0 < grp) ++b1;
-    hz_problem* pi = probs[zp[b0]];
-    pi->stats.vcycles += b1 - b0;
-    CoarseJob<T> j;
-    j.S = factor_of<T>(pi);
-    j.coef = coarse_coef_of<T>(pi);
-    j.b = sc.rc + b0 * Nc;
-    j.y = sc.ec + b0 * Nc;
-    j.gbuf = gb + b0 * Nc;
-    j.nrhs = b1 - b0;
-    jobs.push_back(j);
-    b0 = b1;
-  }
-  if (nu == 0) {
-    // u = 0: the cycle is the coarse correction alone, z = P A_c^{-1} P^T f
-    launch_restrict<T>(p, pr0->M, pr0->Mc, rw, f, sc.rc, nb, af, Addr(Nc), st);
-    timed_coarse_jobs<T>(pr0, jobs.data(), int(jobs.size()), st);
-    launch_prolong<T>(p, pr0->M, pr0->Mc, rw, sc.ec, z, false, nb, az, Addr(Nc), st);
-    return;
-  }
-  V2<T>* cur = sc.ua;
-  V2<T>* nxt = sc.ub;
-  launch_jacobi0<T, T>(p, fine, f, af, cur, Addr(N), nb, st);
-  for (int sw = 1; sw < nu; ++sw) {
-    launch_stencil<T, T, T, T>(p, ST_SMOOTH, fine, cur, Addr(N), f, af, nxt, Addr(N), nb, st);
-    std::swap(cur, nxt);
-  }
-  launch_stencil<T, T, T, T>(p, ST_RESID, fine, cur, Addr(N), f, af, sc.rf, Addr(N), nb, st);
-  launch_restrict<T>(p, pr0->M, pr0->Mc, rw, sc.rf, sc.rc, nb, Addr(N), Addr(Nc), st);
-  timed_coarse_jobs<T>(pr0, jobs.data(), int(jobs.size()), st);
-  launch_prolong<T>(p, pr0->M, pr0->Mc, rw, sc.ec, cur, true, nb, Addr(N), Addr(Nc), st);
-  for (int sw = 0; sw < nu; ++sw) {
-    if (sw == nu - 1) {
-      launch_stencil<T, T, T, T>(p, ST_SMOOTH, fine, cur, Addr(N), f, af, z, az, nb, st);
+  // buffers: jacobi0 writes ua, each further sweep alternates, so after nu - 1 sweeps the
+  // iterate is in ua (nu odd) or ub (nu even)
+  V2<T>* cur = (nu % 2 == 1) ? sc.ua : sc.ub;
+  V2<T>* nxt = (nu % 2 == 1) ? sc.ub : sc.ua;
+  if (phases & VC_PRE) {
+    if (nu == 0) {
+      // u = 0: the cycle is the coarse correction alone, z = P A_c^{-1} P^T f
+      launch_restrict<T>(p, pr0->M, pr0->Mc, rw, f, sc.rc, nb, af, Addr(Nc), st);
     } else {
-      launch_stencil<T, T, T, T>(p, ST_SMOOTH, fine, cur, Addr(N), f, af, nxt, Addr(N), nb, st);
-      std::swap(cur, nxt);
+      V2<T>* c = sc.ua;
+      V2<T>* x = sc.ub;
+      launch_jacobi0<T, T>(p, fine, f, af, c, Addr(N), nb, st);
+      for (int sw = 1; sw < nu; ++sw) {
+        launch_stencil<T, T, T, T>(p, ST_SMOOTH, fine, c, Addr(N), f, af, x, Addr(N), nb, st);
+        std::swap(c, x);
+      }
+      launch_stencil<T, T, T, T>(p, ST_RESID, fine, c, Addr(N), f, af, sc.rf, Addr(N), nb, st);
+      launch_restrict<T>(p, pr0->M, pr0->Mc, rw, sc.rf, sc.rc, nb, Addr(N), Addr(Nc), st);
+    }
+  }
+  if (phases & VC_COARSE) {
+    // coarse jobs: runs of solves of one problem, at most the LDS group size per job
+    const int grp = coarse_group<T>(pr0->L);
+    std::vector<CoarseJob<T>> jobs;
+    for (int b0 = 0; b0 < nb;) {
+      int b1 = b0;
+      while (b1 < nb && zp[b1] == zp[b0] && b1 - b0 < grp) ++b1;
+      hz_problem* pi = probs[zp[b0]];
+      pi->stats.vcycles += b1 - b0;
+      CoarseJob<T> j;
+      j.S = factor_of<T>(pi);
+      j.coef = coarse_coef_of<T>(pi);
+      j.b = sc.rc + b0 * Nc;
+      j.y = sc.ec + b0 * Nc;
+      j.gbuf = gb + b0 * Nc;
+      j.nrhs = b1 - b0;
+      jobs.push_back(j);
+      b0 = b1;
+    }
+    timed_coarse_jobs<T>(pr0, jobs.data(), int(jobs.size()), st);
+  }
+  if (phases & VC_POST) {
+    if (nu == 0) {
+      launch_prolong<T>(p, pr0->M, pr0->Mc, rw, sc.ec, z, false, nb, az, Addr(Nc), st);
+      return;
+    }
+    launch_prolong<T>(p, pr0->M, pr0->Mc, rw, sc.ec, cur, true, nb, Addr(N), Addr(Nc), st);
+    for (int sw = 0; sw < nu; ++sw) {
+      if (sw == nu - 1) {
+        launch_stencil<T, T, T, T>(p, ST_SMOOTH, fine, cur, Addr(N), f, af, z, az, nb, st);
+      } else {
+        launch_stencil<T, T, T, T>(p, ST_SMOOTH, fine, cur, Addr(N), f, af, nxt, Addr(N), nb, st);
+        std::swap(cur, nxt);
+      }
     }
   }
 }
@@ -665,7 +680,10 @@ struct Lockstep {
   clk::time_point t0;
   bool issued = false;
 
-  ~Lockstep() { drop_graphs(); }
+  ~Lockstep() {
+    drop_graphs();
+    if (cap_st) (void)hipStreamDestroy(cap_st);
+  }
   Lockstep(const Lockstep&) = delete;
   Lockstep& operator=(const Lockstep&) = delete;
   Lockstep(hz_problem* const* probs_, int nprob_, int nrhs_, const double2* Fb_,
@@ -808,7 +826,7 @@ struct Lockstep {
     }
     (void)maxnv;
     if (!use_graphs()) {
-      enqueue_round(na, st);
+      enqueue_round(na, st, VC_ALL);
       return true;
     }
     // the launches of a round depend on its problems and their order only (everything that
@@ -817,114 +835,137 @@ struct Lockstep {
     std::vector<uintptr_t> sig(1, uintptr_t(na));
     for (int z = 0; z < na; ++z) sig.push_back(reinterpret_cast<uintptr_t>(probs[zp[z]]));
     GraphEntry& ge = graphs[sig];
-    if (ge.exec) {
-      HZ_HIP(hipGraphLaunch(ge.exec, st));
-      for (auto& dlt : ge.delta) {
-        dlt.pr->stats.vcycles += dlt.vcycles;
-        dlt.pr->stats.coarse_solves += dlt.launches;
-        dlt.pr->stats.coarse_bytes += dlt.bytes;
-      }
+    if (ge.pre) {
+      // the coarse solve is a cooperative launch, which stream capture does not take: it
+      // runs directly between the two captured halves of the round
+      HZ_HIP(hipGraphLaunch(ge.pre, st));
+      enqueue_round(na, st, VC_COARSE);
+      HZ_HIP(hipGraphLaunch(ge.post, st));
+      probs[zp[0]]->stats.graph_rounds += 1;
       return true;
     }
-    if (ge.seen++ == 0 || !capture_round(ge, na, st)) enqueue_round(na, st);
+    if (ge.seen++ == 0 || !capture_round(ge, na, st)) enqueue_round(na, st, VC_ALL);
     return true;
   }
 
-  // Graph replay of rounds (HIP stream capture); off when a member records per-launch
-  // device times, or when HZ_GRAPHS=0, or after a capture failed.
-  struct StatDelta {
-    hz_problem* pr;
-    long vcycles, launches;
-    double bytes;
-  };
+  // Graph replay of rounds (HIP stream capture), opt-in with HZ_GRAPHS=1 (measured slower
+  // than direct launches for these rounds); off when a member records per-launch device
+  // times or after a capture failed.
   struct GraphEntry {
     int seen = 0;
-    hipGraphExec_t exec = nullptr;
-    std::vector<StatDelta> delta;
+    hipGraphExec_t pre = nullptr, post = nullptr;
   };
   std::map<std::vector<uintptr_t>, GraphEntry> graphs;
   bool graphs_failed = false;
 
   bool use_graphs() const {
     const char* e = std::getenv("HZ_GRAPHS");
-    if ((e && e[0] == '0') || graphs_failed) return false;
+    if (!(e && e[0] == '1') || graphs_failed) return false;
     for (int i = 0; i < nprob; ++i)
       if (probs[i] && probs[i]->timing) return false;
     return true;
   }
 
   void drop_graphs() {
-    for (auto& g : graphs)
-      if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+    for (auto& g : graphs) {
+      if (g.second.pre) (void)hipGraphExecDestroy(g.second.pre);
+      if (g.second.post) (void)hipGraphExecDestroy(g.second.post);
+    }
     graphs.clear();
   }
 
-  // Captures this round's launches (recording only: nothing runs during capture), keeps the
-  // executable graph and the counter increments of one round, then launches it.
+  // Captures the launches of one half of a round (recording only: nothing runs).
+  // Capture runs on a private stream (the caller's may be the null stream, which cannot be
+  // captured); only recording happens there, the graphs run on the caller's stream.
+  hipStream_t cap_st = nullptr;
+  hipGraphExec_t capture_half(int na, int phases, hipStream_t) {
+    const char* lg = std::getenv("HZ_GRAPHS_LOG");
+    const bool verbose = lg && lg[0] == '1';
+    if (!cap_st && hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      cap_st = nullptr;
+      return nullptr;
+    }
+    hipStream_t st = cap_st;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      if (verbose) std::fprintf(stderr, "hz graphs: begin capture: %s\n", hipGetErrorString(e));
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    bool ok = true;
+    try {
+      enqueue_round(na, st, phases);
+    } catch (const HipError& he) {
+      if (verbose)
+        std::fprintf(stderr, "hz graphs: %s during capture: %s\n", he.where.c_str(),
+                     hipGetErrorString(he.e));
+      ok = false;
+    } catch (...) {
+      ok = false;
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(st, &g);
+    if (e != hipSuccess) {
+      if (verbose) std::fprintf(stderr, "hz graphs: end capture: %s\n", hipGetErrorString(e));
+      ok = false;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (ok && g) {
+      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        if (verbose) std::fprintf(stderr, "hz graphs: instantiate: %s\n", hipGetErrorString(e));
+        ok = false;
+        ex = nullptr;
+      }
+    }
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    if (!ok && ex) {
+      (void)hipGraphExecDestroy(ex);
+      ex = nullptr;
+    }
+    return ex;
+  }
+
+  // Captures the two halves of this round around its coarse solve and runs the round from
+  // them; false (nothing run) if capture is not available.
   bool capture_round(GraphEntry& ge, int na, hipStream_t st) {
     if (graphs.size() > 32) {              // many distinct member sets: start over
       drop_graphs();
       return false;
     }
-    std::vector<StatDelta> before;
-    for (int i = 0; i < nprob; ++i)
-      if (probs[i])
-        before.push_back({probs[i], probs[i]->stats.vcycles, probs[i]->stats.coarse_solves,
-                          probs[i]->stats.coarse_bytes});
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-      (void)hipGetLastError();
-      graphs_failed = true;
-      return false;
-    }
-    bool ok = true;
-    try {
-      enqueue_round(na, st);
-    } catch (...) {
-      ok = false;
-    }
-    hipGraph_t g = nullptr;
-    if (hipStreamEndCapture(st, &g) != hipSuccess) ok = false;
-    hipGraphExec_t ex = nullptr;
-    if (ok && g && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) ok = false;
-    if (g) (void)hipGraphDestroy(g);
-    (void)hipGetLastError();
-    // counters were advanced once by the recording pass: keep that as this round's share
-    ge.delta.clear();
-    for (auto& b : before)
-      ge.delta.push_back({b.pr, b.pr->stats.vcycles - b.vcycles,
-                          b.pr->stats.coarse_solves - b.launches,
-                          b.pr->stats.coarse_bytes - b.bytes});
-    if (!ok) {
-      if (ex) (void)hipGraphExecDestroy(ex);
-      for (auto& b : before) {                // the eager round counts them again
-        b.pr->stats.vcycles = b.vcycles;
-        b.pr->stats.coarse_solves = b.launches;
-        b.pr->stats.coarse_bytes = b.bytes;
-      }
+    hipGraphExec_t pre = capture_half(na, VC_PRE, st);
+    hipGraphExec_t post = pre ? capture_half(na, VC_POST, st) : nullptr;
+    if (!pre || !post) {
+      if (pre) (void)hipGraphExecDestroy(pre);
       graphs_failed = true;
       drop_graphs();
       return false;
     }
-    ge.exec = ex;
-    HZ_HIP(hipGraphLaunch(ex, st));
+    ge.pre = pre;
+    ge.post = post;
+    HZ_HIP(hipGraphLaunch(pre, st));
+    enqueue_round(na, st, VC_COARSE);
+    HZ_HIP(hipGraphLaunch(post, st));
     return true;
   }
 
   // Upload of this round's tables, the round's kernels and the read-back (as built by
   // issue()).
-  void enqueue_round(int na, hipStream_t st) {
+  void enqueue_round(int na, hipStream_t st, int phases) {
     const bool mixed = o.prec == HZ_MIXED;
     const long N = ws->N, cap = ws->cap;
     const int p = probs[zp[0]]->p, nblk = ws->nblk;
     const Region d = region_at(dreg(0), ws->cap);
-    upload(0, st);
+    if (phases & VC_PRE) upload(0, st);
     const long* d_src = d.tab;
     const long* d_vj = d.tab + cap;
     const long* d_vb = d.tab + 2 * cap;
     const long* d_zj = d.tab + 3 * cap;
     const long* d_w = d.tab + 4 * cap;
     // v_j = r / beta (cycle start) or w / h_{j,j-1}
-    launch_scale_b(ws->RW, Addr(0, d_src), d.scl, ws->V, Addr(0, d_vj), N, na, st);
+    if (phases & VC_PRE) launch_scale_b(ws->RW, Addr(0, d_src), d.scl, ws->V, Addr(0, d_vj), N, na, st);
     // z_j = V-cycle(v_j) for every unfinished solve at once
     hz_problem* pr0 = probs[zp[0]];
     if (!mixed) {
@@ -933,16 +974,17 @@ struct Lockstep {
                          reinterpret_cast<const double2* const*>(d.ptab + cap)};
       vcycle_group<double>(probs, zp.data(), na, fine, pr0->rw, ws->s64,
                            static_cast<double2*>(ws->gb), ws->V, Addr(0, d_vj), ws->Zd,
-                           Addr(0, d_zj), st);
+                           Addr(0, d_zj), st, phases);
     } else {
       DevOp<float> fine{nullptr, nullptr, pr0->M,
                         reinterpret_cast<const float2* const*>(d.ptab),
                         reinterpret_cast<const float2* const*>(d.ptab + cap)};
-      launch_d2f_b(ws->V, Addr(0, d_vj), ws->s32.ff, Addr(N), N, na, st);
+      if (phases & VC_PRE) launch_d2f_b(ws->V, Addr(0, d_vj), ws->s32.ff, Addr(N), N, na, st);
       vcycle_group<float>(probs, zp.data(), na, fine, pr0->frw, ws->s32,
                           static_cast<float2*>(ws->gb), ws->s32.ff, Addr(N), ws->Zf,
-                          Addr(0, d_zj), st);
+                          Addr(0, d_zj), st, phases);
     }
+    if (!(phases & VC_POST)) return;
     // w = A_0 z_j
     const DevOp<double> a0{nullptr, nullptr, pr0->M, reinterpret_cast<const double2* const*>(d.ptab + 2 * cap),
                            nullptr};

@@ -303,12 +303,17 @@ def test_graph_replay_equals_eager(hz, torch, prec, monkeypatch):
     probs = [hz.Problem(k, 1.0 / n, p, 1 + 1j * b, prec=prec, restart=6) for b in (0.2, 1.1)]
     Fs = [pr.planewave_rhs(t) for pr in probs for t in (0.4, 2.9)]
     out = {}
+    replays = {}
     for mode in ("0", "1"):
         monkeypatch.setenv("HZ_GRAPHS", mode)
+        probs[0].stats(reset=True)
         us, rs = hz.solve_batched(probs, Fs, 2, tol=1e-10)
         u1, r1 = probs[0].solve(Fs[0], tol=1e-10)
         out[mode] = (us, rs, u1, r1)
+        replays[mode] = probs[0].stats()["graph_rounds"]
     monkeypatch.delenv("HZ_GRAPHS")
+    _log(f"  rounds replayed from graphs: {replays}")
+    assert replays["0"] == 0 and replays["1"] > 0
     (ua, ra, va, sa), (ub, rb, vb, sb) = out["0"], out["1"]
     assert len({r["iterations"] for r in ra}) > 1          # solves left the batch at different rounds
     for q in range(4):
