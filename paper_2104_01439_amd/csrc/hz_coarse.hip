@@ -9,6 +9,7 @@
 // S_j is formed explicitly by blocked Gauss-Jordan; the rank-NB updates run on FP64 MFMA.
 // Solve:  g_j = S_j (b_j - A_{j,j-1} g_{j-1}),   x_j = g_j - S_j (A_{j,j+1} x_{j+1}).
 
+#include <type_traits>
 #include <stdexcept>
 
 #include "hz_common.h"
@@ -496,6 +497,29 @@ __device__ __forceinline__ void gather_block(const V2<T>* src, long sstride, int
   }
 }
 
+// Sum over each row of 16 lanes (every lane of the row gets it): a butterfly of lane
+// permutations within the row (mirror, half mirror, then the two quad exchanges), each step
+// moving the two 32-bit halves of a value with DPP.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(bits), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(bits >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <typename T>
+__device__ __forceinline__ T row16_sum(T v) {
+  v += dpp_move<0x140>(v);   // row_mirror: lane i <- 15 - i
+  v += dpp_move<0x141>(v);   // row_half_mirror: lane i <- 7 - i within each half row
+  v += dpp_move<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  return v;
+}
+
 // 512 threads. Waves 0-1 ("exchange waves") gather neighbour results (polling) into LDS and
 // publish the results; while a step computes they stage the next step's right-hand side
 // (or zeros) into the LDS buffer the step no longer needs, so the two buffers swap roles from
@@ -503,16 +527,29 @@ __device__ __forceinline__ void gather_block(const V2<T>* src, long sstride, int
 // block into t. Waves 2-7 ("stream waves") form rows of S_j t: stream wave sw owns row group
 // sw / CG (RW rows of each chunk of RG * RW rows) and column half sw % CG, each lane QW
 // columns per chunk, so that one chunk covers the block rows of a workgroup and all of its
-// factor loads are in flight at once; they are issued right after the previous step's last
-// chunk was consumed. Per row the sum runs over the lane's columns in ascending order, then
-// across the wave, then over the column halves, for any number of right-hand sides.
+// factor loads are in flight at once. Factor loads are issued while the waves would wait for
+// the exchange: right after the previous step's last chunk was consumed, and where a step is
+// one chunk, a part of them two steps ahead. Per row the sum runs over the lane's columns in
+// ascending order, then over each row of 16 lanes (row16_sum), then over the column halves
+// and the four rows of lanes in order, for any number of right-hand sides.
 constexpr int NSW = 6;                 // stream waves
 constexpr int CSOL_CG = 2, CSOL_RG = 3, CSOL_RW = 3, CSOL_QW = 9;
+
+// Column groups per chunk requested two steps ahead when a step is one chunk: as many as the
+// registers left beside a chunk and the accumulators hold.
+template <typename T, int NR>
+constexpr bool csolve_one_ok() {   // registers for a chunk, the early columns and start values
+  return !(sizeof(T) == 8 && NR >= 4);
+}
+template <typename T, int NR>
+constexpr int csolve_early() {
+  return sizeof(T) == 8 ? (NR == 1 ? 6 : 3) : (NR <= 2 ? 9 : 6);
+}
 
 template <int P, typename T, int NR>
 __global__ void __launch_bounds__(512)
 k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cstride,
-         int* __restrict__ err) {
+         int one, int* __restrict__ err) {
   // workgroups [jb Gp, (jb + 1) Gp) serve job jb (one coarse system and its right-hand sides)
   const int jb = blockIdx.x / Gp;
   const CoarseJob<T>* job = &jobs.j[jb];
@@ -531,7 +568,7 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
   V2<T>* cl = reinterpret_cast<V2<T>*>(smem);  // coefficient table
   V2<T>* buf0 = cl + NCOEF;                    // two [NR][nmax] buffers: t and neighbour
   V2<T>* buf1 = buf0 + NR * nmax;
-  __shared__ T red[2][CG][RCH][NR];
+  __shared__ T red[2][CG][4][RCH][NR];      // partial row sums per column half and row of 16 lanes
   const int G = Gp, g = blockIdx.x - jb * Gp;
   // wave-uniform (scalar) role index: the two roles run separate code
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -542,7 +579,7 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
   for (int i = threadIdx.x; i < NCOEF; i += 512) cl[i] = coef[i];
 
   // exchange waves: dst[h][c] = b_j (forward steps) or 0, c < nj, in slices of 128 EH
-  auto stage = [&](const StepPlan& q, V2<T>* dst) {
+  auto stage = [&](const StepPlan& q, V2<T>* dst) __attribute__((always_inline)) {
     const long d0 = long(P) * q.j * Mc;
     for (int c0 = 0; c0 < q.nj; c0 += 128 * EH) {
       V2<T> v[NR][EH];
@@ -566,7 +603,8 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
   // t += sgn * A_{j,jn} y_jn for every right-hand side; run by all 512 threads (each role
   // calls it from its own loop, so that the two roles never share a code path: a wait for
   // outstanding loads at a shared join would hold the stream waves' prefetch)
-  auto fold = [&](const StepPlan& pl, int jn, T sgn, V2<T>* t, const V2<T>* yn) {
+  auto fold = [&](const StepPlan& pl, int jn, T sgn, V2<T>* t, const V2<T>* yn)
+                  __attribute__((always_inline)) {
     for (int h = 0; h < nrhs; ++h)
       for (int c = threadIdx.x; c < pl.nj; c += 512) {
         const V2<T> cp = coupling<P, T>(c, pl.j, jn, nc, Mc, cl, yn + h * nmax);
@@ -577,6 +615,197 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
       }
   };
 
+  if constexpr (csolve_one_ok<T, NR>()) {
+  if (one) {
+    // ---------------- every step is one chunk ----------------
+    // The exchange waves request a step's start value (b_j or 0) into registers before they
+    // poll for its neighbour rows and write it into t once the rows are in; the rows are
+    // published by the first stream wave right after the row sums are complete, so the
+    // exchange waves only poll. Columns q < QE of a chunk are requested two steps ahead,
+    // while the previous step still waits for its neighbour; the other columns once the
+    // previous step's product is formed. Early columns of even steps (counted from s_begin)
+    // live in B, those of odd steps in A[.][q < QE]; late columns in A[.][q >= QE]. Both
+    // roles pass the same barriers in the same order.
+    V2<T>* t = buf0;
+    V2<T>* yn = buf1;
+    // the folds of a step, between the same barriers for both roles
+    auto fold_step = [&](const StepPlan& pl, bool exch) __attribute__((always_inline)) {
+      if (pl.jpre >= 0) {
+        __syncthreads();
+        fold(pl, pl.jpre, T(-1), t, yn);
+        __syncthreads();
+        if (exch && pl.active && pl.jfly >= 0)
+          gather_block<P, T, NR, EH>(gbuf, Nc, pl.jfly, nc, Mc, nrhs, nmax, yn, threadIdx.x, err);
+      }
+      __syncthreads();
+      if (pl.active) {
+        if (pl.jfly >= 0) fold(pl, pl.jfly, pl.fwd ? T(-1) : T(1), t, yn);
+        __syncthreads();
+      }
+    };
+    if (wave < 2) {
+      // ---- exchange waves: start values and neighbour rows of each step ----
+      constexpr int NRE = NR <= 2 ? NR : 1, EHE = NR <= 2 ? EH : 1;   // registers permitting
+      for (int s = s_begin; s < s_end; ++s) {
+        const StepPlan pl = make_plan<P>(s, g, G, nc, Mc);
+        const long d0 = long(P) * pl.j * Mc;
+        V2<T> bv[NRE][EHE];
+        if constexpr (NR <= 2) {
+#pragma unroll
+          for (int h = 0; h < NR; ++h)
+#pragma unroll
+            for (int e = 0; e < EH; ++e) {
+              const int c = threadIdx.x + 128 * e;
+              bv[h][e] = (pl.active && pl.fwd && h < nrhs && c < pl.nj)
+                             ? b[h * cstride + d0 + c] : czero<T>();
+            }
+        }
+        if (pl.active) {
+          if (pl.jpre >= 0)
+            gather_block<P, T, NR, EH>(gbuf, Nc, pl.jpre, nc, Mc, nrhs, nmax, yn, threadIdx.x,
+                                       err);
+          else if (pl.jfly >= 0)
+            gather_block<P, T, NR, EH>(pl.fwd ? gbuf : y, pl.fwd ? Nc : cstride, pl.jfly, nc, Mc,
+                                       nrhs, nmax, yn, threadIdx.x, err);
+          if constexpr (NR <= 2) {
+#pragma unroll
+            for (int h = 0; h < NR; ++h)
+#pragma unroll
+              for (int e = 0; e < EH; ++e) {
+                const int c = threadIdx.x + 128 * e;
+                if (h < nrhs && c < pl.nj) t[h * nmax + c] = bv[h][e];
+              }
+          } else {
+            stage(pl, t);
+          }
+        }
+        fold_step(pl, true);
+        __syncthreads();               // the row sums are complete
+      }
+    } else {
+      // ---- stream waves ----
+      constexpr int QE = csolve_early<T, NR>();
+      V2<T> A[RW][QW];
+      V2<T> B[RW][QE > 0 ? QE : 1];
+      struct Tile { const V2<T>* Sj; int rw0, r1, nj, c0, c1; };
+      auto tile_of = [&](int s2) __attribute__((always_inline)) {
+        Tile tl{S, 0, 0, 0, 0, 0};
+        if (s2 < s_end) {
+          const StepPlan pn = make_plan<P>(s2, g, G, nc, Mc);
+          if (pn.active && pn.r1 > pn.r0) {
+            tl.Sj = S + size_t(pn.j) * bsz;
+            tl.rw0 = pn.r0 + rg * RW;
+            tl.r1 = pn.r1;
+            tl.nj = pn.nj;
+            tl.c0 = (pn.nj * cg) / CG;
+            tl.c1 = (pn.nj * (cg + 1)) / CG;
+          }
+        }
+        return tl;
+      };
+      // the publishing lanes: row rr = lane / NR of the chunk, right-hand side lane % NR
+      const bool publisher = sw == 0 && lane < RCH * NR;
+#define HZ_LOAD_COLS(DST, QLO, QHI, TL)                                                      \
+  _Pragma("unroll") for (int i = 0; i < RW; ++i)                                             \
+  _Pragma("unroll") for (int q = QLO; q < QHI; ++q) {                                        \
+    const int c = TL.c0 + lane + 64 * q;                                                     \
+    DST[i][q] = (TL.rw0 + i < TL.r1 && c < TL.c1) ? TL.Sj[size_t(TL.rw0 + i) * TL.nj + c]    \
+                                                   : czero<T>();                             \
+  }
+      {
+        const Tile t0 = tile_of(s_begin), t1 = tile_of(s_begin + 1);
+        if constexpr (QE > 0) { HZ_LOAD_COLS(B, 0, QE, t0) }
+        HZ_LOAD_COLS(A, QE, QW, t0)
+        if constexpr (QE > 0) { HZ_LOAD_COLS(A, 0, QE, t1) }
+      }
+      // one step; the parity of the step decides which registers hold its early columns
+      auto step = [&](int s, auto even_c) __attribute__((always_inline)) {
+        constexpr bool EVEN = decltype(even_c)::value;
+        const StepPlan pl = make_plan<P>(s, g, G, nc, Mc);
+        const int nj = pl.nj;
+        fold_step(pl, false);
+        const int r0 = pl.r0, r1 = pl.r1;
+        // backwards, the forward result of the row this lane publishes (requested before the
+        // product, so that it has arrived when the row sums are complete)
+        const int pr = r0 + lane / NR, ph = lane % NR;
+        const bool pub = publisher && pr < r1 && ph < nrhs;
+        const V2<T> gprev = (pub && !pl.fwd)
+                                ? ld_coh<T>(gbuf + ph * Nc + long(P) * pl.j * Mc + pr)
+                                : czero<T>();
+        if (r1 > r0) {
+          const int c0 = (nj * cg) / CG, c1 = (nj * (cg + 1)) / CG;
+          T ar[RW][NR], ai[RW][NR];
+#pragma unroll
+          for (int i = 0; i < RW; ++i)
+#pragma unroll
+            for (int h = 0; h < NR; ++h) { ar[i][h] = T(0); ai[i][h] = T(0); }
+#pragma unroll
+          for (int q = 0; q < QW; ++q) {
+            const int c = c0 + lane + 64 * q;
+            if (c >= c1) continue;
+#pragma unroll
+            for (int h = 0; h < NR; ++h) {
+              if (h >= nrhs) continue;
+              const V2<T> tv = t[h * nmax + c];
+#pragma unroll
+              for (int i = 0; i < RW; ++i) {
+                const V2<T> sv = (EVEN && q < QE) ? B[i][q < QE ? q : 0] : A[i][q];
+                ar[i][h] += sv.x * tv.x - sv.y * tv.y;
+                ai[i][h] += sv.x * tv.y + sv.y * tv.x;
+              }
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < RW; ++i)
+#pragma unroll
+            for (int h = 0; h < NR; ++h) {
+              const T sr = row16_sum(ar[i][h]), si = row16_sum(ai[i][h]);
+              if ((lane & 15) == 0) {
+                red[0][cg][lane >> 4][rg * RW + i][h] = sr;
+                red[1][cg][lane >> 4][rg * RW + i][h] = si;
+              }
+            }
+        }
+        __syncthreads();                 // the row sums are complete
+        if (pub) {
+          const int rr = lane / NR;
+          T sr = red[0][0][0][rr][ph], si = red[1][0][0][rr][ph];
+#pragma unroll
+          for (int k = 0; k < CG; ++k)
+#pragma unroll
+            for (int u = (k == 0 ? 1 : 0); u < 4; ++u) {
+              sr += red[0][k][u][rr][ph];
+              si += red[1][k][u][rr][ph];
+            }
+          // forward rows go to gbuf (the middle block's straight to y); backward rows are
+          // the forward result minus the sum
+          V2<T> o;
+          o.x = pl.fwd ? sr : gprev.x - sr;
+          o.y = pl.fwd ? si : gprev.y - si;
+          V2<T>* dst = (pl.fwd && !pl.mid) ? gbuf + ph * Nc : y + ph * cstride;
+          st_coh<T>(dst + long(P) * pl.j * Mc + pr, o);
+        }
+        // requests for the steps ahead, issued while the exchange waves poll: the late
+        // columns of the next step and the early columns of the one after, into the
+        // registers this step freed
+        {
+          const Tile tn = tile_of(s + 1);
+          HZ_LOAD_COLS(A, QE, QW, tn)
+        }
+        if constexpr (QE > 0) {
+          const Tile tnn = tile_of(s + 2);
+          if constexpr (EVEN) { HZ_LOAD_COLS(B, 0, QE, tnn) } else { HZ_LOAD_COLS(A, 0, QE, tnn) }
+        }
+      };
+#undef HZ_LOAD_COLS
+      for (int s = s_begin; s < s_end; s += 2) {
+        step(s, std::true_type{});
+        if (s + 1 < s_end) step(s + 1, std::false_type{});
+      }
+    }
+    return;
+  }
+  }
   if (wave < 2) {
     // ---------------- exchange waves ----------------
     bool staged = false;             // t already holds this step's start value
@@ -625,12 +854,14 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
           const int rr = threadIdx.x / NR, h = threadIdx.x % NR;
           const int r = rb + rr;
           if (r < pl.r1 && h < nrhs) {
-            T sr = red[0][0][rr][h], si = red[1][0][rr][h];
+            T sr = red[0][0][0][rr][h], si = red[1][0][0][rr][h];
 #pragma unroll
-            for (int k = 1; k < CG; ++k) {
-              sr += red[0][k][rr][h];
-              si += red[1][k][rr][h];
-            }
+            for (int k = 0; k < CG; ++k)
+#pragma unroll
+              for (int u = (k == 0 ? 1 : 0); u < 4; ++u) {
+                sr += red[0][k][u][rr][h];
+                si += red[1][k][u][rr][h];
+              }
             V2<T> o;
             if (pl.fwd) {
               o.x = sr;
@@ -716,8 +947,11 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
         for (int i = 0; i < RW; ++i)
 #pragma unroll
           for (int h = 0; h < NR; ++h) {
-            const T sr = wave_sum(ar[i][h]), si = wave_sum(ai[i][h]);
-            if (lane == 0) { red[0][cg][rg * RW + i][h] = sr; red[1][cg][rg * RW + i][h] = si; }
+            const T sr = row16_sum(ar[i][h]), si = row16_sum(ai[i][h]);
+            if ((lane & 15) == 0) {
+              red[0][cg][lane >> 4][rg * RW + i][h] = sr;
+              red[1][cg][lane >> 4][rg * RW + i][h] = si;
+            }
           }
         __syncthreads();                 // the exchange waves combine and publish ...
         const bool last = rb + RCH >= r1;
@@ -755,7 +989,7 @@ constexpr size_t kLdsPerWorkgroup = 160 * 1024;   // gfx950
 template <int P, typename T, int NR>
 constexpr size_t csolve_lds(int Mc) {
   return (size_t(P * P * 9 * (2 * P + 1) * (2 * P + 1)) + 2 * size_t(P) * Mc * NR) * sizeof(V2<T>) +
-         sizeof(T) * 2 * CSOL_CG * CSOL_RG * CSOL_RW * NR;
+         sizeof(T) * 2 * CSOL_CG * 4 * CSOL_RG * CSOL_RW * NR;
 }
 
 template <int P, typename T, int NR>
@@ -793,17 +1027,21 @@ void csolve_launch(const CoarseLayout& L, const CsJobs<T>& jobs, int njobs, long
   int Gp = 2 * Gh;
   const int G = njobs * Gp;
   const bool persistent = coop && allow_persistent && max_coresident >= G;
+  // every step's rows of a workgroup form one chunk of the stream waves
+  constexpr int RCH = CSOL_RG * CSOL_RW;
+  int one = csolve_one_ok<T, NR>() && (n0 + Gh - 1) / Gh <= RCH &&
+            (n0 + CSOL_CG - 1) / CSOL_CG <= 64 * CSOL_QW;
   int s_begin = 0, s_end = nsteps;
   const long Nc = long(L.Mc) * L.Mc;
   const unsigned fb = unsigned((Nc + 255) / 256);
   k_fill_sentinel<T><<<dim3(fb, njobs), 256, 0, st>>>(jobs, Nc, cstride);
   if (persistent) {
     void* args[] = {&s_begin, &s_end, (void*)&L.nc, (void*)&L.Mc, &Gp, (void*)&jobs,
-                    (void*)&cstride, &err};
+                    (void*)&cstride, &one, &err};
     HZ_HIP(hipLaunchCooperativeKernel((const void*)kern, dim3(G), dim3(512), args, lds, st));
   } else {
     for (int s = 0; s < nsteps; ++s)
-      kern<<<G, 512, lds, st>>>(s, s + 1, L.nc, L.Mc, Gp, jobs, cstride, err);
+      kern<<<G, 512, lds, st>>>(s, s + 1, L.nc, L.Mc, Gp, jobs, cstride, one, err);
   }
   HZ_HIP(hipGetLastError());
 }
