@@ -705,6 +705,14 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
       };
       // the publishing lanes: row rr = lane / NR of the chunk, right-hand side lane % NR
       const bool publisher = sw == 0 && lane < RCH * NR;
+      // backwards, the forward result of the row this lane publishes, requested a step ahead
+      V2<T> gprev = czero<T>();
+      auto gprev_of = [&](int s2) __attribute__((always_inline)) {
+        const StepPlan pn = make_plan<P>(s2, g, G, nc, Mc);
+        const int r = pn.r0 + lane / NR, h = lane % NR;
+        return (publisher && s2 < s_end && pn.active && !pn.fwd && r < pn.r1 && h < nrhs)
+                   ? ld_coh<T>(gbuf + h * Nc + long(P) * pn.j * Mc + r) : czero<T>();
+      };
 #define HZ_LOAD_COLS(DST, QLO, QHI, TL)                                                      \
   _Pragma("unroll") for (int i = 0; i < RW; ++i)                                             \
   _Pragma("unroll") for (int q = QLO; q < QHI; ++q) {                                        \
@@ -712,6 +720,7 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
     DST[i][q] = (TL.rw0 + i < TL.r1 && c < TL.c1) ? TL.Sj[size_t(TL.rw0 + i) * TL.nj + c]    \
                                                    : czero<T>();                             \
   }
+      gprev = gprev_of(s_begin);
       {
         const Tile t0 = tile_of(s_begin), t1 = tile_of(s_begin + 1);
         if constexpr (QE > 0) { HZ_LOAD_COLS(B, 0, QE, t0) }
@@ -725,13 +734,8 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
         const int nj = pl.nj;
         fold_step(pl, false);
         const int r0 = pl.r0, r1 = pl.r1;
-        // backwards, the forward result of the row this lane publishes (requested before the
-        // product, so that it has arrived when the row sums are complete)
         const int pr = r0 + lane / NR, ph = lane % NR;
         const bool pub = publisher && pr < r1 && ph < nrhs;
-        const V2<T> gprev = (pub && !pl.fwd)
-                                ? ld_coh<T>(gbuf + ph * Nc + long(P) * pl.j * Mc + pr)
-                                : czero<T>();
         if (r1 > r0) {
           const int c0 = (nj * cg) / CG, c1 = (nj * (cg + 1)) / CG;
           T ar[RW][NR], ai[RW][NR];
@@ -785,9 +789,10 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
           V2<T>* dst = (pl.fwd && !pl.mid) ? gbuf + ph * Nc : y + ph * cstride;
           st_coh<T>(dst + long(P) * pl.j * Mc + pr, o);
         }
-        // requests for the steps ahead, issued while the exchange waves poll: the late
-        // columns of the next step and the early columns of the one after, into the
-        // registers this step freed
+        // requests for the steps ahead, issued while the exchange waves poll: the next
+        // step's forward result, the late columns of the next step and the early columns of
+        // the one after, into the registers this step freed
+        gprev = gprev_of(s + 1);
         {
           const Tile tn = tile_of(s + 1);
           HZ_LOAD_COLS(A, QE, QW, tn)
