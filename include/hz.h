@@ -30,6 +30,9 @@
  *   * No exception crosses the ABI. Every call returns a status; hz_last_error() gives a
  *     human-readable message for the calling thread. Non-convergence is not an error.
  *   * One problem must not be used by two threads at once; a concurrent call returns HZ_EBUSY.
+ *     Different problems may be used from different threads and streams: the library orders
+ *     its persistent coarse-solve launches on one device one after another (they must not be
+ *     resident together), whatever streams they are issued on.
  */
 #ifndef HZ_H
 #define HZ_H
@@ -94,23 +97,41 @@ typedef struct {
   long graph_rounds;         /* FGMRES rounds replayed from a captured HIP graph           */
 } hz_stats;
 
-/* Operators exposed by hz_apply (parity hooks; all act on the problem's own data). */
+/* Operators exposed by hz_apply (parity hooks; all act on the problem's own data). Each is one
+ * building block of the twogrid cycle of Sec. 4, Algorithm 1 (two levels) or of the system
+ * matrix of Sec. 2. */
 typedef enum {
-  HZ_OP_A0 = 0,             /* y = A_0 x                               (fine -> fine)     */
-  HZ_OP_AEPS = 1,           /* y = A_eps x                             (fine -> fine)     */
-  HZ_OP_JACOBI = 2,         /* y = x + omega D^-1 (f - A_eps x), D = diag(A_eps)           */
-  HZ_OP_RESTRICT = 3,       /* y = P^T x                               (fine -> coarse)   */
-  HZ_OP_PROLONG = 4,        /* y = P x                                 (coarse -> fine)   */
-  HZ_OP_VCYCLE = 5,         /* y = V-cycle(x) from a zero initial guess (fine -> fine)    */
-  HZ_OP_COARSE_SOLVE = 6,   /* y = (A_eps^{2h})^-1 x                   (coarse -> coarse) */
-  HZ_OP_COARSE_A = 7,       /* y = A_eps^{2h} x                        (coarse -> coarse) */
-  HZ_OP_RESID_RESTRICT = 8  /* y = P^T (f - A_eps x)                   (fine -> coarse)   */
+  HZ_OP_A0 = 0,             /* y = A_0 x: the unshifted system matrix A(k, 0) of Sec. 2,
+                               applied matrix-free                  (fine -> fine)     */
+  HZ_OP_AEPS = 1,           /* y = A_eps x: the shifted matrix A(k, eps) of Sec. 2
+                                                                    (fine -> fine)     */
+  HZ_OP_JACOBI = 2,         /* y = x + omega D^-1 (f - A_eps x), D = diag(A_eps): one
+                               damped Jacobi sweep, the smoother S of Algorithm 1       */
+  HZ_OP_RESTRICT = 3,       /* y = P^T x: the restriction of Algorithm 1 (transpose of
+                               the FE prolongation of nested spaces, Sec. 4)
+                                                                    (fine -> coarse)   */
+  HZ_OP_PROLONG = 4,        /* y = P x: the FE prolongation (coarse grid correction of
+                               Algorithm 1)                         (coarse -> fine)   */
+  HZ_OP_VCYCLE = 5,         /* y = V-cycle(x) from a zero initial guess: Algorithm 1 with
+                               two levels, the preconditioner of Sec. 4 (fine -> fine) */
+  HZ_OP_COARSE_SOLVE = 6,   /* y = (A_eps^{2h})^-1 x: the direct solve on the coarsest
+                               level of Algorithm 1, with the factor computed once at
+                               creation (Sec. 6 factors it once and reuses it)
+                                                                    (coarse -> coarse) */
+  HZ_OP_COARSE_A = 7,       /* y = A_eps^{2h} x: the shifted matrix of Sec. 2 rediscretised
+                               on the 2h mesh (Sec. 4)              (coarse -> coarse) */
+  HZ_OP_RESID_RESTRICT = 8  /* y = P^T (f - A_eps x): the "restrict residual" step of
+                               Algorithm 1                          (fine -> coarse)   */
 } hz_op;
 
 /* Fills the defaults listed in hz_options. */
 hz_status hz_default_options(hz_options* o);
 
-/* Creates a problem for wavenumber k > 0 on n = 1/h cells per side (1/h must be an even
+/* Creates the discrete problem of Sec. 2 (the impedance boundary value problem, its
+ * sesquilinear form and the system matrix A(k, eps) = K - M(k, eps) - i B(k)) together with
+ * the twogrid preconditioner of Sec. 4, Algorithm 1 (coarse operator rediscretised on the
+ * 2h mesh and factored once, as Sec. 6 does in the first FGMRES iteration).
+ * Creates a problem for wavenumber k > 0 on n = 1/h cells per side (1/h must be an even
  * integer >= 2, up to 4096), element order p in {1,2,3} and shift multiplier s with
  * Im(s) > 0 (required: the coarse block LU runs without pivoting, which is safe because the
  * Hermitian part of i*A_eps is Im(s) k^2 M + k B, positive definite). Builds the stencil
@@ -138,7 +159,10 @@ size_t hz_footprint_estimate(double k, double h, int p, const hz_options* o);
  * integrated with 10-point Gauss-Legendre. Asynchronous on hip_stream. */
 hz_status hz_planewave_rhs(const hz_problem* pr, double theta, hz_c64* d_F, void* hip_stream);
 
-/* Solves A_0 u = F by FGMRES(o->restart) preconditioned with the twogrid V-cycle; zero
+/* The outer solve of Sec. 4: right-preconditioned flexible GMRES (after Saad 1993) on the
+ * unshifted system, one twogrid V-cycle of Algorithm 1 on A_eps as the preconditioner, and the
+ * stopping rule of Sec. 5 (relative residual of the unpreconditioned system).
+ * Solves A_0 u = F by FGMRES(o->restart) preconditioned with the twogrid V-cycle; zero
  * initial guess; stops when the relative residual is <= o->tol (the rotation estimate inside
  * a cycle, confirmed by the recomputed true residual), or after o->maxit preconditioner
  * applications (then converged = 0, status HZ_OK). o->nu and o->omega are those given at
@@ -148,7 +172,8 @@ hz_status hz_planewave_rhs(const hz_problem* pr, double theta, hz_c64* d_F, void
 hz_status hz_solve(hz_problem* pr, const hz_c64* d_F, hz_c64* d_u, const hz_options* o,
                    hz_result* res, double* h_res_hist, void* hip_stream);
 
-/* Applies one building block of the method (see hz_op). d_x, d_y: device vectors of the
+/* Applies one building block of Sec. 4, Algorithm 1 or of the system matrix of Sec. 2 (the
+ * passage of each is named at its hz_op value). d_x, d_y: device vectors of the
  * op's input and output spaces; d_f: the second input of HZ_OP_JACOBI and
  * HZ_OP_RESID_RESTRICT (ignored otherwise, may be NULL). prec selects the FP64 or FP32
  * kernels; I/O is always complex FP64 (converted on the device for FP32). d_y must not alias
@@ -156,7 +181,9 @@ hz_status hz_solve(hz_problem* pr, const hz_c64* d_F, hz_c64* d_u, const hz_opti
 hz_status hz_apply(const hz_problem* pr, int op, const hz_c64* d_x, const hz_c64* d_f,
                    hz_c64* d_y, int prec, void* hip_stream);
 
-/* Runs nprob * nrhs_per_prob independent FGMRES solves (the same method as hz_solve) in
+/* Many independent solves of the method at once: the sample generation of Sec. 5 runs one
+ * FGMRES solve (Sec. 4) per (k, h, p, shift) sample and right-hand side.
+ * Runs nprob * nrhs_per_prob independent FGMRES solves (the same method as hz_solve) in
  * lockstep: solve (i, r) uses problem probs[i] and right-hand side d_F[i*nrhs_per_prob + r],
  * writing d_u[i*nrhs_per_prob + r] and res[i*nrhs_per_prob + r]. Each round performs one
  * Arnoldi step of every unfinished solve: the V-cycles of one problem's right-hand sides run
@@ -221,7 +248,9 @@ hz_status hz_engine_create(const hz_engine_config* c, const hz_options* o, hz_en
  * load for angle theta when d_F is NULL, else a copy of the fine vector d_F taken at setup
  * (d_F must stay valid until the request is reported). The solution is written to d_u (a
  * caller-owned fine vector that must stay valid and untouched until the request is
- * reported; it is complete when hz_engine_poll returns it). Thread-safe, non-blocking.
+ * reported; it is complete when hz_engine_poll returns it). The engine reads d_F on its own
+ * streams, which are not ordered after the caller's: the work that produces d_F must have
+ * completed (e.g. its stream synchronised) before the call. Thread-safe, non-blocking.
  * Errors: HZ_EINVAL (bad parameters), HZ_ENOMEM (the request alone exceeds the budget),
  * HZ_EBUSY (the engine is being destroyed). */
 hz_status hz_engine_submit(hz_engine* e, double k, double h, int p, hz_c64 s, double theta,

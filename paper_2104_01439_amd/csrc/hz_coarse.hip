@@ -9,8 +9,10 @@
 // S_j is formed explicitly by blocked Gauss-Jordan; the rank-NB updates run on FP64 MFMA.
 // Solve:  g_j = S_j (b_j - A_{j,j-1} g_{j-1}),   x_j = g_j - S_j (A_{j,j+1} x_{j+1}).
 
-#include <type_traits>
+#include <map>
+#include <mutex>
 #include <stdexcept>
+#include <type_traits>
 
 #include "hz_common.h"
 
@@ -990,6 +992,35 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
 
 constexpr size_t kLdsPerWorkgroup = 160 * 1024;   // gfx950
 
+// The persistent solve spins on its peer workgroups, so two of its launches must never be
+// resident at once: launches on one device run one after another whatever stream they are
+// issued on. Each launch waits for an event recorded after the previous one (one event per
+// device, re-recorded under a process-wide lock; a wait binds to the latest record at the
+// time of the wait call).
+struct PersistentOrder {
+  std::unique_lock<std::mutex> lk;
+  hipEvent_t* ev = nullptr;
+  hipStream_t st;
+  static std::mutex& mu() {
+    static std::mutex m;
+    return m;
+  }
+  PersistentOrder(int dev, hipStream_t s) : lk(mu()), st(s) {
+    static std::map<int, hipEvent_t> last;
+    auto it = last.find(dev);
+    if (it == last.end()) {
+      hipEvent_t e = nullptr;
+      HZ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      it = last.emplace(dev, e).first;
+    } else {
+      HZ_HIP(hipStreamWaitEvent(st, it->second, 0));
+    }
+    ev = &it->second;
+  }
+  // after the launch was issued
+  ~PersistentOrder() { (void)hipEventRecord(*ev, st); }
+};
+
 // Dynamic plus static LDS bytes of one k_csolve workgroup.
 template <int P, typename T, int NR>
 constexpr size_t csolve_lds(int Mc) {
@@ -1008,15 +1039,21 @@ void csolve_launch(const CoarseLayout& L, const CsJobs<T>& jobs, int njobs, long
   const size_t lds = (NCOEF + 2 * size_t(L.size(0)) * NR) * sizeof(V2<T>);
   if (csolve_lds<P, T, NR>(L.Mc) > kLdsPerWorkgroup)
     throw std::runtime_error("coarse solve staging exceeds the LDS of a workgroup");
-  // dynamic LDS beyond the default limit must be requested; the static part counts too
-  static size_t configured = 0;
-  if (lds > 48 * 1024 && lds > configured) {
-    HZ_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               int(lds)));
-    configured = lds;
-  }
   int dev = 0;
   HZ_HIP(hipGetDevice(&dev));
+  // dynamic LDS beyond the default limit must be requested (per device; the static part
+  // counts too); several host threads may get here at once
+  {
+    static std::mutex mu;
+    static std::map<int, size_t> configured;
+    std::lock_guard<std::mutex> g(mu);
+    size_t& c = configured[dev];
+    if (lds > 48 * 1024 && lds > c) {
+      HZ_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 int(lds)));
+      c = lds;
+    }
+  }
   int cus = 0, coop = 0;
   HZ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   HZ_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
@@ -1043,6 +1080,7 @@ void csolve_launch(const CoarseLayout& L, const CsJobs<T>& jobs, int njobs, long
   if (persistent) {
     void* args[] = {&s_begin, &s_end, (void*)&L.nc, (void*)&L.Mc, &Gp, (void*)&jobs,
                     (void*)&cstride, &one, &err};
+    PersistentOrder order(dev, st);
     HZ_HIP(hipLaunchCooperativeKernel((const void*)kern, dim3(G), dim3(512), args, lds, st));
   } else {
     for (int s = 0; s < nsteps; ++s)

@@ -13,6 +13,7 @@
 #include <functional>
 #include <map>
 #include <mutex>
+#include <stdexcept>
 #include <string>
 
 #include "hz_common.h"
@@ -367,6 +368,13 @@ int tuned_variant(const std::string& key, int nvar,
   return best;
 }
 
+// HZ_STENCIL_VARIANT=v forces launch variant v (for checking every variant); unset or
+// negative: the tuner's choice.
+int forced_variant() {
+  const char* e = std::getenv("HZ_STENCIL_VARIANT");
+  return (e && *e) ? std::atoi(e) : -1;
+}
+
 template <int P, typename T, typename TX, typename TF, typename TY>
 void stencil_p(int mode, const DevOp<T>& op, const V2<TX>* x, Addr xs, const V2<TF>* f, Addr fs,
                V2<TY>* y, Addr ys, int nbatch, hipStream_t st) {
@@ -376,6 +384,12 @@ void stencil_p(int mode, const DevOp<T>& op, const V2<TX>* x, Addr xs, const V2<
     else stencil_variant<P, T, TX, TF, TY, ST_SMOOTH>(v, op, x, xs, f, fs, y, ys, nbatch, st);
   };
   const int nvar = P <= 2 ? 4 : 2;
+  const int fv = forced_variant();
+  if (fv >= 0) {
+    if (fv >= nvar) throw std::runtime_error("HZ_STENCIL_VARIANT: no such variant for this order");
+    launch(fv);
+    return;
+  }
   const int bucket = nbatch == 1 ? 1 : nbatch <= 4 ? 4 : nbatch <= 16 ? 16 : 64;
   const std::string key = "st" + std::to_string(P) + "/" + std::to_string(sizeof(T)) +
                           std::to_string(sizeof(TX)) + std::to_string(sizeof(TF)) +

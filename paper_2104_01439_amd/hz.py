@@ -289,6 +289,9 @@ class Engine:
         if u is None:
             u = torch.empty(sizes(n, p)[1], dtype=torch.complex128, device="cuda")
         self._out[req_id] = (u, F)
+        if F is not None:
+            # the engine copies F on its own stream: the work producing F must be complete
+            torch.cuda.current_stream().synchronize()
         _check(lib().hz_engine_submit(self._h, float(k), float(h), int(p),
                                       C64(complex(s).real, complex(s).imag), float(theta),
                                       _ptr(F), _ptr(u), int(req_id)))

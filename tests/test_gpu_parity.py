@@ -149,7 +149,8 @@ def test_mixed_precision_blocks(hz, torch, c):
     z = C.host(C.gp.apply("VCYCLE", C.dev(f), prec="mixed"))
     e = rel(z, C.tg.vcycle(f))
     _log(f"  mixed VCYCLE: rel err {e:.2e}")
-    assert e <= 1e-3
+    # FP32 rounding through the cycle, amplified by the coarse solve (measured <= 1.9e-7)
+    assert e <= 2e-6
 
 
 SOLVES = [
@@ -198,7 +199,8 @@ def test_mixed_solve(hz, torch, k, n, p, s, th):
          f"(delta {r['iterations'] - ro['iterations']:+d}), u rel err {e:.2e}")
     assert r["converged"] == 1
     assert e <= 1e-8
-    assert abs(r["iterations"] - ro["iterations"]) <= max(3, ro["iterations"] // 10)
+    # the flexible outer iteration absorbs the FP32 preconditioner (measured delta 0)
+    assert abs(r["iterations"] - ro["iterations"]) <= 1
 
 
 def test_solve_edge_cases(hz, torch):
