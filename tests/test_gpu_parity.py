@@ -338,3 +338,44 @@ def test_coarse_solve_per_step_launches(hz, torch, c, monkeypatch):
     y2 = C.gp.apply("COARSE_SOLVE", C.dev(rc))
     assert torch.equal(y1, y2)          # same arithmetic, same order
     assert rel(C.host(y1), C.tg.coarse_solve(rc)) <= 1e-10
+
+
+@pytest.mark.parametrize("c", [CASES[1], CASES[2], CASES[4], CASES[6]])
+def test_every_stencil_variant_against_oracle(hz, torch, c, monkeypatch):
+    """Every launch variant the autotuner may pick (tile height, XCD-aware tile order),
+    forced one at a time: each matches the oracle and all are bitwise equal."""
+    C = case(hz, torch, c)
+    nvar = 4 if C.p <= 2 else 2
+    x = inputs.random_complex(C.fine.N, seed=1234)
+    f = inputs.random_complex(C.fine.N, seed=99)
+    xc = inputs.random_complex(C.coarse.N, seed=4321)
+    dx, df, dxc = C.dev(x), C.dev(f), C.dev(xc)
+    ref = {
+        "A0": C.A0 @ x,
+        "AEPS": C.tg.Aeps @ x,
+        "JACOBI": jacobi_sweep(C.tg.Aeps, C.tg.dinv, 0.6, x, f),
+        "COARSE_A": C.tg.Ac @ xc,
+        "RESID_RESTRICT": C.tg.P.T @ (f - C.tg.Aeps @ x),
+        "VCYCLE": C.tg.vcycle(f),
+    }
+    first = {}
+    for v in range(nvar):
+        monkeypatch.setenv("HZ_STENCIL_VARIANT", str(v))
+        for name, o in ref.items():
+            arg = dxc if name == "COARSE_A" else (df if name == "VCYCLE" else dx)
+            g = C.gp.apply(name, arg, df)
+            e = rel(C.host(g), o)
+            assert e <= (1e-10 if name == "VCYCLE" else 1e-12), (v, name, e)
+            if v == 0:
+                first[name] = g
+            else:
+                assert torch.equal(g, first[name]), (v, name)
+        gm = C.gp.apply("JACOBI", dx, df, prec="mixed")
+        em = rel(C.host(gm), ref["JACOBI"])
+        assert em <= 2e-6, (v, "mixed JACOBI", em)
+        if v == 0:
+            first["mixed"] = gm
+        else:
+            assert torch.equal(gm, first["mixed"]), (v, "mixed JACOBI")
+    monkeypatch.delenv("HZ_STENCIL_VARIANT")
+    _log(f"  {nvar} variants agree with the oracle and bitwise with each other")
