@@ -181,6 +181,26 @@ hz_status hz_solve(hz_problem* pr, const hz_c64* d_F, hz_c64* d_u, const hz_opti
 hz_status hz_apply(const hz_problem* pr, int op, const hz_c64* d_x, const hz_c64* d_f,
                    hz_c64* d_y, int prec, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): hz_apply without any allocation. Same operators,
+ * arguments, layouts, results (the same kernels with the same arithmetic) and errors as
+ * hz_apply, plus:
+ *   * the kernels' scratch (V-cycle iterates, residual, coarse vectors, the coarse solve's
+ *     forward-sweep buffer and timeout flag, FP32 staging) lives in one fixed device array
+ *     of 64 MiB per GPU, held from the first call on that GPU until the process ends; a
+ *     problem needing more (above about 1.1 M fine dofs in FP64, 0.98 M in HZ_MIXED) is
+ *     rejected with HZ_EINVAL and a message giving both sizes;
+ *   * HZ_MIXED needs the problem's FP32 coarse factor to exist already (a problem created
+ *     with HZ_MIXED, or one mixed hz_apply / hz_solve earlier), else HZ_EINVAL;
+ *   * no timing is booked and the stencil autotuner times nothing (the cached choice, else
+ *     the default tile; every tile gives the same result);
+ *   * every call on one GPU shares that GPU's array: calls that overlap on one GPU (other
+ *     streams or threads, before the previous call's kernels have completed) race and give
+ *     undefined results. Serialise them, e.g. by issuing them all on one stream.
+ * The first call on a device looks up the array's device address (no allocation). */
+hz_status hz_apply_noalloc(const hz_problem* pr, int op, const hz_c64* d_x, const hz_c64* d_f,
+                           hz_c64* d_y, int prec, void* hip_stream);
+
 /* Many independent solves of the method at once: the sample generation of Sec. 5 runs one
  * FGMRES solve (Sec. 4) per (k, h, p, shift) sample and right-hand side.
  * Runs nprob * nrhs_per_prob independent FGMRES solves (the same method as hz_solve) in

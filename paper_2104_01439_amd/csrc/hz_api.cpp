@@ -503,18 +503,22 @@ double csolve_job_bytes(const CoarseLayout& L, size_t item, int nrhs) {
 // Coarse solves of jobs (timed with HIP events on the stream when the first problem was
 // created with timing; counters accumulate in that problem).
 template <typename T>
-void timed_coarse_jobs(hz_problem* pr, const CoarseJob<T>* jobs, int njobs, hipStream_t st) {
+void timed_coarse_jobs(hz_problem* pr, const CoarseJob<T>* jobs, int njobs, hipStream_t st,
+                       const CoarseSolveWork* cw = nullptr) {
   double bytes = 0;
   for (int i = 0; i < njobs; ++i) bytes += csolve_job_bytes(pr->L, sizeof(V2<T>), jobs[i].nrhs);
+  // a caller-given work set (the allocation-free apply) is never timed: no events are made
+  const bool timed = pr->timing && !cw;
+  if (!cw) cw = &pr->cw;
   std::pair<hipEvent_t, hipEvent_t> e{};
-  if (pr->timing) {
+  if (timed) {
     e = take_events(pr);
     HZ_HIP(hipEventRecord(e.first, st));
   }
-  pr->stats.coarse_solves += coarse_solve_jobs<T>(pr->L, jobs, njobs, pr->Nc, pr->cw.err,
-                                                  pr->cw.persistent, st);
+  pr->stats.coarse_solves += coarse_solve_jobs<T>(pr->L, jobs, njobs, pr->Nc, cw->err,
+                                                  cw->persistent, st);
   pr->stats.coarse_bytes += bytes;
-  if (pr->timing) {
+  if (timed) {
     HZ_HIP(hipEventRecord(e.second, st));
     pr->ev_pending.push_back(e);
     if (pr->ev_pending.size() > 64) collect_timing(pr, true);
@@ -539,7 +543,8 @@ enum VcPhase { VC_PRE = 1, VC_COARSE = 2, VC_POST = 4, VC_ALL = 7 };
 template <typename T>
 void vcycle_group(hz_problem* const* probs, const int* zp, int nb, const DevOp<T>& fine,
                   const T* rw, const Scratch<T>& sc, V2<T>* gb, const V2<T>* f, Addr af,
-                  V2<T>* z, Addr az, hipStream_t st, int phases = VC_ALL) {
+                  V2<T>* z, Addr az, hipStream_t st, int phases = VC_ALL,
+                  const CoarseSolveWork* cw = nullptr) {
   hz_problem* pr0 = probs[zp[0]];
   const int p = pr0->p, nu = pr0->opt.nu;
   const long N = pr0->N, Nc = pr0->Nc;
@@ -583,7 +588,7 @@ void vcycle_group(hz_problem* const* probs, const int* zp, int nb, const DevOp<T
       jobs.push_back(j);
       b0 = b1;
     }
-    timed_coarse_jobs<T>(pr0, jobs.data(), int(jobs.size()), st);
+    timed_coarse_jobs<T>(pr0, jobs.data(), int(jobs.size()), st, cw);
   }
   if (phases & VC_POST) {
     if (nu == 0) {
@@ -602,28 +607,27 @@ void vcycle_group(hz_problem* const* probs, const int* zp, int nb, const DevOp<T
   }
 }
 
-// Single-problem forms used by hz_apply.
+// Single-problem forms used by hz_apply: one right-hand side, the coarse-solve work of the
+// level (the problem's own, or the caller's for the allocation-free apply).
 template <typename T>
-void vcycle(hz_problem* pr, const Level<T>& lv, int nu, const V2<T>* f, Addr af, V2<T>* z,
-            Addr az, int nb, hipStream_t st) {
-  (void)nu;
+void vcycle(hz_problem* pr, const Level<T>& lv, const V2<T>* f, V2<T>* z, hipStream_t st,
+            bool own_work) {
   hz_problem* const probs[1] = {pr};
   const int zp[1] = {0};
-  vcycle_group<T>(probs, zp, nb, lv.fine, lv.rw, lv.sc, reinterpret_cast<V2<T>*>(pr->cw.g), f,
-                  af, z, az, st);
+  vcycle_group<T>(probs, zp, 1, lv.fine, lv.rw, lv.sc, reinterpret_cast<V2<T>*>(lv.cw.g), f,
+                  Addr(), z, Addr(), st, VC_ALL, own_work ? nullptr : &lv.cw);
 }
 template <typename T>
-void timed_coarse_solve(hz_problem* pr, const Level<T>& lv, const V2<T>* b, V2<T>* y, int nrhs,
-                        hipStream_t st) {
-  (void)nrhs;
+void timed_coarse_solve(hz_problem* pr, const Level<T>& lv, const V2<T>* b, V2<T>* y,
+                        hipStream_t st, bool own_work) {
   CoarseJob<T> j;
   j.S = lv.S;
   j.coef = lv.coarse.coef;
   j.b = b;
   j.y = y;
-  j.gbuf = reinterpret_cast<V2<T>*>(pr->cw.g);
+  j.gbuf = reinterpret_cast<V2<T>*>(lv.cw.g);
   j.nrhs = 1;
-  timed_coarse_jobs<T>(pr, &j, 1, st);
+  timed_coarse_jobs<T>(pr, &j, 1, st, own_work ? nullptr : &lv.cw);
 }
 
 // Complex Givens rotation with c real: [c s; -conj(s) c] [a; b] = [r; 0].
@@ -1191,6 +1195,170 @@ hz_status solve_impl(hz_problem* pr, const double2* F, double2* u, const hz_opti
 // C ABI
 // =========================================================================================
 
+// ------------------------------------------------------------------------------------------
+// hz_apply and its allocation-free variant share one body; they differ only in where the
+// scratch of the kernels lives (the problem's own buffers, allocated on first use, or the
+// file-scope device array below).
+// ------------------------------------------------------------------------------------------
+
+namespace {
+
+struct ApplyBufs {
+  Scratch<double> s64;                 // V-cycle iterates, residual, coarse vectors (FP64)
+  Scratch<float> s32;                  // the same in FP32, plus the FP32 copy of the input
+  float2 *ax32 = nullptr, *af32 = nullptr, *ay32 = nullptr;   // FP32 staging of x, f, y (fine)
+  float2 *cx32 = nullptr, *cy32 = nullptr;                    // and of coarse x, y
+  CoarseSolveWork cw;                  // coarse forward-sweep buffer and timeout flag
+  bool own = true;                     // the problem's own buffers (timed coarse solves)
+};
+
+hz_status check_apply(hz_problem* pr, int op, const hz_c64* d_x, const hz_c64* d_f,
+                      const hz_c64* d_y, int prec) {
+  if (!pr || !d_x || !d_y) return fail(HZ_EINVAL, "null argument");
+  if ((op == HZ_OP_JACOBI || op == HZ_OP_RESID_RESTRICT) && !d_f)
+    return fail(HZ_EINVAL, "this operator needs d_f");
+  if (op < 0 || op > HZ_OP_RESID_RESTRICT) return fail(HZ_EINVAL, "unknown operator");
+  if (prec != HZ_FP64 && prec != HZ_MIXED) return fail(HZ_EINVAL, "bad precision");
+  if (prec == HZ_FP64 && !pr->S) return fail(HZ_EINVAL, "problem was created for mixed precision only");
+  return HZ_OK;
+}
+
+void apply_impl(hz_problem* pr, int op, const double2* x, const double2* f, double2* y, int prec,
+                const ApplyBufs& b, hipStream_t st) {
+  const int p = pr->p;
+  const bool fine_in = !(op == HZ_OP_PROLONG || op == HZ_OP_COARSE_SOLVE || op == HZ_OP_COARSE_A);
+  const bool fine_out = !(op == HZ_OP_RESTRICT || op == HZ_OP_COARSE_SOLVE ||
+                          op == HZ_OP_COARSE_A || op == HZ_OP_RESID_RESTRICT);
+  const Addr o;
+  if (prec == HZ_FP64) {
+    Level<double> lv = level64(pr, b.s64);
+    lv.cw = b.cw;
+    const DevOp<double> a0{pr->cA0, nullptr, pr->M};
+    switch (op) {
+      case HZ_OP_A0: launch_stencil<double, double, double, double>(p, ST_APPLY, a0, x, o, nullptr, o, y, o, 1, st); break;
+      case HZ_OP_AEPS: launch_stencil<double, double, double, double>(p, ST_APPLY, lv.fine, x, o, nullptr, o, y, o, 1, st); break;
+      case HZ_OP_JACOBI: launch_stencil<double, double, double, double>(p, ST_SMOOTH, lv.fine, x, o, f, o, y, o, 1, st); break;
+      case HZ_OP_RESTRICT: launch_restrict<double>(p, pr->M, pr->Mc, pr->rw, x, y, 1, o, o, st); break;
+      case HZ_OP_PROLONG: launch_prolong<double>(p, pr->M, pr->Mc, pr->rw, x, y, false, 1, o, o, st); break;
+      case HZ_OP_VCYCLE: vcycle<double>(pr, lv, x, y, st, b.own); break;
+      case HZ_OP_COARSE_SOLVE: timed_coarse_solve<double>(pr, lv, x, y, st, b.own); break;
+      case HZ_OP_COARSE_A: launch_stencil<double, double, double, double>(p, ST_APPLY, lv.coarse, x, o, nullptr, o, y, o, 1, st); break;
+      case HZ_OP_RESID_RESTRICT:
+        launch_stencil<double, double, double, double>(p, ST_RESID, lv.fine, x, o, f, o, b.s64.rf, o, 1, st);
+        launch_restrict<double>(p, pr->M, pr->Mc, pr->rw, b.s64.rf, y, 1, o, o, st);
+        break;
+    }
+    return;
+  }
+  Level<float> lv = level32(pr, b.s32);
+  lv.cw = b.cw;
+  const long nin = fine_in ? pr->N : pr->Nc;
+  const long nout = fine_out ? pr->N : pr->Nc;
+  // FP32 copies: x -> ax32 (fine) or cx32 (coarse), f -> af32; result in ay32 / cy32
+  float2* xin = fine_in ? b.ax32 : b.cx32;
+  launch_d2f(x, xin, nin, st);
+  if (f) launch_d2f(f, b.af32, pr->N, st);
+  float2* yout = fine_out ? b.ay32 : b.cy32;
+  switch (op) {
+    case HZ_OP_A0: {
+      const DevOp<double> a0{pr->cA0, nullptr, pr->M};
+      launch_stencil<double, float, double, double>(p, ST_APPLY, a0, xin, o, nullptr, o, y, o, 1, st);
+      return;
+    }
+    case HZ_OP_AEPS: launch_stencil<float, float, float, float>(p, ST_APPLY, lv.fine, xin, o, nullptr, o, yout, o, 1, st); break;
+    case HZ_OP_JACOBI: launch_stencil<float, float, float, float>(p, ST_SMOOTH, lv.fine, xin, o, b.af32, o, yout, o, 1, st); break;
+    case HZ_OP_RESTRICT: launch_restrict<float>(p, pr->M, pr->Mc, pr->frw, xin, yout, 1, o, o, st); break;
+    case HZ_OP_PROLONG: launch_prolong<float>(p, pr->M, pr->Mc, pr->frw, xin, yout, false, 1, o, o, st); break;
+    case HZ_OP_VCYCLE: vcycle<float>(pr, lv, xin, yout, st, b.own); break;
+    case HZ_OP_COARSE_SOLVE: timed_coarse_solve<float>(pr, lv, xin, yout, st, b.own); break;
+    case HZ_OP_COARSE_A: launch_stencil<float, float, float, float>(p, ST_APPLY, lv.coarse, xin, o, nullptr, o, yout, o, 1, st); break;
+    case HZ_OP_RESID_RESTRICT:
+      launch_stencil<float, float, float, float>(p, ST_RESID, lv.fine, xin, o, b.af32, o, b.s32.rf, o, 1, st);
+      launch_restrict<float>(p, pr->M, pr->Mc, pr->frw, b.s32.rf, yout, 1, o, o, st);
+      break;
+  }
+  launch_f2d(yout, y, nout, st);
+}
+
+}  // namespace
+
+// Scratch of hz_apply_noalloc: one array per device (each GPU holds its own copy at its own
+// address until the process ends). Host code never uses its name as an address: the device
+// address is looked up once per device with hipGetSymbolAddress and kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;
+
+// Device address of the current device's scratch array (set up on the first call per device,
+// with that device current; also creates the device's coarse-solve ordering event then).
+char* noalloc_scratch() {
+  int dev = 0;
+  HZ_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) throw HipError{e, "hipGetSymbolAddress(scratch)"};
+  coarse_order_init(dev);
+  g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  return static_cast<char*>(ptr);
+}
+
+// Carves the buffers of one apply out of the scratch array (256-byte aligned pieces).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T> T* take(size_t n) {
+    T* p = reinterpret_cast<T*>(base + off);
+    off += (n * sizeof(T) + 255) / 256 * 256;
+    return p;
+  }
+};
+ApplyBufs noalloc_carve(char* base, long N, long Nc, int prec, size_t* used) {
+  Carver c{base};
+  ApplyBufs b;
+  b.cw.err = c.take<int>(64);
+  b.cw.g = c.take<double2>(size_t(Nc));
+  if (prec == HZ_FP64) {
+    b.s64.cap = 1;
+    b.s64.ua = c.take<double2>(N);
+    b.s64.ub = c.take<double2>(N);
+    b.s64.rf = c.take<double2>(N);
+    b.s64.rc = c.take<double2>(Nc);
+    b.s64.ec = c.take<double2>(Nc);
+  } else {
+    b.s32.cap = 1;
+    b.s32.ua = c.take<float2>(N);
+    b.s32.ub = c.take<float2>(N);
+    b.s32.rf = c.take<float2>(N);
+    b.s32.ff = c.take<float2>(N);
+    b.s32.rc = c.take<float2>(Nc);
+    b.s32.ec = c.take<float2>(Nc);
+    b.ax32 = c.take<float2>(N);
+    b.af32 = c.take<float2>(N);
+    b.ay32 = c.take<float2>(N);
+    b.cx32 = c.take<float2>(Nc);
+    b.cy32 = c.take<float2>(Nc);
+  }
+  if (used) *used = c.off;
+  return b;
+}
+size_t noalloc_bytes(long N, long Nc, int prec) {
+  size_t used = 0;
+  (void)noalloc_carve(nullptr, N, Nc, prec, &used);
+  return used;
+}
+ApplyBufs noalloc_layout(char* base, long N, long Nc, int prec) {
+  return noalloc_carve(base, N, Nc, prec, nullptr);
+}
+
+}  // namespace
+
 extern "C" {
 
 hz_status hz_default_options(hz_options* o) {
@@ -1347,74 +1515,61 @@ hz_status hz_solve(hz_problem* pr, const hz_c64* d_F, hz_c64* d_u, const hz_opti
 hz_status hz_apply(const hz_problem* cpr, int op, const hz_c64* d_x, const hz_c64* d_f,
                    hz_c64* d_y, int prec, void* hip_stream) {
   hz_problem* pr = const_cast<hz_problem*>(cpr);
-  if (!pr || !d_x || !d_y) return fail(HZ_EINVAL, "null argument");
-  if ((op == HZ_OP_JACOBI || op == HZ_OP_RESID_RESTRICT) && !d_f)
-    return fail(HZ_EINVAL, "this operator needs d_f");
-  if (op < 0 || op > HZ_OP_RESID_RESTRICT) return fail(HZ_EINVAL, "unknown operator");
-  if (prec != HZ_FP64 && prec != HZ_MIXED) return fail(HZ_EINVAL, "bad precision");
+  hz_status v = check_apply(pr, op, d_x, d_f, d_y, prec);
+  if (v != HZ_OK) return v;
   BusyGuard guard(pr->busy);
   if (!guard.ok) return fail(HZ_EBUSY, "problem is in use");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  const double2* x = reinterpret_cast<const double2*>(d_x);
-  const double2* f = reinterpret_cast<const double2*>(d_f);
-  double2* y = reinterpret_cast<double2*>(d_y);
-  const int p = pr->p;
-  const bool fine_in = !(op == HZ_OP_PROLONG || op == HZ_OP_COARSE_SOLVE || op == HZ_OP_COARSE_A);
-  const bool fine_out = !(op == HZ_OP_RESTRICT || op == HZ_OP_COARSE_SOLVE ||
-                          op == HZ_OP_COARSE_A || op == HZ_OP_RESID_RESTRICT);
   try {
+    ApplyBufs b;
     if (prec == HZ_FP64) {
-      if (!pr->S) return fail(HZ_EINVAL, "problem was created for mixed precision only");
       ensure_fp64_work(pr);
-      const Level<double> lv = level64(pr, pr->s64);
-      const DevOp<double> a0{pr->cA0, nullptr, pr->M};
-      const Addr o;
-      switch (op) {
-        case HZ_OP_A0: launch_stencil<double, double, double, double>(p, ST_APPLY, a0, x, o, nullptr, o, y, o, 1, st); break;
-        case HZ_OP_AEPS: launch_stencil<double, double, double, double>(p, ST_APPLY, lv.fine, x, o, nullptr, o, y, o, 1, st); break;
-        case HZ_OP_JACOBI: launch_stencil<double, double, double, double>(p, ST_SMOOTH, lv.fine, x, o, f, o, y, o, 1, st); break;
-        case HZ_OP_RESTRICT: launch_restrict<double>(p, pr->M, pr->Mc, pr->rw, x, y, 1, o, o, st); break;
-        case HZ_OP_PROLONG: launch_prolong<double>(p, pr->M, pr->Mc, pr->rw, x, y, false, 1, o, o, st); break;
-        case HZ_OP_VCYCLE: vcycle<double>(pr, lv, pr->opt.nu, x, o, y, o, 1, st); break;
-        case HZ_OP_COARSE_SOLVE: timed_coarse_solve<double>(pr, lv, x, y, 1, st); break;
-        case HZ_OP_COARSE_A: launch_stencil<double, double, double, double>(p, ST_APPLY, lv.coarse, x, o, nullptr, o, y, o, 1, st); break;
-        case HZ_OP_RESID_RESTRICT:
-          launch_stencil<double, double, double, double>(p, ST_RESID, lv.fine, x, o, f, o, pr->s64.rf, o, 1, st);
-          launch_restrict<double>(p, pr->M, pr->Mc, pr->rw, pr->s64.rf, y, 1, o, o, st);
-          break;
-      }
+      b.s64 = pr->s64;
     } else {
       ensure_mixed_work(pr, st);
       ensure_apply32(pr);
-      const Level<float> lv = level32(pr, pr->s32);
-      const long nin = fine_in ? pr->N : pr->Nc;
-      const long nout = fine_out ? pr->N : pr->Nc;
-      const Addr o;
-      // FP32 copies: x -> ax32 (fine) or cx32 (coarse), f -> af32; result in ay32 / cy32
-      float2* xin = fine_in ? pr->ax32 : pr->cx32;
-      launch_d2f(x, xin, nin, st);
-      if (f) launch_d2f(f, pr->af32, pr->N, st);
-      float2* yout = fine_out ? pr->ay32 : pr->cy32;
-      switch (op) {
-        case HZ_OP_A0: {
-          const DevOp<double> a0{pr->cA0, nullptr, pr->M};
-          launch_stencil<double, float, double, double>(p, ST_APPLY, a0, xin, o, nullptr, o, y, o, 1, st);
-          return HZ_OK;
-        }
-        case HZ_OP_AEPS: launch_stencil<float, float, float, float>(p, ST_APPLY, lv.fine, xin, o, nullptr, o, yout, o, 1, st); break;
-        case HZ_OP_JACOBI: launch_stencil<float, float, float, float>(p, ST_SMOOTH, lv.fine, xin, o, pr->af32, o, yout, o, 1, st); break;
-        case HZ_OP_RESTRICT: launch_restrict<float>(p, pr->M, pr->Mc, pr->frw, xin, yout, 1, o, o, st); break;
-        case HZ_OP_PROLONG: launch_prolong<float>(p, pr->M, pr->Mc, pr->frw, xin, yout, false, 1, o, o, st); break;
-        case HZ_OP_VCYCLE: vcycle<float>(pr, lv, pr->opt.nu, xin, o, yout, o, 1, st); break;
-        case HZ_OP_COARSE_SOLVE: timed_coarse_solve<float>(pr, lv, xin, yout, 1, st); break;
-        case HZ_OP_COARSE_A: launch_stencil<float, float, float, float>(p, ST_APPLY, lv.coarse, xin, o, nullptr, o, yout, o, 1, st); break;
-        case HZ_OP_RESID_RESTRICT:
-          launch_stencil<float, float, float, float>(p, ST_RESID, lv.fine, xin, o, pr->af32, o, pr->s32.rf, o, 1, st);
-          launch_restrict<float>(p, pr->M, pr->Mc, pr->frw, pr->s32.rf, yout, 1, o, o, st);
-          break;
-      }
-      launch_f2d(yout, y, nout, st);
+      b.s32 = pr->s32;
+      b.ax32 = pr->ax32; b.af32 = pr->af32; b.ay32 = pr->ay32;
+      b.cx32 = pr->cx32; b.cy32 = pr->cy32;
     }
+    b.cw = pr->cw;
+    b.own = true;
+    apply_impl(pr, op, reinterpret_cast<const double2*>(d_x), reinterpret_cast<const double2*>(d_f),
+               reinterpret_cast<double2*>(d_y), prec, b, st);
+    return HZ_OK;
+  } catch (...) {
+    return map_exception();
+  }
+}
+
+hz_status hz_apply_noalloc(const hz_problem* cpr, int op, const hz_c64* d_x, const hz_c64* d_f,
+                           hz_c64* d_y, int prec, void* hip_stream) {
+  hz_problem* pr = const_cast<hz_problem*>(cpr);
+  hz_status v = check_apply(pr, op, d_x, d_f, d_y, prec);
+  if (v != HZ_OK) return v;
+  if (prec == HZ_MIXED && !pr->Sf)
+    return fail(HZ_EINVAL, "the problem holds no FP32 coarse factor (create it with HZ_MIXED, or "
+                           "run one mixed-precision hz_apply or hz_solve first)");
+  const size_t need = noalloc_bytes(pr->N, pr->Nc, prec);
+  if (need > kScratchBytes)
+    return fail(HZ_EINVAL, "the allocation-free apply needs " + std::to_string(need) +
+                               " scratch bytes for this problem; its maximum is " +
+                               std::to_string(kScratchBytes));
+  BusyGuard guard(pr->busy);
+  if (!guard.ok) return fail(HZ_EBUSY, "problem is in use");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  try {
+    char* base = noalloc_scratch();
+    ApplyBufs b = noalloc_layout(base, pr->N, pr->Nc, prec);
+    b.cw.persistent = pr->cw.persistent;
+    b.own = false;
+    // the coarse solve's timeout flag must start at zero (the array keeps the last call's
+    // contents); a fill kernel, not a memset, so that the call may be captured
+    launch_fill_zero(reinterpret_cast<double2*>(b.cw.err), 16, st);
+    set_stencil_tuning(false);
+    struct Restore { ~Restore() { set_stencil_tuning(true); } } restore;
+    apply_impl(pr, op, reinterpret_cast<const double2*>(d_x), reinterpret_cast<const double2*>(d_f),
+               reinterpret_cast<double2*>(d_y), prec, b, st);
     return HZ_OK;
   } catch (...) {
     return map_exception();

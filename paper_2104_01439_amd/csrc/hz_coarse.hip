@@ -997,28 +997,36 @@ constexpr size_t kLdsPerWorkgroup = 160 * 1024;   // gfx950
 // issued on. Each launch waits for an event recorded after the previous one (one event per
 // device, re-recorded under a process-wide lock; a wait binds to the latest record at the
 // time of the wait call).
+std::mutex& order_mu() {
+  static std::mutex m;
+  return m;
+}
+// per device: the event recorded after its latest persistent launch (created on first use,
+// or ahead of it by coarse_order_init); guarded by order_mu()
+std::map<int, std::pair<hipEvent_t, bool>>& order_events() {
+  static std::map<int, std::pair<hipEvent_t, bool>> m;
+  return m;
+}
+std::pair<hipEvent_t, bool>& order_event_locked(int dev) {
+  auto& m = order_events();
+  auto it = m.find(dev);
+  if (it == m.end()) {
+    hipEvent_t e = nullptr;
+    HZ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    it = m.emplace(dev, std::make_pair(e, false)).first;
+  }
+  return it->second;
+}
 struct PersistentOrder {
   std::unique_lock<std::mutex> lk;
-  hipEvent_t* ev = nullptr;
+  std::pair<hipEvent_t, bool>* ev = nullptr;
   hipStream_t st;
-  static std::mutex& mu() {
-    static std::mutex m;
-    return m;
-  }
-  PersistentOrder(int dev, hipStream_t s) : lk(mu()), st(s) {
-    static std::map<int, hipEvent_t> last;
-    auto it = last.find(dev);
-    if (it == last.end()) {
-      hipEvent_t e = nullptr;
-      HZ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      it = last.emplace(dev, e).first;
-    } else {
-      HZ_HIP(hipStreamWaitEvent(st, it->second, 0));
-    }
-    ev = &it->second;
+  PersistentOrder(int dev, hipStream_t s) : lk(order_mu()), st(s) {
+    ev = &order_event_locked(dev);
+    if (ev->second) HZ_HIP(hipStreamWaitEvent(st, ev->first, 0));
   }
   // after the launch was issued
-  ~PersistentOrder() { (void)hipEventRecord(*ev, st); }
+  ~PersistentOrder() { ev->second = hipEventRecord(ev->first, st) == hipSuccess; }
 };
 
 // Dynamic plus static LDS bytes of one k_csolve workgroup.
@@ -1176,6 +1184,11 @@ void factor_p(const CoarseLayout& L, const DevOp<double>& cop, double2* S,
 }
 
 }  // namespace
+
+void coarse_order_init(int dev) {
+  std::lock_guard<std::mutex> g(order_mu());
+  (void)order_event_locked(dev);
+}
 
 hz_status coarse_factor(const CoarseLayout& L, const DevOp<double>& cop, double2* S,
                         const CoarseFactorWork& w, hipStream_t st) {

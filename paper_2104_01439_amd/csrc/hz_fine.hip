@@ -317,6 +317,7 @@ void stencil_variant(int v, const DevOp<T>& op, const V2<TX>* x, Addr xs, const 
 // it is harmless) and keeps the fastest for the rest of the process. HZ_TUNE=0 disables it.
 std::mutex g_tune_mu;
 std::map<std::string, int> g_tune;
+thread_local bool tl_tune = true;
 
 int tuned_variant(const std::string& key, int nvar,
                   const std::function<void(int)>& launch, hipStream_t st) {
@@ -330,7 +331,8 @@ int tuned_variant(const std::string& key, int nvar,
     return !(e && e[0] == '0');
   }();
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (!enabled || hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+  if (!enabled || !tl_tune || hipStreamIsCapturing(st, &cs) != hipSuccess ||
+      cs != hipStreamCaptureStatusNone) {
     (void)hipGetLastError();
     return 0;
   }
@@ -399,6 +401,8 @@ void stencil_p(int mode, const DevOp<T>& op, const V2<TX>* x, Addr xs, const V2<
 }
 
 }  // namespace
+
+void set_stencil_tuning(bool on) { tl_tune = on; }
 
 template <typename T, typename TX, typename TF, typename TY>
 void launch_stencil(int p, int mode, const DevOp<T>& op, const V2<TX>* x, Addr xs,

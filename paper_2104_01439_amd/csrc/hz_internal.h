@@ -164,6 +164,12 @@ template <typename T>
 int coarse_solve(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b,
                  V2<T>* y, int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st);
 void launch_factor_to_f32(const double2* S, float2* Sf, size_t n, hipStream_t st);
+// Creates the per-device event that orders persistent coarse-solve launches (otherwise made
+// by the first such launch on the device).
+void coarse_order_init(int dev);
+// Stencil launches of the calling thread pick a variant without timing any (the cached
+// choice, else variant 0; every variant gives the same result) while this is off.
+void set_stencil_tuning(bool on);
 
 // Krylov kernels. Vectors of length N; a basis V is row-major [nv][ldv].
 // Batched forms run nbatch independent instances: instance z uses V + av.at(z), w + aw.at(z),

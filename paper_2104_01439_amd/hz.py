@@ -93,6 +93,7 @@ _SIGS = {
     "hz_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(Options), ctypes.POINTER(Result),
                                 ctypes.POINTER(ctypes.c_double), _P]),
     "hz_apply": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_int, _P]),
+    "hz_apply_noalloc": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_int, _P]),
     "hz_solve_batched": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_P),
                                         ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(Options),
                                         ctypes.POINTER(Result), _P]),
@@ -226,11 +227,14 @@ class Problem:
             out["hist"] = list(hist[: res.iterations])
         return u, out
 
-    def apply(self, op, x, f=None, prec="fp64"):
+    def apply(self, op, x, f=None, prec="fp64", y=None, noalloc=False):
+        """y = op(x[, f]) by hz_apply, or by hz_apply_noalloc (the library allocates nothing;
+        y is allocated here unless given)."""
         op_id = OPS[op]
         coarse_out = op in ("RESTRICT", "COARSE_SOLVE", "COARSE_A", "RESID_RESTRICT")
-        y = self.empty(coarse=coarse_out)
-        _check(lib().hz_apply(self._h, op_id, _ptr(x), _ptr(f), _ptr(y), _PREC[prec], _stream()))
+        y = self.empty(coarse=coarse_out) if y is None else y
+        fn = lib().hz_apply_noalloc if noalloc else lib().hz_apply
+        _check(fn(self._h, op_id, _ptr(x), _ptr(f), _ptr(y), _PREC[prec], _stream()))
         return y
 
     def close(self):

@@ -105,6 +105,7 @@ def test_null_arguments(hz):
     L = hz.lib()
     assert L.hz_solve(None, None, None, None, None, None, None) == hz.HZ_EINVAL
     assert L.hz_apply(None, 0, None, None, None, 0, None) == hz.HZ_EINVAL
+    assert L.hz_apply_noalloc(None, 0, None, None, None, 0, None) == hz.HZ_EINVAL
     assert L.hz_problem_info(None, None, None, None) == hz.HZ_EINVAL
     L.hz_destroy_problem(None)
 
