@@ -22,8 +22,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-from paper_2104_01439_amd.roofline import (HBM_PEAK_GBS, coarse_solve_bytes,  # noqa: E402
-                                           factor_bytes)
+from paper_2104_01439_amd.roofline import (FP64_MFMA_PEAK_TFLOPS, HBM_PEAK_GBS,  # noqa: E402
+                                           STENCIL_BYTES_PER_DOF, coarse_solve_bytes,
+                                           factor_bytes, factor_flops)
 
 
 def log(msg):
@@ -45,6 +46,83 @@ def measured_traffic(path="profiles/k_csolve_p1_k400_n2048_traffic.txt"):
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def host_cpu():
+    """CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    return model, ncpu
+
+
+def cpu_baseline_both(cfg, iterations):
+    """The oracle's projected solve rate with its default threads (threaded BLAS in the
+    banded LU and the dense products; the sparse products are single-threaded) and again
+    limited to one thread."""
+    from threadpoolctl import threadpool_limits
+    allc = cpu_baseline(cfg, iterations)
+    with threadpool_limits(limits=1):
+        one = cpu_baseline(cfg, iterations)
+    model, ncpu = host_cpu()
+    allc["cpu_model"] = model
+    allc["nproc"] = ncpu
+    allc["one_thread"] = {"value": one["value"], "unit": one["unit"], "cores": 1,
+                          "projected_s_per_solve": one["projected_s_per_solve"],
+                          "sample_wall_s": one["sample_wall_s"]}
+    return allc
+
+
+def stencil_rates(cfg, prec, reps=20):
+    """Live device time of each fine-level pass of the V-cycle at the workload's size (HIP
+    events on the launch stream, `reps` back-to-back launches after a warm-up that also lets
+    the tile autotuner settle), against its algorithmic bytes."""
+    import torch
+    from paper_2104_01439_amd import hz, inputs
+
+    k, n, p, s = cfg["k"], cfg["n"], cfg["p"], cfg["s"]
+    pr = hz.Problem(k, 1.0 / n, p, s, nu=cfg["nu"], omega=cfg["omega"], prec=prec)
+    x = torch.from_numpy(inputs.random_complex(pr.N, seed=5)).cuda()
+    f = torch.from_numpy(inputs.random_complex(pr.N, seed=6)).cuda()
+    xc = torch.from_numpy(inputs.random_complex(pr.Nc, seed=7)).cuda()
+    yf, yc = pr.empty(), pr.empty(coarse=True)
+    B = STENCIL_BYTES_PER_DOF
+    item = 16 if prec == "fp64" else 8
+    passes = {
+        "A0 apply": ("A0", x, None, yf, B["a0_apply"], 1),
+        "Jacobi sweep": ("JACOBI", x, f, yf, B["jacobi_sweep"], 1),
+        "residual + restriction (2 kernels)": ("RESID_RESTRICT", x, f, yc,
+                                               B["residual"] + B["restriction"], 2),
+        "restriction": ("RESTRICT", x, None, yc, B["restriction"], 1),
+        "prolongation": ("PROLONG", xc, None, yf, B["prolongation"], 1),
+    }
+    out = {}
+    for name, (op, a, b, y, bpd, nk) in passes.items():
+        for _ in range(3):
+            pr.apply(op, a, b, y=y, prec=prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            pr.apply(op, a, b, y=y, prec=prec)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = bpd * (item / 16) * pr.N / (ms * 1e-3) / 1e9
+        out[name] = {"us": 1e3 * ms, "bytes_per_dof": bpd * item / 16, "kernels": nk,
+                     "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS}
+    pr.close()
+    return out
 
 
 def cpu_baseline(cfg, iterations):
@@ -470,12 +548,17 @@ def main():
     cfg = cfgs[a.workload]
     g = run_gpu(cfg, a.steps, a.warmup, a.prec)
     value = a.steps / g["seconds"]
+    log("fine-level passes: live timing at the workload's size ...")
+    stencils = stencil_rates(cfg, a.prec)
     cpu = None
     if not a.no_cpu:
-        log("cpu baseline: timing the oracle on a bounded sample ...")
-        cpu = cpu_baseline(cfg, g["iterations"][-1])
-        log(f"cpu baseline: {cpu['sample_wall_s']:.1f} s of sampling, projected "
-            f"{cpu['projected_s_per_solve']:.0f} s per solve")
+        log("cpu baseline: timing the oracle on a bounded sample (default threads, then one) ...")
+        cpu = cpu_baseline_both(cfg, g["iterations"][-1])
+        log(f"cpu baseline: projected {cpu['projected_s_per_solve']:.0f} s per solve "
+            f"({cpu['cores']} threads), {cpu['one_thread']['projected_s_per_solve']:.0f} s "
+            "on one thread")
+    fflop = factor_flops(cfg["n"], cfg["p"])
+    ftf = fflop / (g["factor_ms"] * 1e-3) / 1e12
     cs_gbs = g["coarse_bytes"] / (g["coarse_ms"] * 1e-3) / 1e9
     out = {
         "metric": "FGMRES solves/s",
@@ -502,9 +585,26 @@ def main():
                      "bytes_per_launch": g["coarse_bytes"], "avg_launch_ms": g["coarse_ms"],
                      "launches": g["coarse_launches"]},
         "setup_factor_ms": g["factor_ms"],
+        "factorisation": {"kernel": "coarse block factorisation (Schur complements, "
+                                    "Gauss-Jordan panels and FP64 MFMA updates)",
+                          "bound": "mfma", "ms": g["factor_ms"], "flop": fflop,
+                          "achieved_tflops": ftf, "peak_tflops": FP64_MFMA_PEAK_TFLOPS,
+                          "frac": ftf / FP64_MFMA_PEAK_TFLOPS},
+        "stencil_passes": stencils,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    release()
+
+
+def release():
+    """Frees every device object before the interpreter exits (problems are closed by the
+    steps; this drops torch's cached blocks once the device is idle)."""
+    import gc
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
 
 
 def main_sweep(a, cfg):

@@ -70,6 +70,9 @@ def main(argv=None):
         b = coarse_solve_bytes(n, p, item)
         out["coarse_solve"] = {"bytes": b, "ms": ms, "GB/s": b / (ms * 1e-3) / 1e9}
     pr.close()
+    del F
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
     return 0
 

@@ -2,6 +2,20 @@
 hardware moved) and the MI355X peaks they are set against."""
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix, published
+
+# Algorithmic bytes per fine dof of the fine-level passes (complex FP64 = 16 B; each operand
+# counted once; a coarse vector is a quarter of a fine one):
+#   A_0 apply        x read, y written                          32
+#   first sweep      f read, u = omega D^-1 f written            32
+#   Jacobi sweep     u, f read, u' written                       48
+#   residual         u, f read, r written                        48
+#   restriction      r read, r_c written (1/4)                   20
+#   prolongation     e_c read (1/4), P e_c written               20
+#   prolongation+add e_c read (1/4), u read, u + P e_c written   36
+STENCIL_BYTES_PER_DOF = {"a0_apply": 32, "jacobi_first": 32, "jacobi_sweep": 48,
+                         "residual": 48, "restriction": 20, "prolongation": 20,
+                         "prolongation_add": 36}
 
 
 def coarse_solve_bytes(n, p, itemsize=16, nrhs=1):
@@ -26,3 +40,11 @@ def stencil_apply_bytes(n, p, itemsize=16):
     """y = A x on the fine lattice: x read once, y written once."""
     M = p * n + 1
     return 2 * M * M * itemsize
+
+
+def factor_flops(n, p):
+    """Real flops of the coarse block factorisation: every block inverted by Gauss-Jordan,
+    (p Mc)^3 complex multiply-adds (8 real flops each) per block."""
+    nc = n // 2
+    Mc = p * nc + 1
+    return 8.0 * (nc * float(p * Mc) ** 3 + float(Mc) ** 3)
