@@ -1416,8 +1416,8 @@ hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_option
       CoarseFactorWork wk;
       const size_t mb = size_t(pr->L.size(0));
       wk.T = pr->mem.alloc_async<double2>(2 * mb * mb, st);     // one set per chain
-      wk.W = pr->mem.alloc_async<double2>(2 * mb * 32, st);
-      wk.R = pr->mem.alloc_async<double2>(2 * mb * 32, st);
+      wk.W = pr->mem.alloc_async<double2>(2 * sweep_panel_elems(mb), st);
+      wk.R = pr->mem.alloc_async<double2>(2 * sweep_pinv_elems(), st);
       wk.flag = pr->mem.alloc_async<int>(1, st);
       const DevOp<double> cop{pr->cAc, nullptr, pr->Mc};
       pr->timing = opt.timing != 0;

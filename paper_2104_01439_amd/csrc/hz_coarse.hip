@@ -22,7 +22,6 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int NB = 32;   // Gauss-Jordan panel width
 
 __device__ __forceinline__ int region(int a, int M) { return a == 0 ? 0 : (a == M - 1 ? 2 : 1); }
 
@@ -112,45 +111,127 @@ k_schur_left(int j, int jn, int nc, int Mc, const double2* __restrict__ coef,
 }
 
 // ------------------------------------------------------------------------------------------
-// Blocked Gauss-Jordan inversion, in place. One panel K = [k0, k0 + w), w <= NB = 32, with
-// Pinv = X[K,K]^{-1} and W[i,:] = X[i,K] Pinv:
-//   X[K,K] <- Pinv,   X[i,K] <- -W[i,:],   X[K,j] <- Pinv X[K,j],   X[i,j] <- X[i,j] - W[i,:] X[K,j]
-// for i, j outside K. Panels and 32 x 32 tiles are aligned, so every tile of the update is
-// entirely in the pivot rows, the pivot columns, or neither (no cancellation-prone forms).
-// The panel kernel writes Wt (rows outside K: W, rows in K: Pinv) and Rt = X[K, :].
+// Block inversion by the symmetric Gauss-Jordan sweep. D_j is complex symmetric (A_eps is,
+// and a Schur complement of a complex symmetric matrix with transposed couplings is too), so
+// the sweep keeps every intermediate symmetric and only the upper 32 x 32 tiles are updated.
+// One pass per pivot tile K (width w <= 32), with P = X[K,K]^{-1} and the pivot row panel
+// R[t] = X[K,t] (taken from the upper tile (K,t), or transposed from (t,K) when t < K):
+//   X[K,K] <- -P,   X[K,t] <- P R[t],   X[t,K] <- (P R[t])^T,
+//   X[i,t] <- X[i,t] - (P R[i])^T R[t]                      for i, t != K.
+// After every pivot the block holds -D^{-1}; a final pass negates it and mirrors the upper
+// tiles into the lower ones, leaving S = D^{-1} dense and row-major for the solves.
+// Without pivoting this is safe for the same reason as the block LU: every leading pivot
+// block is a Schur complement of i D, whose Hermitian part is positive definite.
+//
+// Pass K is one launch. Workgroup 0 already forms the next pass's pivot block
+// X[K+1,K+1] - (P R[K+1])^T R[K+1] and inverts it (32 Gauss-Jordan steps in LDS), so that no
+// pass waits for a separate panel kernel; the other workgroups update one upper tile per
+// wave on FP64 MFMA and write the next pivot row panel as they go. Panels and pivot inverses
+// are double-buffered by pass parity.
 // ------------------------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256)
-k_gj_panel(const double2* __restrict__ X, int n, int k0, int w, double2* __restrict__ Wt,
-           double2* __restrict__ Rt, int* __restrict__ flag) {
-  __shared__ double2 Y[2][NB][NB + 1];         // double-buffered Gauss-Jordan on X[K,K]
-  __shared__ double2 Xp[32][NB + 1];            // this workgroup's rows of X[:, K]
+constexpr int SB = 32;   // tile and pivot panel width
+
+struct SweepPass {
+  double2* X;            // the block, row-major n x n
+  int n, T;              // size, tiles per side
+  int K;                 // pivot tile of this pass
+  const double2* Rc;     // this pass's pivot row panel [32][T*32] (zero beyond n)
+  double2* Rn;           // the next pass's
+  const double2* Pc;     // this pass's pivot inverse, 32 x 32 row-major (zero beyond w)
+  double2* Pn;           // the next pass's
+  int* flag;             // set on a zero or non-finite pivot
+};
+
+// Complex MFMA step C += (sa a) b on 16 x 16 blocks (a, b: this lane's operand values).
+__device__ __forceinline__ void cmfma(v4d& cr, v4d& ci, double2 a, double2 b, double sa) {
+  cr = __builtin_amdgcn_mfma_f64_16x16x4f64(sa * a.x, b.x, cr, 0, 0, 0);
+  cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-sa * a.y, b.y, cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f64_16x16x4f64(sa * a.x, b.y, ci, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f64_16x16x4f64(sa * a.y, b.x, ci, 0, 0, 0);
+}
+
+// Rs = P R[t] for the 16 x 16 output blocks (bp, bq), bq in [BQ0, BQ1). Lane l of block
+// (bp, bq) holds Rs[16 bp + l/16 + 4 r][16 bq + l%16] in register r (the FP64 MFMA output
+// layout), which is also the A-operand layout of Rs^T for the k-step 16 bp + 4 r.
+template <int BQ0, int BQ1>
+__device__ __forceinline__ void sweep_pr(const SweepPass& a, int t, v4d (&sr)[2][2],
+                                         v4d (&si)[2][2]) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int ld = a.T * SB;
+#pragma unroll
+  for (int bp = 0; bp < 2; ++bp)
+#pragma unroll
+    for (int bq = BQ0; bq < BQ1; ++bq) { sr[bp][bq] = v4d{0, 0, 0, 0}; si[bp][bq] = v4d{0, 0, 0, 0}; }
+#pragma unroll
+  for (int k0 = 0; k0 < SB; k0 += 4) {
+    double2 av[2], bv[2];
+#pragma unroll
+    for (int bp = 0; bp < 2; ++bp) av[bp] = a.Pc[(16 * bp + li) * SB + k0 + lk];
+#pragma unroll
+    for (int bq = BQ0; bq < BQ1; ++bq) bv[bq] = a.Rc[size_t(k0 + lk) * ld + t * SB + 16 * bq + li];
+#pragma unroll
+    for (int bp = 0; bp < 2; ++bp)
+#pragma unroll
+      for (int bq = BQ0; bq < BQ1; ++bq) cmfma(sr[bp][bq], si[bp][bq], av[bp], bv[bq], 1.0);
+  }
+}
+
+// C -= Rs^T R[tj] for output blocks (bm, bn), bm in [BM0, BM1), bn in [BN0, BN1); Rs blocks
+// (., bm) as left by sweep_pr.
+template <int BM0, int BM1, int BN0, int BN1>
+__device__ __forceinline__ void sweep_upd(const SweepPass& a, int tj, const v4d (&sr)[2][2],
+                                          const v4d (&si)[2][2], v4d (&cr)[2][2],
+                                          v4d (&ci)[2][2]) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int ld = a.T * SB;
+#pragma unroll
+  for (int k0 = 0; k0 < SB; k0 += 4) {
+    double2 bv[2];
+#pragma unroll
+    for (int bn = BN0; bn < BN1; ++bn) bv[bn] = a.Rc[size_t(k0 + lk) * ld + tj * SB + 16 * bn + li];
+#pragma unroll
+    for (int bm = BM0; bm < BM1; ++bm) {
+      const double2 av = make_double2(sr[k0 >> 4][bm][(k0 >> 2) & 3], si[k0 >> 4][bm][(k0 >> 2) & 3]);
+#pragma unroll
+      for (int bn = BN0; bn < BN1; ++bn) cmfma(cr[bm][bn], ci[bm][bn], av, bv[bn], -1.0);
+    }
+  }
+}
+
+// Loads the upper tile (ti, tj) into the MFMA output layout (zero beyond n). A diagonal
+// tile is read from its upper triangle only (mirrored), so that every matrix the sweep works
+// on is exactly symmetric: rounding differences between the two triangles of the diagonal
+// tiles would otherwise be amplified from block to block along the factorisation chain.
+__device__ __forceinline__ void sweep_load(const SweepPass& a, int ti, int tj, v4d (&cr)[2][2],
+                                           v4d (&ci)[2][2]) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = ti * SB + 16 * bm + lk + 4 * r, col = tj * SB + 16 * bn + li;
+        if (row > col) { const int q = row; row = col; col = q; }   // diagonal tiles only
+        double2 v = make_double2(0, 0);
+        if (row < a.n && col < a.n) v = a.X[size_t(row) * a.n + col];
+        cr[bm][bn][r] = v.x;
+        ci[bm][bn][r] = v.y;
+      }
+}
+
+// Inverts the w x w leading part of the 32 x 32 block in Y[0] by w Gauss-Jordan sweep steps
+// (the rest is the identity) and writes P = its inverse (zero outside w x w) to dst. The
+// block is first made exactly symmetric from its upper triangle, and P is written from the
+// upper triangle of the result. 256 threads, double-buffered LDS, one barrier per step.
+__device__ void sweep_invert(double2 (*Y)[SB][SB + 1], int w, double2* __restrict__ dst,
+                             int* flag) {
   const int tid = threadIdx.x;
-  const int base = blockIdx.x * 32;
-  // coalesced staging, all loads in flight at once: the diagonal panel block, this
-  // workgroup's rows of the column panel and its columns of the row panel
-  {
-    double2 vy[4], vx[4], vr[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + 256 * q;
-      const int r = idx / NB, c = idx % NB;
-      vy[q] = make_double2(r == c ? 1.0 : 0.0, 0.0);
-      if (r < w && c < w) vy[q] = X[size_t(k0 + r) * n + k0 + c];
-      const int i = base + r;
-      vx[q] = (i < n && c < w) ? X[size_t(i) * n + k0 + c] : make_double2(0, 0);
-      const int jj = base + idx % 32, kk = idx / 32;
-      vr[q] = (jj < n && kk < w) ? X[size_t(k0 + kk) * n + jj] : make_double2(0, 0);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + 256 * q;
-      const int r = idx / NB, c = idx % NB;
-      Y[0][r][c] = vy[q];
-      Xp[r][c] = vx[q];
-      const int jj = base + idx % 32, kk = idx / 32;
-      if (jj < n) Rt[size_t(kk) * n + jj] = vr[q];
-    }
+  for (int q = 0; q < 4; ++q) {
+    const int idx = tid + 256 * q, r = idx / SB, c = idx % SB;
+    if (r > c) Y[0][r][c] = Y[0][c][r];
   }
   __syncthreads();
   bool bad = false;
@@ -159,7 +240,8 @@ k_gj_panel(const double2* __restrict__ X, int n, int k0, int w, double2* __restr
     const double2 pv = Y[cur][t][t];
     const double mag = pv.x * pv.x + pv.y * pv.y;
     if (!(mag > 0.0) || !isfinite(mag)) bad = true;
-    // 1/mag: hardware reciprocal refined by two Newton steps (full double precision)
+    // 1/mag: hardware reciprocal refined by two Newton steps (full double precision; shorter
+    // than the IEEE division sequence on the step's critical path)
     double rm = __builtin_amdgcn_rcp(mag);
     rm = rm * (2.0 - mag * rm);
     rm = rm * (2.0 - mag * rm);
@@ -167,133 +249,193 @@ k_gj_panel(const double2* __restrict__ X, int n, int k0, int w, double2* __restr
     double2 yrt[4], ytc[4], yrc[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int idx = tid + 256 * q;
-      const int r = idx / NB, c = idx % NB;
+      const int idx = tid + 256 * q, r = idx / SB, c = idx % SB;
       yrt[q] = Y[cur][r][t];
       ytc[q] = Y[cur][t][c];
       yrc[q] = Y[cur][r][c];
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int idx = tid + 256 * q;
-      const int r = idx / NB, c = idx % NB;
+      const int idx = tid + 256 * q, r = idx / SB, c = idx % SB;
       double2 v;
       if (r == t) {
-        v = (c == t) ? pinv : cmul<double>(ytc[q], pinv);
+        v = (c == t) ? make_double2(-pinv.x, -pinv.y) : cmul<double>(ytc[q], pinv);
       } else if (c == t) {
-        const double2 a = cmul<double>(yrt[q], pinv);
-        v = make_double2(-a.x, -a.y);
+        v = cmul<double>(yrt[q], pinv);
       } else {
-        const double2 a = cmul<double>(yrt[q], pinv), b = ytc[q];
+        const double2 g = cmul<double>(yrt[q], pinv);
         v = yrc[q];
-        v.x -= a.x * b.x - a.y * b.y;
-        v.y -= a.x * b.y + a.y * b.x;
+        v.x -= g.x * ytc[q].x - g.y * ytc[q].y;
+        v.y -= g.x * ytc[q].y + g.y * ytc[q].x;
       }
       Y[cur ^ 1][r][c] = v;
     }
     cur ^= 1;
     __syncthreads();
   }
-  if (bad && tid == 0 && blockIdx.x == 0) *flag = 1;
-  for (int idx = tid; idx < 32 * NB; idx += 256) {
-    const int r = idx / NB, kk = idx % NB;
-    const int i = base + r;
-    if (i >= n) continue;
-    double2 v = make_double2(0, 0);
-    if (kk < w) {
-      if (i >= k0 && i < k0 + w) {
-        v = Y[cur][i - k0][kk];
-      } else {
-#pragma unroll 8
-        for (int t = 0; t < NB; ++t) cfma(v, Xp[r][t], Y[cur][t][kk]);
-      }
-    }
-    Wt[size_t(i) * NB + kk] = v;
+  if (bad) atomicOr(flag, 1);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = tid + 256 * q, r = idx / SB, c = idx % SB;
+    const double2 v = Y[cur][min(r, c)][max(r, c)];
+    dst[idx] = (r < w && c < w) ? make_double2(-v.x, -v.y) : make_double2(0, 0);
   }
 }
 
-// Tile update on FP64 MFMA. Each wave owns a 32 x 32 tile (2 x 2 blocks of 16 x 16);
-// operands are read straight from the (L2-resident) panels.
-// v_mfma_f64_16x16x4: lane l holds A[l%16][l/16], B[l/16][l%16] and D[l/16 + 4r][l%16]
-// (r = 0..3; the FP64 layout interleaves rows by 4, checked on the device).
+// Before the first pass: the pivot row panel of tile 0 (workgroups 1..T) and the inverse of
+// the first pivot block (workgroup 0).
 __global__ void __launch_bounds__(256)
-k_gj_update(double2* __restrict__ X, int n, int k0, const double2* __restrict__ Wt,
-            const double2* __restrict__ Rt) {
-  const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int tiles = (n + 31) / 32;
-  if (wave >= tiles * tiles) return;
-  const int ti = wave / tiles, tj = wave % tiles;
-  const int kt = k0 / 32;
-  const int i0 = ti * 32, j0 = tj * 32;
-  const int li = lane & 15, lk = lane >> 4;
-  if (tj == kt) {
-    // pivot columns: X[i,K] = -W[i,:] (i outside K), X[K,K] = Pinv
-    for (int e = lane; e < 32 * 32; e += 64) {
-      const int r = e / 32, c = e % 32;
-      const int row = i0 + r, col = j0 + c;
-      if (row < n && col < n) {
-        double2 v = Wt[size_t(row) * NB + c];
-        if (ti != kt) v = make_double2(-v.x, -v.y);
-        X[size_t(row) * n + col] = v;
+k_sweep_first(SweepPass a) {
+  __shared__ double2 Y[2][SB][SB + 1];
+  const int tid = threadIdx.x;
+  const int ld = a.T * SB;
+  if (blockIdx.x == 0) {
+    const int w = min(SB, a.n);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q, r = idx / SB, c = idx % SB;
+      Y[0][r][c] = (r < w && c < w) ? a.X[size_t(r) * a.n + c]
+                                    : make_double2(r == c ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    sweep_invert(Y, w, a.Pn, a.flag);
+    return;
+  }
+  const int t = blockIdx.x - 1;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = tid + 256 * q, r = idx / SB, c = idx % SB;
+    const int col = t * SB + c;
+    a.Rn[size_t(r) * ld + col] = (r < a.n && col < a.n) ? a.X[size_t(r) * a.n + col]
+                                                        : make_double2(0, 0);
+  }
+}
+
+// One pass of the sweep (pivot tile K). Workgroup 0 prepares the next pass's pivot inverse;
+// every other wave owns one upper tile (ti <= tj).
+__global__ void __launch_bounds__(256)
+k_sweep_pass(SweepPass a) {
+  __shared__ double2 Y[2][SB][SB + 1];
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int wave = threadIdx.x >> 6;
+  const int K = a.K, T = a.T, n = a.n, ld = T * SB;
+  if (blockIdx.x == 0) {
+    if (K + 1 >= T) return;
+    // X[K+1,K+1] - (P R[K+1])^T R[K+1]: wave w forms output block (w/2, w%2)
+    const int t1 = K + 1;
+    v4d sr[2][2], si[2][2], cr[2][2], ci[2][2];
+    sweep_load(a, t1, t1, cr, ci);
+    const int bm = wave >> 1, bn = wave & 1;
+    if (bm == 0) sweep_pr<0, 1>(a, t1, sr, si); else sweep_pr<1, 2>(a, t1, sr, si);
+    if (bm == 0 && bn == 0) sweep_upd<0, 1, 0, 1>(a, t1, sr, si, cr, ci);
+    else if (bm == 0) sweep_upd<0, 1, 1, 2>(a, t1, sr, si, cr, ci);
+    else if (bn == 0) sweep_upd<1, 2, 0, 1>(a, t1, sr, si, cr, ci);
+    else sweep_upd<1, 2, 1, 2>(a, t1, sr, si, cr, ci);
+    const int w = min(SB, n - t1 * SB);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = 16 * bm + lk + 4 * r, c = 16 * bn + li;
+      const double2 v = make_double2(cr[bm][bn][r], ci[bm][bn][r]);
+      Y[0][m][c] = (m < w && c < w) ? v : make_double2(m == c ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    sweep_invert(Y, w, a.Pn, a.flag);
+    return;
+  }
+  // tile of this wave (wave-uniform)
+  int u = (blockIdx.x - 1) * 4 + wave;
+  const int nu = T * (T + 1) / 2;
+  if (u >= nu) return;
+  int ti = 0;
+  while (u >= T - ti) { u -= T - ti; ++ti; }
+  const int tj = ti + u;
+  if (ti == K + 1 && tj == K + 1) return;     // replaced by the next pass's pivot inverse
+  v4d sr[2][2], si[2][2], cr[2][2], ci[2][2];
+  bool transposed = false;                    // the result is Rs^T (pivot column tile)
+  if (ti == K && tj == K) {
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double2 v = a.Pc[(16 * bm + lk + 4 * r) * SB + 16 * bn + li];
+          cr[bm][bn][r] = -v.x;
+          ci[bm][bn][r] = -v.y;
+        }
+  } else if (ti == K) {
+    sweep_pr<0, 2>(a, tj, cr, ci);           // X[K,tj] = P R[tj]
+  } else if (tj == K) {
+    sweep_pr<0, 2>(a, ti, cr, ci);           // X[ti,K] = (P R[ti])^T
+    transposed = true;
+  } else {
+    sweep_load(a, ti, tj, cr, ci);
+    sweep_pr<0, 2>(a, ti, sr, si);
+    sweep_upd<0, 2, 0, 2>(a, tj, sr, si, cr, ci);
+  }
+  // store (rows and columns beyond n are not stored); tiles in the next pivot row or column
+  // also go to the next pass's panel: R'[t] = X[K+1, t]
+  const bool nrow = ti == K + 1, ncol = tj == K + 1;
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double2 v = make_double2(cr[bm][bn][r], ci[bm][bn][r]);
+        // element (m, c) of the computed 32 x 32 result; transposed results land at (c, m)
+        const int m = 16 * bm + lk + 4 * r, c = 16 * bn + li;
+        const int tm = transposed ? c : m, tc = transposed ? m : c;   // position in the tile
+        const int row = ti * SB + tm, col = tj * SB + tc;
+        if (row < n && col < n) a.X[size_t(row) * n + col] = v;
+        if (nrow) a.Rn[size_t(tm) * ld + tj * SB + tc] = v;
+        if (ncol) a.Rn[size_t(tc) * ld + ti * SB + tm] = v;
       }
+}
+
+// Final pass: S = -X, the upper tiles negated in place and mirrored into the lower ones
+// (diagonal tiles from their upper triangle).
+__global__ void __launch_bounds__(256)
+k_sweep_last(double2* __restrict__ X, int n, int T) {
+  __shared__ double2 L[SB][SB + 1];
+  int u = blockIdx.x;
+  int ti = 0;
+  while (u >= T - ti) { u -= T - ti; ++ti; }
+  const int tj = ti + u;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = tid + 256 * q, r = idx / SB, c = idx % SB;
+    const int row = ti * SB + r, col = tj * SB + c;
+    double2 v = make_double2(0, 0);
+    if (row < n && col < n) {
+      v = X[size_t(row) * n + col];
+      v = make_double2(-v.x, -v.y);
+    }
+    L[r][c] = v;
+  }
+  __syncthreads();
+  if (ti == tj) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q, r = idx / SB, c = idx % SB;
+      const int row = ti * SB + r, col = tj * SB + c;
+      if (row < n && col < n) X[size_t(row) * n + col] = L[min(r, c)][max(r, c)];
     }
     return;
   }
-  const bool pivot_rows = ti == kt;        // X[K,j] = Pinv X[K,j]; else X -= W X[K,j]
-  v4d cre[2][2], cim[2][2];
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = i0 + bi * 16 + lk + 4 * r, col = j0 + bj * 16 + li;
-        double2 v = make_double2(0, 0);
-        if (!pivot_rows && row < n && col < n) v = X[size_t(row) * n + col];
-        cre[bi][bj][r] = v.x;
-        cim[bi][bj][r] = v.y;
-      }
-  const double sg = pivot_rows ? 1.0 : -1.0;
-#pragma unroll
-  for (int k = 0; k < NB; k += 4) {
-    double are[2], aim[2], bre[2], bim[2];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi) {
-      const int row = i0 + bi * 16 + li;
-      double2 a = make_double2(0, 0);
-      if (row < n) a = Wt[size_t(row) * NB + k + lk];
-      are[bi] = sg * a.x;
-      aim[bi] = sg * a.y;
-    }
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      const int col = j0 + bj * 16 + li;
-      double2 b = make_double2(0, 0);
-      if (col < n) b = Rt[size_t(k + lk) * n + col];
-      bre[bj] = b.x;
-      bim[bj] = b.y;
-    }
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) {
-        // C += (sg a) b: re += are*bre - aim*bim, im += are*bim + aim*bre
-        cre[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[bi], bre[bj], cre[bi][bj], 0, 0, 0);
-        cre[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-aim[bi], bim[bj], cre[bi][bj], 0, 0, 0);
-        cim[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[bi], bim[bj], cim[bi][bj], 0, 0, 0);
-        cim[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[bi], bre[bj], cim[bi][bj], 0, 0, 0);
-      }
+  for (int q = 0; q < 4; ++q) {
+    const int idx = tid + 256 * q, r = idx / SB, c = idx % SB;
+    const int row = ti * SB + r, col = tj * SB + c;
+    if (row < n && col < n) X[size_t(row) * n + col] = L[r][c];
   }
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = i0 + bi * 16 + lk + 4 * r, col = j0 + bj * 16 + li;
-        if (row < n && col < n) X[size_t(row) * n + col] = make_double2(cre[bi][bj][r], cim[bi][bj][r]);
-      }
+  for (int q = 0; q < 4; ++q) {
+    const int idx = tid + 256 * q, r = idx / SB, c = idx % SB;
+    const int row = tj * SB + r, col = ti * SB + c;
+    if (row < n && col < n) X[size_t(row) * n + col] = L[c][r];
+  }
 }
 
 __global__ void k_factor_to_f32(const double2* __restrict__ S, float2* __restrict__ Sf, size_t n) {
@@ -1128,6 +1270,13 @@ int csolve_jobs_p(const CoarseLayout& L, const CoarseJob<T>* jobs, int njobs, lo
 // Twisted block LU: the top chain factors blocks 0 .. m-1 downwards (D_j against j-1), the
 // bottom chain blocks nb-1 .. m+1 upwards (D_j against j+1), on two streams; the middle
 // block m takes both Schur complements. Each inverse is stored in place of its block.
+}  // namespace
+
+size_t sweep_panel_elems(size_t nmax) { return 2 * size_t(SB) * ((nmax + SB - 1) / SB) * SB; }
+size_t sweep_pinv_elems() { return 2 * size_t(SB) * SB; }
+
+namespace {
+
 template <int P>
 void factor_block(const CoarseLayout& L, const DevOp<double>& cop, double2* S, int j, int jn1,
                   int jn2, double2* T, double2* W, double2* R, int* flag, hipStream_t st) {
@@ -1142,13 +1291,30 @@ void factor_block(const CoarseLayout& L, const DevOp<double>& cop, double2* S, i
                                                                 S + L.off(jn), nn, n, T);
     k_schur_left<P><<<g2, 256, 0, st>>>(j, jn, L.nc, L.Mc, cop.coef, T, n, D);
   }
-  const int tiles = (n + 31) / 32;
-  const int upd_blocks = (tiles * tiles + 3) / 4;
-  for (int k0 = 0; k0 < n; k0 += NB) {
-    const int wdt = std::min(NB, n - k0);
-    k_gj_panel<<<(n + 31) / 32, 256, 0, st>>>(D, n, k0, wdt, W, R, flag);
-    k_gj_update<<<upd_blocks, 256, 0, st>>>(D, n, k0, W, R);
+  // symmetric sweep: first panel and pivot inverse, one launch per pivot tile, final mirror
+  const int nt = (n + SB - 1) / SB;
+  const size_t ld = size_t(nt) * SB;
+  SweepPass a;
+  a.X = D;
+  a.n = n;
+  a.T = nt;
+  a.flag = flag;
+  a.K = -1;
+  a.Rc = nullptr;
+  a.Pc = nullptr;
+  a.Rn = W;
+  a.Pn = R;
+  k_sweep_first<<<nt + 1, 256, 0, st>>>(a);
+  const int nu = nt * (nt + 1) / 2;
+  for (int K = 0; K < nt; ++K) {
+    a.K = K;
+    a.Rc = W + size_t(K & 1) * SB * ld;
+    a.Rn = W + size_t((K + 1) & 1) * SB * ld;
+    a.Pc = R + size_t(K & 1) * SB * SB;
+    a.Pn = R + size_t((K + 1) & 1) * SB * SB;
+    k_sweep_pass<<<1 + (nu + 3) / 4, 256, 0, st>>>(a);
   }
+  k_sweep_last<<<nu, 256, 0, st>>>(D, n, nt);
 }
 
 template <int P>
@@ -1165,8 +1331,8 @@ void factor_p(const CoarseLayout& L, const DevOp<double>& cop, double2* S,
   HZ_HIP(hipStreamWaitEvent(s2, fork, 0));
   // top chain on st, bottom chain on s2 (own temporaries)
   double2* T2 = w.T + mb * mb;
-  double2* W2 = w.W + mb * NB;
-  double2* R2 = w.R + mb * NB;
+  double2* W2 = w.W + sweep_panel_elems(mb);
+  double2* R2 = w.R + sweep_pinv_elems();
   int step = 0;
   for (int jt = 0, jb = nb - 1; jt < m || jb > m; ++jt, --jb, ++step) {
     if (jt < m) factor_block<P>(L, cop, S, jt, jt > 0 ? jt - 1 : -1, -1, w.T, w.W, w.R, w.flag, st);

@@ -121,10 +121,13 @@ void launch_f2d(const float2* x, double2* y, long n, hipStream_t st);
 // HZ_ESINGULAR (pivot check on device, read back at the end).
 struct CoarseFactorWork {
   double2* T = nullptr;      // temp blocks, 2 x (max block size)^2 (one per chain)
-  double2* W = nullptr;      // Gauss-Jordan panel buffers, 2 x (max block size) x 32
-  double2* R = nullptr;
+  double2* W = nullptr;      // pivot row panels, 2 x sweep_panel_elems(max block size)
+  double2* R = nullptr;      // pivot block inverses, 2 x sweep_pinv_elems()
   int* flag = nullptr;       // device error flag
 };
+// Elements of one chain's pivot row panels (two passes' worth) and pivot inverses.
+size_t sweep_panel_elems(size_t nmax);
+size_t sweep_pinv_elems();
 hz_status coarse_factor(const CoarseLayout& L, const DevOp<double>& cop, double2* S,
                         const CoarseFactorWork& w, hipStream_t st);
 // Solves A_c y = b with the stored inverses; nrhs right-hand sides with stride cstride.
