@@ -519,6 +519,61 @@ def main_serving(a):
     print(json.dumps(out), flush=True)
 
 
+def main_search(a):
+    """Shift-search samples (Sec. 5 data generation) on the GPU: samples/s, the data set, the
+    Table 1 map's exponents beside the searched ones, and a per-order refit of the map."""
+    import torch
+    from paper_2104_01439_amd import inputs, samplegen, shiftmap
+
+    torch.cuda.set_device(0)
+    samples = inputs.shift_samples(a.samples, seed=2, ells=tuple(range(4, a.max_ell + 1)))
+    log(f"shift search: {len(samples)} samples, ell 4..{a.max_ell} ...")
+    for i in range(a.warmup):
+        samplegen.generate(samples[:4])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rows = samplegen.generate(samples)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    evals = sum(r["evaluations"] for r in rows)
+    tab = [float(shiftmap.sigma_map(r["k"], r["ell"], r["p"])) for r in rows]
+    fits = {}
+    for p in (1, 2, 3):
+        sel = [r for r in rows if r["p"] == p]
+        if len(sel) < 4:
+            continue
+        w = shiftmap.sample_weights([r["ell"] for r in sel], [p] * len(sel))
+        est, loss = shiftmap.fit([r["k"] for r in sel], [r["ell"] for r in sel],
+                                 [r["sigma_hat"] for r in sel], w, epochs=a.epochs)
+        fits[p] = {"weights": est, "loss": loss, "samples": len(sel)}
+    out = {
+        "metric": "shift-search samples/s",
+        "value": len(rows) / dt,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * dt,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: random real right-hand sides, g = 0",
+        "config": {"workload": "shift_search", "samples": len(rows), "ells": [4, a.max_ell],
+                   "sigma_range": [1.0, 2.0], "tol": 1e-2, "solve_tol": 1e-8, "maxit": 50},
+        "solves_per_s": evals / dt,
+        "evaluations": evals,
+        "rows": rows,
+        "table1_sigma": tab,
+        "mean_abs_sigma_hat_minus_table1": float(np.mean([abs(r["sigma_hat"] - t)
+                                                           for r, t in zip(rows, tab)])),
+        "refit": fits,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -531,6 +586,9 @@ def main():
     ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals per s (0: all at once)")
     ap.add_argument("--max-active", type=int, default=32, help="serving: engine slots")
     ap.add_argument("--baseline", action="store_true", help="serving: also time the plain FP64 path")
+    ap.add_argument("--samples", type=int, default=48, help="shift_search: samples")
+    ap.add_argument("--max-ell", type=int, default=8, help="shift_search: largest mesh level")
+    ap.add_argument("--epochs", type=int, default=20000, help="shift_search: refit epochs")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
@@ -540,6 +598,8 @@ def main():
     from paper_2104_01439_amd import inputs
     if a.workload == "serving":
         return main_serving(a)
+    if a.workload == "shift_search":
+        return main_search(a)
     if a.workload == inputs.CFG_MIXED["name"] and a.prec == "compare":
         return main_precision(a, inputs.CFG_MIXED)
     if a.workload == inputs.CFG_SWEEP["name"]:

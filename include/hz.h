@@ -268,7 +268,8 @@ hz_status hz_engine_create(const hz_engine_config* c, const hz_options* o, hz_en
  * load for angle theta when d_F is NULL, else a copy of the fine vector d_F taken at setup
  * (d_F must stay valid until the request is reported). The solution is written to d_u (a
  * caller-owned fine vector that must stay valid and untouched until the request is
- * reported; it is complete when hz_engine_poll returns it). The engine reads d_F on its own
+ * reported; it is complete when hz_engine_poll returns it); with d_u NULL only the result
+ * (iterations, residuals) is reported. The engine reads d_F on its own
  * streams, which are not ordered after the caller's: the work that produces d_F must have
  * completed (e.g. its stream synchronised) before the call. Thread-safe, non-blocking.
  * Errors: HZ_EINVAL (bad parameters), HZ_ENOMEM (the request alone exceeds the budget),
@@ -286,6 +287,43 @@ hz_status hz_engine_info(hz_engine* e, hz_engine_info_t* info);
 /* Stops the engine: waits for the current round, drops queued and unfinished requests (they
  * are not reported) and frees everything. NULL is a no-op. */
 void hz_engine_destroy(hz_engine* e);
+
+/* ---------------------------------------------------------------------------------------
+ * Shift search: the data generation of Sec. 5. For a sample (k, h, p) and a right-hand side
+ * F (the paper draws its components uniformly from [-1, 1] and sets g = 0), the exponent
+ * sigma of the shift eps = k^sigma (the multiplier s = 1 + i k^(sigma - 2)) that minimises
+ * rho(sigma) = (r_end / r_0)^(1 / end), the average reduction of the true residual
+ * ||F - A_0 u|| of an FGMRES solve stopped at the options' tolerance or iteration cap
+ * (Sec. 5: 1e-8 and 50 iterations, no restarts), is located by golden-section search on
+ * [sigma_lo, sigma_hi] until the bracket is at most tol wide (Sec. 5: [1, 2] and 1e-2).
+ * --------------------------------------------------------------------------------------- */
+typedef struct {
+  double k;             /* wavenumber                                                  */
+  double h;             /* fine mesh size (1/h an even integer)                         */
+  int p;                /* element order                                               */
+} hz_search_sample;
+
+typedef struct {
+  double sigma;         /* midpoint of the final bracket: the sample's near-optimal exponent */
+  double rho;           /* smallest objective value evaluated                               */
+  double sigma_best;    /* the exponent at which it was evaluated                           */
+  int evaluations;      /* solves run for this sample                                        */
+  int status;           /* HZ_OK, or the error of a failed solve                             */
+} hz_search_result;
+
+/* Runs the n searches concurrently on one serving engine (config cfg, solver options o; NULL
+ * = defaults; the paper's setting is o->tol = 1e-8, o->maxit = 50, o->restart = 50): every
+ * objective evaluation is an engine request that sets up and factors the problem with that
+ * shift and solves A_0 u = F with d_F[i] (a caller-owned fine vector of sample i, read
+ * while the call runs). In each step the bracket [a, b] with inner points c < d keeps [a, d]
+ * if rho(c) < rho(d), else [c, b]; the new inner point is the golden section of the kept
+ * bracket. Blocks until all searches are done; out[i] receives sample i's result. Errors:
+ * HZ_EINVAL (arguments), the engine's errors; a failed solve ends its sample's search (its
+ * status is set) and the call returns that error after all searches have ended. */
+hz_status hz_shift_search(const hz_search_sample* samples, int n, const hz_c64* const* d_F,
+                          double sigma_lo, double sigma_hi, double tol,
+                          const hz_engine_config* cfg, const hz_options* o,
+                          hz_search_result* out);
 
 /* Copies the problem's counters into *out (waiting for pending timed launches) and, if
  * reset is nonzero, zeroes them. Without timing the device times stay 0. */

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <condition_variable>
 #include <deque>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -2060,8 +2061,9 @@ void engine_loop_main(hz_engine* e) {
       for (int q = 0; q < pp->cap; ++q) {
         EngineRequest* r = pp->member[q];
         if (r && pp->ls->S[q].done) {
-          HZ_HIP(hipMemcpyAsync(r->u, pp->ws->Us + size_t(q) * pp->ws->N, size_t(pp->ws->N) * 16,
-                                hipMemcpyDeviceToDevice, st));
+          if (r->u)
+            HZ_HIP(hipMemcpyAsync(r->u, pp->ws->Us + size_t(q) * pp->ws->N,
+                                  size_t(pp->ws->N) * 16, hipMemcpyDeviceToDevice, st));
           finished.push_back(r);
         }
       }
@@ -2151,7 +2153,7 @@ hz_status hz_engine_create(const hz_engine_config* c, const hz_options* o, hz_en
 
 hz_status hz_engine_submit(hz_engine* e, double k, double h, int p, hz_c64 s, double theta,
                            const hz_c64* d_F, hz_c64* d_u, long req_id) {
-  if (!e || !d_u) return fail(HZ_EINVAL, "null argument");
+  if (!e) return fail(HZ_EINVAL, "null engine");
   int n = 0;
   std::string why;
   const cd sc(s.re, s.im);
@@ -2226,6 +2228,151 @@ void hz_engine_destroy(hz_engine* e) {
         r = nullptr;
       }
   delete e;
+}
+
+}  // extern "C"
+
+// -----------------------------------------------------------------------------------------
+// Shift search (Sec. 5, data generation): for every sample (k, h, p) and its right-hand side,
+// the exponent sigma in [sigma_lo, sigma_hi] of the shift eps = k^sigma that minimises the
+// average residual reduction rho = (r_end / r_0)^(1 / end) of an FGMRES solve, found by
+// golden-section search down to a bracket of width tol. All searches advance concurrently on
+// one serving engine: each evaluation is an engine request (set up and factored with its
+// shift, solved by continuous batching with the other samples' evaluations).
+// -----------------------------------------------------------------------------------------
+
+namespace {
+
+struct SearchState {
+  double a = 0, b = 0, c = 0, d = 0, fc = 0, fd = 0;
+  bool hc = false, hd = false, done = false;
+  int evals = 0;
+  double best_rho = 0, best_sigma = 0;
+  hz_status status = HZ_OK;
+  std::string err;
+};
+
+constexpr double kGolden = 0.6180339887498949;   // (sqrt(5) - 1) / 2
+
+// Objective of one solve: (r_end / r_0)^(1 / end); 0 when no iteration was needed.
+double search_rho(const hz_result& r) {
+  if (r.iterations <= 0) return 0.0;
+  return std::pow(r.rel_res_true, 1.0 / r.iterations);
+}
+
+}  // namespace
+
+extern "C" {
+
+hz_status hz_shift_search(const hz_search_sample* samples, int n, const hz_c64* const* d_F,
+                          double sigma_lo, double sigma_hi, double tol,
+                          const hz_engine_config* cfg, const hz_options* o,
+                          hz_search_result* out) {
+  if (!samples || n < 1 || !d_F || !out) return fail(HZ_EINVAL, "null argument");
+  if (!(sigma_lo < sigma_hi) || !std::isfinite(sigma_lo) || !std::isfinite(sigma_hi) ||
+      !(tol > 0))
+    return fail(HZ_EINVAL, "need sigma_lo < sigma_hi and tol > 0");
+  for (int i = 0; i < n; ++i) {
+    int nn = 0;
+    std::string why;
+    if (!d_F[i]) return fail(HZ_EINVAL, "null right-hand side");
+    if (!valid_problem(samples[i].k, samples[i].h, samples[i].p, cd(1, 1), nn, why))
+      return fail(HZ_EINVAL, "sample " + std::to_string(i) + ": " + why);
+  }
+  hz_engine* e = nullptr;
+  hz_status st = hz_engine_create(cfg, o, &e);
+  if (st != HZ_OK) return st;
+  std::vector<SearchState> S(n);
+  int remaining = n;
+  // request id = 2 sample + slot (slot 0: the point c, slot 1: the point d)
+  auto submit = [&](int i, int slot) {
+    const double sigma = slot == 0 ? S[i].c : S[i].d;
+    const double k = samples[i].k;
+    const hz_c64 sh{1.0, std::pow(k, sigma - 2.0)};   // eps = k^sigma = Im(s) k^2
+    const hz_status r = hz_engine_submit(e, k, samples[i].h, samples[i].p, sh, 0.0, d_F[i],
+                                         nullptr, 2L * i + slot);
+    if (r != HZ_OK) {
+      S[i].status = r;
+      S[i].err = hz_last_error();
+      S[i].done = true;
+      --remaining;
+    }
+  };
+  // advance sample i while both inner points are known
+  auto advance = [&](int i) {
+    SearchState& z = S[i];
+    while (!z.done && z.hc && z.hd) {
+      if (z.b - z.a <= tol) {
+        z.done = true;
+        --remaining;
+        break;
+      }
+      if (z.fc < z.fd) {           // the minimum lies in [a, d]
+        z.b = z.d;
+        z.d = z.c;
+        z.fd = z.fc;
+        z.c = z.b - kGolden * (z.b - z.a);
+        z.hc = false;
+        submit(i, 0);
+      } else {                     // in [c, b]
+        z.a = z.c;
+        z.c = z.d;
+        z.fc = z.fd;
+        z.d = z.a + kGolden * (z.b - z.a);
+        z.hd = false;
+        submit(i, 1);
+      }
+    }
+  };
+  for (int i = 0; i < n; ++i) {
+    SearchState& z = S[i];
+    z.a = sigma_lo;
+    z.b = sigma_hi;
+    z.c = z.b - kGolden * (z.b - z.a);
+    z.d = z.a + kGolden * (z.b - z.a);
+    z.best_rho = std::numeric_limits<double>::infinity();
+    submit(i, 0);
+    if (!z.done) submit(i, 1);
+  }
+  std::vector<hz_engine_result> buf(64);
+  while (remaining > 0 && st == HZ_OK) {
+    int nd = 0;
+    st = hz_engine_poll(e, buf.data(), int(buf.size()), &nd, 200);
+    for (int q = 0; q < nd && st == HZ_OK; ++q) {
+      const hz_engine_result& r = buf[q];
+      const int i = int(r.id / 2), slot = int(r.id % 2);
+      SearchState& z = S[i];
+      if (z.done) continue;
+      if (r.status != HZ_OK) {
+        z.status = hz_status(r.status);
+        z.err = r.message;
+        z.done = true;
+        --remaining;
+        continue;
+      }
+      const double rho = search_rho(r.result);
+      const double sigma = slot == 0 ? z.c : z.d;
+      ++z.evals;
+      if (rho < z.best_rho) {
+        z.best_rho = rho;
+        z.best_sigma = sigma;
+      }
+      if (slot == 0) { z.fc = rho; z.hc = true; } else { z.fd = rho; z.hd = true; }
+      advance(i);
+    }
+  }
+  hz_engine_destroy(e);
+  if (st != HZ_OK) return st;
+  for (int i = 0; i < n; ++i) {
+    out[i].sigma = 0.5 * (S[i].a + S[i].b);
+    out[i].rho = S[i].best_rho;
+    out[i].sigma_best = S[i].best_sigma;
+    out[i].evaluations = S[i].evals;
+    out[i].status = S[i].status;
+  }
+  for (int i = 0; i < n; ++i)
+    if (S[i].status != HZ_OK) return fail(S[i].status, "sample " + std::to_string(i) + ": " + S[i].err);
+  return HZ_OK;
 }
 
 }  // extern "C"

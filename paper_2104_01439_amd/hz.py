@@ -80,6 +80,19 @@ class EngineInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class SearchSample(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_double), ("h", ctypes.c_double), ("p", ctypes.c_int)]
+
+
+class SearchResult(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("rho", ctypes.c_double),
+                ("sigma_best", ctypes.c_double), ("evaluations", ctypes.c_int),
+                ("status", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _P = ctypes.c_void_p
 _SIGS = {
     "hz_default_options": (ctypes.c_int, [ctypes.POINTER(Options)]),
@@ -111,6 +124,10 @@ _SIGS = {
     "hz_engine_info": (ctypes.c_int, [_P, ctypes.POINTER(EngineInfo)]),
     "hz_engine_destroy": (None, [_P]),
     "hz_last_error": (ctypes.c_char_p, []),
+    "hz_shift_search": (ctypes.c_int, [ctypes.POINTER(SearchSample), ctypes.c_int,
+                                       ctypes.POINTER(_P), ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.POINTER(EngineConfig),
+                                       ctypes.POINTER(Options), ctypes.POINTER(SearchResult)]),
 }
 
 _lib = None
@@ -328,3 +345,24 @@ class Engine:
             self.close()
         except Exception:
             pass
+
+
+def shift_search(samples, Fs, sigma_lo=1.0, sigma_hi=2.0, tol=1e-2, solve_tol=1e-8, maxit=50,
+                 restart=50, prec="fp64", max_active=64, setup_threads=4, hbm_budget=0):
+    """Golden-section search of the shift exponent for every sample (hz_shift_search):
+    samples = [(k, h, p)], Fs = matching complex128 CUDA right-hand sides. Returns one result
+    dict per sample (sigma, rho, sigma_best, evaluations, status)."""
+    n = len(samples)
+    assert len(Fs) == n and n > 0
+    S = (SearchSample * n)(*[SearchSample(float(k), float(h), int(p)) for k, h, p in samples])
+    FF = (ctypes.c_void_p * n)(*[_ptr(F).value for F in Fs])
+    o = options(restart=restart, maxit=maxit, tol=solve_tol, prec=prec)
+    c = EngineConfig()
+    _check(lib().hz_engine_default_config(ctypes.byref(c)))
+    c.hbm_budget, c.max_active, c.setup_threads = int(hbm_budget), max_active, setup_threads
+    out = (SearchResult * n)()
+    # the engine reads the right-hand sides on its own streams
+    torch.cuda.current_stream().synchronize()
+    _check(lib().hz_shift_search(S, n, FF, sigma_lo, sigma_hi, tol, ctypes.byref(c),
+                                 ctypes.byref(o), out))
+    return [r.as_dict() for r in out]

@@ -58,3 +58,26 @@ def serving_requests(count=2000, seed=1, rate=None, kmin=10.0, kmax=300.0, bmin=
         t += gap
         out.append(dict(id=i, t=t, k=k, p=p, n=n, beta=beta, theta=theta))
     return out
+
+
+def shift_samples(count, seed=2, ells=(4, 5, 6, 7, 8, 9, 10), orders=(1, 2, 3)):
+    """Samples of the shift search (Sec. 5, data generation): per sample draw the order p,
+    then ell (h = 2^-ell), then k uniform in [3p / (16 h), 3p / (4 h)]; the right-hand side
+    is drawn by sample_rhs from the sample's own seed."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        p = int(rng.choice(orders))
+        ell = int(rng.choice(ells))
+        h = 2.0 ** -ell
+        k = float(rng.uniform(3 * p / (16 * h), 3 * p / (4 * h)))
+        out.append(dict(id=i, p=p, ell=ell, h=h, n=2 ** ell, k=k, rhs_seed=seed * 100003 + i))
+    return out
+
+
+def sample_rhs(sample):
+    """Right-hand side of a shift-search sample: every component uniform in [-1, 1], real
+    (imaginary part zero), on the fine lattice of (p, h)."""
+    M = sample["p"] * sample["n"] + 1
+    rng = np.random.default_rng(sample["rhs_seed"])
+    return rng.uniform(-1.0, 1.0, M * M) + 0j
