@@ -559,10 +559,17 @@ void vcycle_group(hz_problem* const* probs, const int* zp, int nb, const DevOp<T
       // u = 0: the cycle is the coarse correction alone, z = P A_c^{-1} P^T f
       launch_restrict<T>(p, pr0->M, pr0->Mc, rw, f, sc.rc, nb, af, Addr(Nc), st);
     } else {
+      // sweep s leaves the iterate in ua (s odd) or ub (s even); the first two sweeps from
+      // zero run as one pass
       V2<T>* c = sc.ua;
       V2<T>* x = sc.ub;
-      launch_jacobi0<T, T>(p, fine, f, af, c, Addr(N), nb, st);
-      for (int sw = 1; sw < nu; ++sw) {
+      if (nu == 1) {
+        launch_jacobi0<T, T>(p, fine, f, af, c, Addr(N), nb, st);
+      } else {
+        launch_stencil<T, T, T, T>(p, ST_SMOOTH0, fine, f, af, f, af, x, Addr(N), nb, st);
+        std::swap(c, x);
+      }
+      for (int sw = 2; sw < nu; ++sw) {
         launch_stencil<T, T, T, T>(p, ST_SMOOTH, fine, c, Addr(N), f, af, x, Addr(N), nb, st);
         std::swap(c, x);
       }
@@ -1462,6 +1469,16 @@ hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_option
       ensure_fp64_work(pr);
     }
     HZ_HIP(hipStreamSynchronize(st));
+    // set-up temporaries went back to the device's stream-ordered pool (the FP64 factor of a
+    // mixed problem is the largest); hand the unused part back so that later allocations,
+    // of this or any other problem, find it
+    {
+      int dev = 0;
+      hipMemPool_t pool = nullptr;
+      if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess)
+        (void)hipMemPoolTrimTo(pool, 0);
+      (void)hipGetLastError();
+    }
     pr->setup_s = secs(t0);
     *out = pr;
     return HZ_OK;

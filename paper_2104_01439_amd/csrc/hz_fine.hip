@@ -59,7 +59,11 @@ k_stencil(DevOp<T> op, const V2<TX>* __restrict__ x, Addr ax, const V2<TF>* __re
     const int ly = idx / LW, lx = idx - ly * LW;
     const int a = ax0 + lx, b = by0 + ly;
     V2<T> v = czero<T>();
-    if (a >= 0 && a < M && b >= 0 && b < M) v = cvt<T>(x[long(b) * M + a]);
+    if (a >= 0 && a < M && b >= 0 && b < M) {
+      v = cvt<T>(x[long(b) * M + a]);
+      if constexpr (MODE == ST_SMOOTH0)    // the first sweep from zero: u1 = wdinv f
+        v = cmul<T>(wdinv[((b % P) * P + (a % P)) * 9 + region(b, M) * 3 + region(a, M)], v);
+    }
     tile[ly][lx] = v;
   }
   __syncthreads();
@@ -127,7 +131,7 @@ k_stencil(DevOp<T> op, const V2<TX>* __restrict__ x, Addr ax, const V2<TF>* __re
       V2<T> out = acc[cb][ca];
       if constexpr (MODE == ST_RESID) {
         out = csub<T>(cvt<T>(f[gi]), out);
-      } else if constexpr (MODE == ST_SMOOTH) {
+      } else if constexpr (MODE == ST_SMOOTH || MODE == ST_SMOOTH0) {
         const V2<T> d = wdinv[(cb * P + ca) * 9 + reg[cb][ca]];
         const V2<T> rr = csub<T>(cvt<T>(f[gi]), out);
         out = cadd<T>(tile[P * ty + P + cb][P * tx + P + ca], cmul<T>(d, rr));
@@ -291,7 +295,7 @@ struct StencilVariant {
   int byt;
   bool xcd;
 };
-constexpr StencilVariant kVariants[] = {{4, false}, {4, true}, {8, false}, {8, true}};
+constexpr StencilVariant kVariants[] = {{4, false}, {4, true}, {8, false}, {8, true}, {16, true}};
 
 template <int P, typename T, typename TX, typename TF, typename TY, int MODE, int BYT, bool XCD>
 void stencil_launch(const DevOp<T>& op, const V2<TX>* x, Addr xs, const V2<TF>* f, Addr fs,
@@ -309,6 +313,7 @@ void stencil_variant(int v, const DevOp<T>& op, const V2<TX>* x, Addr xs, const 
   if (v == 1) stencil_launch<P, T, TX, TF, TY, MODE, 4, true>(op, x, xs, f, fs, y, ys, nbatch, st);
   else if (v == 2 && P <= 2) stencil_launch<P, T, TX, TF, TY, MODE, (P <= 2 ? 8 : 4), false>(op, x, xs, f, fs, y, ys, nbatch, st);
   else if (v == 3 && P <= 2) stencil_launch<P, T, TX, TF, TY, MODE, (P <= 2 ? 8 : 4), true>(op, x, xs, f, fs, y, ys, nbatch, st);
+  else if (v == 4 && P == 1) stencil_launch<P, T, TX, TF, TY, MODE, (P == 1 ? 16 : 4), true>(op, x, xs, f, fs, y, ys, nbatch, st);
   else stencil_launch<P, T, TX, TF, TY, MODE, 4, false>(op, x, xs, f, fs, y, ys, nbatch, st);
 }
 
@@ -383,9 +388,10 @@ void stencil_p(int mode, const DevOp<T>& op, const V2<TX>* x, Addr xs, const V2<
   auto launch = [&](int v) {
     if (mode == ST_APPLY) stencil_variant<P, T, TX, TF, TY, ST_APPLY>(v, op, x, xs, f, fs, y, ys, nbatch, st);
     else if (mode == ST_RESID) stencil_variant<P, T, TX, TF, TY, ST_RESID>(v, op, x, xs, f, fs, y, ys, nbatch, st);
-    else stencil_variant<P, T, TX, TF, TY, ST_SMOOTH>(v, op, x, xs, f, fs, y, ys, nbatch, st);
+    else if (mode == ST_SMOOTH) stencil_variant<P, T, TX, TF, TY, ST_SMOOTH>(v, op, x, xs, f, fs, y, ys, nbatch, st);
+    else stencil_variant<P, T, TX, TF, TY, ST_SMOOTH0>(v, op, x, xs, f, fs, y, ys, nbatch, st);
   };
-  const int nvar = P <= 2 ? 4 : 2;
+  const int nvar = P == 1 ? 5 : P == 2 ? 4 : 2;
   const int fv = forced_variant();
   if (fv >= 0) {
     if (fv >= nvar) throw std::runtime_error("HZ_STENCIL_VARIANT: no such variant for this order");

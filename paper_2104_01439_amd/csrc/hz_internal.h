@@ -91,9 +91,12 @@ struct CoarseLayout {
 // Launchers (hz_fine.hip, hz_coarse.hip, hz_krylov.hip)
 // ------------------------------------------------------------------------------------------
 
-enum StencilMode { ST_APPLY = 0, ST_RESID = 1, ST_SMOOTH = 2 };
+enum StencilMode { ST_APPLY = 0, ST_RESID = 1, ST_SMOOTH = 2, ST_SMOOTH0 = 3 };
 
 // y = A x  |  y = f - A x  |  y = x + wdinv (f - A x)   on one level, lattice M x M;
+// ST_SMOOTH0: the first two Jacobi sweeps from a zero iterate in one pass, y = u1 + wdinv
+// (f - A u1) with u1 = wdinv f formed while staging (x must be f, with the same offsets);
+// bitwise the result of the first sweep followed by an ST_SMOOTH sweep.
 // nbatch independent vectors, batch element z at x + ax.at(z), f + af.at(z), y + ay.at(z).
 template <typename T, typename TX, typename TF, typename TY>
 void launch_stencil(int p, int mode, const DevOp<T>& op, const V2<TX>* x, Addr ax,

@@ -1,9 +1,12 @@
 """Short fixed workload for kernel profilers (rocprofv3 --kernel-trace / --pmc).
 
-Creates one problem of a named workload, then runs, each on torch's current stream:
+Creates one problem of a named workload (its creation runs the coarse factorisation), then
+runs, each on torch's current stream:
   * `--copy-mib` MiB of a plain FP64 scale y = 1.0 * x (a copy-shaped kernel of known
     size: reads and writes exactly that many bytes), the calibration for HBM counters;
   * `--applies` applications of A_0 (matrix-free fine stencil, 32 B per fine dof);
+  * `--stencils` applications of each other fine-level pass of the V-cycle (Jacobi sweep,
+    residual + restriction, restriction, prolongation);
   * `--coarse-solves` coarse block triangular solves (the whole stored factor read twice).
 It prints the device time of each group from HIP events and the algorithmic bytes, so that
 counter totals can be set against them:
@@ -23,6 +26,7 @@ def main(argv=None):
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--applies", type=int, default=8)
     ap.add_argument("--coarse-solves", type=int, default=4)
+    ap.add_argument("--stencils", type=int, default=0)
     a = ap.parse_args(argv)
 
     import torch
@@ -63,6 +67,14 @@ def main(argv=None):
         ms = timed(lambda: pr.apply("A0", F, prec=a.prec), a.applies)
         b = stencil_apply_bytes(n, p)
         out["A0"] = {"bytes": b, "ms": ms, "GB/s": b / (ms * 1e-3) / 1e9}
+    if a.stencils:
+        from paper_2104_01439_amd import inputs as inp
+        x = torch.from_numpy(inp.random_complex(pr.N, seed=5)).cuda()
+        f = torch.from_numpy(inp.random_complex(pr.N, seed=6)).cuda()
+        xc = torch.from_numpy(inp.random_complex(pr.Nc, seed=7)).cuda()
+        for op, arg in (("JACOBI", x), ("RESID_RESTRICT", x), ("RESTRICT", x), ("PROLONG", xc)):
+            ms = timed(lambda: pr.apply(op, arg, f, prec=a.prec), a.stencils)
+            out[op] = {"ms": ms}
     if a.coarse_solves:
         rc = pr.apply("RESTRICT", F)
         item = 8 if a.prec == "mixed" else 16

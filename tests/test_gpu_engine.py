@@ -128,3 +128,25 @@ def test_engine_admission_and_errors(hz, torch):
     for i in range(4):
         eng.submit(100 + i, 20.0, 1 / 64, 2, 1 + 0.5j, theta=0.3)
     eng.close()
+
+
+def test_mixed_setup_returns_its_temporaries():
+    """A mixed-precision problem factors in FP64 into a stream-ordered temporary of the full
+    FP64 factor size; after creation that memory is free again for anyone (the pool is
+    trimmed), and destroying the problem returns the rest."""
+    import torch
+    from paper_2104_01439_amd import hz
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0, _ = torch.cuda.mem_get_info()
+    pr = hz.Problem(120.0, 1 / 256, 3, 1 + 0.5j, prec="mixed")     # FP64 factor 5.5 GB
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    held = pr.info()["footprint_bytes"]
+    pr.close()
+    torch.cuda.synchronize()
+    free2, _ = torch.cuda.mem_get_info()
+    print(f"held {held / 1e9:.2f} GB, free drop after create {(free0 - free1) / 1e9:.2f} GB, "
+          f"after destroy {(free0 - free2) / 1e9:.2f} GB", flush=True)
+    assert free0 - free1 <= held + (512 << 20)
+    assert free0 - free2 <= 512 << 20

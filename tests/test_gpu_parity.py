@@ -345,7 +345,7 @@ def test_every_stencil_variant_against_oracle(hz, torch, c, monkeypatch):
     """Every launch variant the autotuner may pick (tile height, XCD-aware tile order),
     forced one at a time: each matches the oracle and all are bitwise equal."""
     C = case(hz, torch, c)
-    nvar = 4 if C.p <= 2 else 2
+    nvar = {1: 5, 2: 4, 3: 2}[C.p]
     x = inputs.random_complex(C.fine.N, seed=1234)
     f = inputs.random_complex(C.fine.N, seed=99)
     xc = inputs.random_complex(C.coarse.N, seed=4321)
