@@ -376,8 +376,10 @@ def run_serving(count, rate, prec, max_active, tol=1e-8, restart=50):
         if time.perf_counter() - last_log > 20:
             last_log = time.perf_counter()
             inf = eng.info()
+            free = torch.cuda.mem_get_info()[0]
             log(f"  serving: {len(done)}/{len(reqs)} done, {inf['admitted']} admitted, "
-                f"{inf['queued']} queued, {inf['bytes_in_use'] / 1e9:.1f} GB in use")
+                f"{inf['queued']} queued, {inf['bytes_in_use'] / 1e9:.1f} GB in use, "
+                f"{free / 1e9:.1f} GB free on the device")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     eng.close()

@@ -1707,6 +1707,7 @@ struct EngineRequest {
   double2* u = nullptr;           // caller's solution buffer
   clk::time_point t_submit, t_admit;
   size_t bytes_setup = 0, bytes = 0;
+  size_t release_bytes = 0;       // credited to the budget once the reaper has freed them
   hz_problem* pr = nullptr;
   EnginePool* pool = nullptr;
   int slot = -1;
@@ -1804,9 +1805,13 @@ struct hz_engine {
 namespace {
 
 // Releases the memory of a retired request (and pool slots it reserved); caller holds mu.
+// The request's own bytes are credited back by the reaper after the frees have happened:
+// a free waits for the device, and the budget must not count memory that is still held.
 void engine_release_locked(hz_engine* e, EngineRequest* r) {
   if (!r->admitted) return;
-  e->used -= r->setup_done ? r->bytes : r->bytes_setup;
+  const size_t b = r->setup_done ? r->bytes : r->bytes_setup;
+  if (r->pr) r->release_bytes = b;
+  else e->used -= b;                       // a failed set-up freed its memory already
   e->admitted -= 1;
   ClassState& c = e->classes[ClassKey{r->n, r->p}];
   c.slots_used -= 1;
@@ -1859,8 +1864,16 @@ void engine_reaper_main(hz_engine* e) {
         return;
       }
     }
+    const size_t freed = (r ? r->release_bytes : 0) + (pool ? pool->bytes : 0);
     delete r;
     pool.reset();
+    if (freed) {
+      {
+        std::lock_guard<std::mutex> g(e->mu);
+        e->used -= freed;
+      }
+      e->cv_work.notify_all();
+    }
   }
 }
 
@@ -1909,7 +1922,11 @@ void engine_admit(hz_engine* e) {
     const size_t pool_b = size_t(cap) * slot_bytes(r->n, r->p, e->opt.restart, e->opt.prec);
     const bool new_pool = c.slots_used >= c.slots_total;
     if (new_pool) need += pool_b;
-    if (e->used + need > e->cfg.hbm_budget && e->admitted > 0) break;
+    // over the budget only a lone request is admitted, and only when no freed memory is
+    // still on its way back
+    if (e->used + need > e->cfg.hbm_budget &&
+        (e->admitted > 0 || !e->trash.empty() || !e->dead_pools.empty()))
+      break;
     e->pending.pop_front();
     if (new_pool) {
       c.slots_total += cap;
@@ -1988,8 +2005,7 @@ void engine_leave(hz_engine* e, EngineRequest* r) {
     ClassState& c = e->classes[ClassKey{pool->n, pool->p}];
     // the leaving request still counts in slots_used
     if (c.slots_total - pool->cap >= c.slots_used - 1) {
-      c.slots_total -= pool->cap;
-      e->used -= pool->bytes;
+      c.slots_total -= pool->cap;          // its bytes are credited when the reaper frees it
       for (size_t i = 0; i < e->pools.size(); ++i)
         if (e->pools[i].get() == pool) {
           e->dead_pools.push_back(std::move(e->pools[i]));

@@ -157,6 +157,15 @@ k_jacobi0(DevOp<T> op, const V2<TF>* __restrict__ f, Addr af, V2<T>* __restrict_
   y[ay.at(bz) + i] = cmul<T>(wd[cls * 9 + reg], cvt<T>(f[af.at(bz) + i]));
 }
 
+// Workgroups of a 1D launch over lattice points are dealt round-robin to the 8 XCDs (each
+// with its own L2); renumbering them so that XCD x takes a contiguous band of 1/8 of the
+// points keeps the lattice rows that neighbouring rows of outputs share in one L2.
+__device__ __forceinline__ long xcd_band_block(int nblocks) {
+  const int per = (nblocks + 7) / 8;
+  return long(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+inline unsigned xcd_band_grid(long nblocks) { return unsigned(8 * ((nblocks + 7) / 8)); }
+
 // yc(A, B) = sum over fine points (2A + dx, 2B + dy) of RW[cls(A,B)][dy][dx] r(...)
 template <int P, typename T>
 __global__ void __launch_bounds__(256)
@@ -164,7 +173,7 @@ k_restrict(int Mf, int Mc, const T* __restrict__ rw, const V2<T>* __restrict__ r
            V2<T>* __restrict__ yc, Addr af, Addr ac) {
   constexpr int WR = 4 * P + 1;
   const long Nc = long(Mc) * Mc;
-  const long i = long(blockIdx.x) * 256 + threadIdx.x;
+  const long i = xcd_band_block(int((Nc + 255) / 256)) * 256 + threadIdx.x;
   if (i >= Nc) return;
   r += af.at(blockIdx.y);
   yc += ac.at(blockIdx.y);
@@ -198,7 +207,7 @@ k_prolong(int Mf, int Mc, const T* __restrict__ rw, const V2<T>* __restrict__ xc
           V2<T>* __restrict__ yf, Addr af, Addr ac) {
   constexpr int WR = 4 * P + 1;
   const long Nf = long(Mf) * Mf;
-  const long i = long(blockIdx.x) * 256 + threadIdx.x;
+  const long i = xcd_band_block(int((Nf + 255) / 256)) * 256 + threadIdx.x;
   if (i >= Nf) return;
   xc += ac.at(blockIdx.y);
   yf += af.at(blockIdx.y);
@@ -434,7 +443,7 @@ template <typename T>
 void launch_restrict(int p, int Mf, int Mc, const T* rw, const V2<T>* r, V2<T>* yc, int nbatch,
                      Addr fstride, Addr cstride, hipStream_t st) {
   const long Nc = long(Mc) * Mc;
-  dim3 grid(unsigned((Nc + 255) / 256), nbatch);
+  dim3 grid(xcd_band_grid((Nc + 255) / 256), nbatch);
   if (p == 1) k_restrict<1, T><<<grid, 256, 0, st>>>(Mf, Mc, rw, r, yc, fstride, cstride);
   else if (p == 2) k_restrict<2, T><<<grid, 256, 0, st>>>(Mf, Mc, rw, r, yc, fstride, cstride);
   else k_restrict<3, T><<<grid, 256, 0, st>>>(Mf, Mc, rw, r, yc, fstride, cstride);
@@ -445,7 +454,7 @@ template <typename T>
 void launch_prolong(int p, int Mf, int Mc, const T* rw, const V2<T>* xc, V2<T>* yf, bool add,
                     int nbatch, Addr fstride, Addr cstride, hipStream_t st) {
   const long Nf = long(Mf) * Mf;
-  dim3 grid(unsigned((Nf + 255) / 256), nbatch);
+  dim3 grid(xcd_band_grid((Nf + 255) / 256), nbatch);
 #define HZ_PRO(PP)                                                                             \
   if (add) k_prolong<PP, T, true><<<grid, 256, 0, st>>>(Mf, Mc, rw, xc, yf, fstride, cstride); \
   else k_prolong<PP, T, false><<<grid, 256, 0, st>>>(Mf, Mc, rw, xc, yf, fstride, cstride);

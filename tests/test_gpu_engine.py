@@ -60,6 +60,11 @@ def test_engine_results_equal_alone(hz, torch, prec):
         eng.submit(i, k, 1.0 / n, p, 1 + 1j * b, theta=th)
     got = drain(eng, len(MIX))
     info = eng.info()
+    # finished requests' memory is credited back once their frees have completed
+    t0 = time.time()
+    while info["bytes_in_use"] != 0 and time.time() - t0 < 30:
+        time.sleep(0.05)
+        info = eng.info()
     eng.close()
     assert info["completed"] == len(MIX) and info["admitted"] == 0 and info["bytes_in_use"] == 0
     for i, (k, n, p, b, th) in enumerate(MIX):
