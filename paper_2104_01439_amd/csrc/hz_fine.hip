@@ -200,41 +200,68 @@ k_restrict(int Mf, int Mc, const T* __restrict__ rw, const V2<T>* __restrict__ r
   yc[i] = acc;
 }
 
-// yf(a, b) (+)= sum over coarse (A, B) with |a - 2A|, |b - 2B| <= 2P of RW[cls(A,B)][.][.] xc
+// yf(a, b) (+)= sum over coarse (A, B) with |a - 2A|, |b - 2B| <= 2P of RW[cls(A,B)][.][.] xc.
+// One thread per coarse point (At, Bt) forms the 2 x 2 fine points (2 At + i, 2 Bt + j): their
+// coarse neighbourhoods are the same (2P+1)^2 points (held in registers for P <= 2), and a
+// wave writes contiguous pairs of fine points. Per fine point the terms are summed in the
+// order of ascending B, then A.
 template <int P, typename T, bool ADD>
 __global__ void __launch_bounds__(256)
 k_prolong(int Mf, int Mc, const T* __restrict__ rw, const V2<T>* __restrict__ xc,
           V2<T>* __restrict__ yf, Addr af, Addr ac) {
-  constexpr int WR = 4 * P + 1;
-  const long Nf = long(Mf) * Mf;
-  const long i = xcd_band_block(int((Nf + 255) / 256)) * 256 + threadIdx.x;
-  if (i >= Nf) return;
+  constexpr int WR = 4 * P + 1, NB = 2 * P + 1;
+  constexpr bool CACHE = P <= 2;
+  const long Nc = long(Mc) * Mc;
+  const long t = xcd_band_block(int((Nc + 255) / 256)) * 256 + threadIdx.x;
+  if (t >= Nc) return;
   xc += ac.at(blockIdx.y);
   yf += af.at(blockIdx.y);
-  const int b = int(i / Mf), a = int(i - long(b) * Mf);
-  V2<T> acc = czero<T>();
-  const int A0 = (a - 2 * P + 1) >> 1, B0 = (b - 2 * P + 1) >> 1;   // ceil((a - 2P) / 2)
+  const int Bt = int(t / Mc), At = int(t - long(Bt) * Mc);
+  V2<T> xv[CACHE ? NB : 1][CACHE ? NB : 1];
+  if constexpr (CACHE) {
 #pragma unroll
-  for (int jb = 0; jb <= 2 * P; ++jb) {
-    const int B = B0 + jb;
-    const int dy = b - 2 * B;
-    if (B < 0 || B >= Mc || dy < -2 * P || dy > 2 * P) continue;
+    for (int jb = 0; jb < NB; ++jb)
 #pragma unroll
-    for (int ja = 0; ja <= 2 * P; ++ja) {
-      const int A = A0 + ja;
-      const int dx = a - 2 * A;
-      if (A < 0 || A >= Mc || dx < -2 * P || dx > 2 * P) continue;
-      const int cls = (B % P) * P + (A % P);
-      const T wt = rw[(cls * WR + dy + 2 * P) * WR + dx + 2 * P];
-      if (wt != T(0)) {
-        const V2<T> v = xc[long(B) * Mc + A];
-        acc.x += wt * v.x;
-        acc.y += wt * v.y;
+      for (int ja = 0; ja < NB; ++ja) {
+        const int A = At - P + ja, B = Bt - P + jb;
+        xv[jb][ja] = (A >= 0 && A < Mc && B >= 0 && B < Mc) ? xc[long(B) * Mc + A] : czero<T>();
       }
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int b = 2 * Bt + j;
+    if (b >= Mf) continue;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int a = 2 * At + i;
+      if (a >= Mf) continue;
+      V2<T> acc = czero<T>();
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb) {
+        const int B = Bt - P + jb;
+        const int dy = b - 2 * B;
+        if (B < 0 || B >= Mc || dy < -2 * P || dy > 2 * P) continue;
+#pragma unroll
+        for (int ja = 0; ja < NB; ++ja) {
+          const int A = At - P + ja;
+          const int dx = a - 2 * A;
+          if (A < 0 || A >= Mc || dx < -2 * P || dx > 2 * P) continue;
+          const int cls = (B % P) * P + (A % P);
+          const T wt = rw[(cls * WR + dy + 2 * P) * WR + dx + 2 * P];
+          if (wt != T(0)) {
+            V2<T> v;
+            if constexpr (CACHE) v = xv[jb][ja];
+            else v = xc[long(B) * Mc + A];
+            acc.x += wt * v.x;
+            acc.y += wt * v.y;
+          }
+        }
+      }
+      const long gi = long(b) * Mf + a;
+      if (ADD) acc = cadd<T>(acc, yf[gi]);
+      yf[gi] = acc;
     }
   }
-  if (ADD) acc = cadd<T>(acc, yf[i]);
-  yf[i] = acc;
 }
 
 struct PwParams {
@@ -453,8 +480,8 @@ void launch_restrict(int p, int Mf, int Mc, const T* rw, const V2<T>* r, V2<T>* 
 template <typename T>
 void launch_prolong(int p, int Mf, int Mc, const T* rw, const V2<T>* xc, V2<T>* yf, bool add,
                     int nbatch, Addr fstride, Addr cstride, hipStream_t st) {
-  const long Nf = long(Mf) * Mf;
-  dim3 grid(xcd_band_grid((Nf + 255) / 256), nbatch);
+  const long Nc = long(Mc) * Mc;
+  dim3 grid(xcd_band_grid((Nc + 255) / 256), nbatch);
 #define HZ_PRO(PP)                                                                             \
   if (add) k_prolong<PP, T, true><<<grid, 256, 0, st>>>(Mf, Mc, rw, xc, yf, fstride, cstride); \
   else k_prolong<PP, T, false><<<grid, 256, 0, st>>>(Mf, Mc, rw, xc, yf, fstride, cstride);
