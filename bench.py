@@ -107,6 +107,21 @@ def stencil_rates(cfg, prec, reps=20):
         "prolongation": ("PROLONG", xc, None, yf, B["prolongation"], 1),
     }
     out = {}
+    # on-box copy probe: torch's FP64 copy of 1 GiB (1 GiB read, 1 GiB written)
+    xs = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    ys = torch.empty_like(xs)
+    for _ in range(3):
+        ys.copy_(xs)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ys.copy_(xs)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * xs.numel() * 8 / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+    del xs, ys
+    out["copy probe (torch, 1 GiB)"] = {"GB/s": copy_gbs, "frac": copy_gbs / HBM_PEAK_GBS}
     for name, (op, a, b, y, bpd, nk) in passes.items():
         for _ in range(3):
             pr.apply(op, a, b, y=y, prec=prec)
@@ -120,7 +135,7 @@ def stencil_rates(cfg, prec, reps=20):
         ms = e0.elapsed_time(e1) / reps
         gbs = bpd * (item / 16) * pr.N / (ms * 1e-3) / 1e9
         out[name] = {"us": 1e3 * ms, "bytes_per_dof": bpd * item / 16, "kernels": nk,
-                     "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS}
+                     "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS, "of_copy_probe": gbs / copy_gbs}
     pr.close()
     return out
 
