@@ -1,6 +1,6 @@
 """Writes the stored expected values of the full-size parity tests, from the oracle only.
 
-    python tests/golden/make_goldens.py [coarse] [solve]
+    python tests/golden/make_goldens.py [coarse] [coarse_b005] [solve] [solve_p1]
 
 Each file holds results of the CPU FP64 oracle (``oracle/``) on seeded inputs
 (``paper_2104_01439_amd/inputs.py``): sampled entries of the result at seeded indices, its
@@ -18,6 +18,9 @@ entry). The GPU tests recompute the same quantities from the library's results.
 * ``solve_p3_k200_n256.npz``: FGMRES(50) on A_0 (Sec. 4) with that twogrid preconditioner,
   plane-wave impedance data at theta = pi/7, tolerance 1e-10, zero initial guess:
   iteration count, residual history, true residual and the solution.
+* ``solve_p1_k200_n1024.npz``: the same solve for P1, k = 200, fine h = 1/1024 (k h = 0.195,
+  as for P1 at k = 400, h = 1/2048; 1 050 625 fine dofs, 263 169 coarse dofs,
+  half-bandwidth 514).
 
 Runs for about ten minutes and needs about 20 GB of memory.
 """
@@ -69,16 +72,16 @@ def coarse(name="coarse_p3_k200_n256", k=K, n=N_FINE, p=P, s=S):
           flush=True)
 
 
-def solve():
+def solve(name="solve_p3_k200_n256", k=K, n=N_FINE, p=P, s=S):
     t0 = time.time()
-    pr = Problem(K, N_FINE, P, S, nu=2, omega=0.6)
+    pr = Problem(k, n, p, s, nu=2, omega=0.6)
     print(f"solve: N={pr.N} set up in {time.time() - t0:.0f} s", flush=True)
     F = pr.planewave_rhs(THETA)
     out = pr.solve(F, tol=1e-10, m=50)
     u = out["u"]
     true_res = np.linalg.norm(F - pr.A0 @ u) / np.linalg.norm(F)
     idx = sample_indices(pr.N, 2025)
-    np.savez(os.path.join(HERE, "solve_p3_k200_n256.npz"), k=K, n=N_FINE, p=P, s=S,
+    np.savez(os.path.join(HERE, name + ".npz"), k=k, n=n, p=p, s=s,
              theta=THETA, tol=1e-10, restart=50, iterations=out["iterations"],
              converged=out["converged"], hist=np.array(out["hist"]), rel_res_true=true_res,
              idx=idx, u_idx=u[idx], u_norm=np.linalg.norm(u), proj=projections(u, 600),
@@ -88,10 +91,12 @@ def solve():
 
 
 if __name__ == "__main__":
-    what = sys.argv[1:] or ["coarse", "coarse_b005", "solve"]
+    what = sys.argv[1:] or ["coarse", "coarse_b005", "solve", "solve_p1"]
     if "coarse" in what:
         coarse()
     if "coarse_b005" in what:
         coarse("coarse_p2_k150_n512_b005", 150.0, 512, 2, 1 + 0.05j)
     if "solve" in what:
         solve()
+    if "solve_p1" in what:
+        solve("solve_p1_k200_n1024", 200.0, 1024, 1, 1 + 0.5j)

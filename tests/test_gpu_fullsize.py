@@ -95,10 +95,14 @@ def test_coarse_solve_two_passes_against_oracle(hz, torch, prec, bound):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_solve_p3_n256_against_oracle(hz, torch, prec):
-    """The mixed-precision workload's solve (tol 1e-10) against the oracle's."""
-    g = _gold("solve_p3_k200_n256")
-    pr = _problem(hz, ("p3n256", prec), 200.0, 256, 3, 1 + 0.5j, prec)
+@pytest.mark.parametrize("gold,key,n,p", [("solve_p3_k200_n256", "p3n256", 256, 3),
+                                          ("solve_p1_k200_n1024", "p1n1024", 1024, 1)])
+def test_solve_against_oracle(hz, torch, prec, gold, key, n, p):
+    """FGMRES with the twogrid preconditioner (tol 1e-10) against the oracle's: P3 at
+    h = 1/256 (the mixed-precision workload) and P1 at h = 1/1024 (over a million fine dofs)."""
+    g = _gold(gold)
+    assert (int(g["n"]), int(g["p"])) == (n, p)
+    pr = _problem(hz, (key, prec), float(g["k"]), n, p, complex(g["s"]), prec)
     F = pr.planewave_rhs(float(g["theta"]))
     u, r = pr.solve(F, tol=float(g["tol"]), restart=int(g["restart"]), prec=prec)
     e_s, e_n, e_p = _sample_errors(u.cpu().numpy(), g, "u")
