@@ -81,3 +81,27 @@ def sample_rhs(sample):
     M = sample["p"] * sample["n"] + 1
     rng = np.random.default_rng(sample["rhs_seed"])
     return rng.uniform(-1.0, 1.0, M * M) + 0j
+
+
+def wedge_mu(n, levels=(0.45, 0.7, 1.0)):
+    """Synthetic three-layer wedge profile mu in (0, 1], one value per cell of the n x n
+    mesh (indexed [row j (y), column i (x)]), sampled at the cell centres: levels[0] below
+    y = 0.2 + 0.3 x, levels[2] above y = 0.75 - 0.25 x, levels[1] in the wedge between
+    (the two interfaces meet at x = 1)."""
+    c = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(c, c, indexing="xy")
+    mu = np.full((n, n), levels[1])
+    mu[Y < 0.2 + 0.3 * X] = levels[0]
+    mu[Y > 0.75 - 0.25 * X] = levels[2]
+    return mu
+
+
+def random_cells(n, lo, hi, seed):
+    """Per-cell values uniform in [lo, hi] (n x n, indexed [row j, column i])."""
+    return np.random.default_rng(seed).uniform(lo, hi, (n, n))
+
+
+# Heterogeneous workload: the wedge profile with k_max = 400 on P1, h = 1/2048, the point
+# source at (0.5, 0.55), g = 0.
+CFG_WEDGE = dict(name="wedge_p1_kmax400_n2048", kmax=400.0, n=2048, p=1, source=(0.5, 0.55),
+                 nu=2, omega=0.6, restart=50, tol=1e-8)
