@@ -144,6 +144,31 @@ hz_status hz_default_options(hz_options* o);
 hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_options* o,
                             void* hip_stream, hz_problem** out);
 
+/* The heterogeneous-wavenumber problem of Sec. 6 (the setting of its numerical results:
+ * k(x) = k_max mu(x), to be solved with a shift that follows the local k). k and the shift
+ * multiplier are constant on every cell of the n x n fine mesh (n = 1/h):
+ * k_cell[j * n + i] > 0 and s_cell[j * n + i] (Im > 0) for the cell [i h, (i+1) h] x
+ * [j h, (j+1) h], host arrays read during the call. The system matrix becomes
+ *   A_s = K - sum_c s_c k_c^2 M_c - i sum_{boundary edges e} k_e B_e
+ * (M_c the mass matrix of cell c, k_e the k of the cell that edge e bounds); FGMRES runs on
+ * A_0 (all s_c = 1), the twogrid cycle of Sec. 4, Algorithm 1 on A_s with the Galerkin coarse
+ * operator P^T A_s P (the coarse form with the fine coefficient integrated exactly), factored
+ * once as for hz_create_problem. Both levels store one stencil per lattice point, assembled
+ * on the device. Every other entry point takes the returned problem as it takes one from
+ * hz_create_problem (hz_solve_batched requires all problems of a batch to be of one kind);
+ * hz_problem_info reports the largest k_cell as k. Errors as hz_create_problem (HZ_EINVAL
+ * names the first invalid cell). Synchronises hip_stream. */
+hz_status hz_create_problem_cells(const double* k_cell, const hz_c64* s_cell, double h, int p,
+                                  const hz_options* o, void* hip_stream, hz_problem** out);
+
+/* Load vector of the point source of Sec. 6, f(x) = amp exp(-width |x - (sx, sy)|^2) with
+ * g = 0 (the paper takes amp = 2, width = 1000): F_i = integral of f phi_i, on every triangle
+ * by the collapsed 6 x 6 Gauss-Legendre rule (Duffy). d_F: fine vector (device); any problem
+ * (constant or per-cell k). Asynchronous on hip_stream. Errors: HZ_EINVAL for a null
+ * argument or non-finite parameters (width must be >= 0). */
+hz_status hz_gaussian_rhs(const hz_problem* pr, double sx, double sy, double amp, double width,
+                          hz_c64* d_F, void* hip_stream);
+
 /* Sizes of a created problem: fine dofs, coarse dofs, device bytes held. */
 hz_status hz_problem_info(const hz_problem* pr, long* n_dofs, long* n_coarse,
                           size_t* footprint_bytes);

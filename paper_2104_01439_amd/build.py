@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhz.so")
 
-SOURCES = ["hz_tables.cpp", "hz_fine.hip", "hz_coarse.hip", "hz_krylov.hip", "hz_api.cpp"]
+SOURCES = ["hz_tables.cpp", "hz_fine.hip", "hz_coarse.hip", "hz_krylov.hip", "hz_cells.hip",
+           "hz_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

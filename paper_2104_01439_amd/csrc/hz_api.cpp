@@ -138,9 +138,10 @@ struct Workspace {
 using namespace hz;
 
 struct hz_problem {
-  double k = 0;
+  double k = 0;              // wavenumber (the largest cell value for per-cell k)
   int n = 0, p = 1;
   cd s;
+  int cells = 0;             // per-cell k and shift: operators stored per lattice point
   hz_options opt{};
   int M = 0, Mc = 0;
   long N = 0, Nc = 0;
@@ -161,6 +162,10 @@ struct hz_problem {
   std::unique_ptr<Workspace> ws1;   // Krylov workspace of hz_solve (allocated at first use)
   CoarseSolveWork cw;         // forward-sweep buffers and error flag of the coarse solve
   double gl_t[10], gl_w[10], lag[40];
+  // quadrature of the point-source load vector: xi, eta, w [nq] each, phi [nloc][nq]; loc
+  double* qtab = nullptr;
+  int* qloc = nullptr;
+  int nq = 0;
   double setup_s = 0;
   std::atomic<int> busy{0};
   // device-time counters (timing mode): event pairs around each coarse-solve launch
@@ -341,6 +346,20 @@ void upload_tables(hz_problem* pr, hipStream_t st) {
   std::vector<float> frw(ft.RW.begin(), ft.RW.end());
   pr->frw = pr->mem.alloc<float>(frw.size());
   HZ_HIP(hipMemcpyAsync(pr->frw, frw.data(), frw.size() * 4, hipMemcpyHostToDevice, st));
+  {
+    const QuadTables qt = build_quad_tables(p, 6);
+    pr->nq = qt.nq;
+    std::vector<double> q;
+    q.insert(q.end(), qt.xi.begin(), qt.xi.end());
+    q.insert(q.end(), qt.eta.begin(), qt.eta.end());
+    q.insert(q.end(), qt.w.begin(), qt.w.end());
+    q.insert(q.end(), qt.phi.begin(), qt.phi.end());
+    pr->qtab = pr->mem.alloc<double>(q.size());
+    HZ_HIP(hipMemcpyAsync(pr->qtab, q.data(), q.size() * 8, hipMemcpyHostToDevice, st));
+    pr->qloc = pr->mem.alloc<int>(qt.loc.size());
+    HZ_HIP(hipMemcpyAsync(pr->qloc, qt.loc.data(), qt.loc.size() * 4, hipMemcpyHostToDevice, st));
+    HZ_HIP(hipStreamSynchronize(st));
+  }
   HZ_HIP(hipStreamSynchronize(st));   // the host tables are local
   gauss_legendre10(pr->gl_t, pr->gl_w);
   for (int l = 0; l < 4; ++l)
@@ -350,6 +369,50 @@ void upload_tables(hz_problem* pr, hipStream_t st) {
         if (mm != l) v *= (pr->gl_t[q] - double(mm) / p) / (double(l) / p - double(mm) / p);
       pr->lag[l * 10 + q] = (l <= p) ? v : 0.0;
     }
+}
+
+// Per-point operators of a problem with per-cell k and shift (row-major [j][i] host arrays of
+// the n x n fine cells): A_0 (s = 1) and A_s with the Jacobi multipliers on the fine lattice,
+// A_s on the coarse lattice (the Galerkin operator), all assembled on the device, plus their
+// FP32 copies. Replaces the class-table operators of upload_tables.
+void upload_cells(hz_problem* pr, const double* k_cell, const hz_c64* s_cell, hipStream_t st) {
+  const int p = pr->p, n = pr->n, W2 = (2 * p + 1) * (2 * p + 1);
+  const long nc2 = long(n) * n;
+  const CellTables ft = build_cell_tables(p, 1, 1.0 / n);
+  const CellTables ct = build_cell_tables(p, 2, 1.0 / n);
+  std::vector<double2> sv(nc2);
+  for (long c = 0; c < nc2; ++c) sv[c] = make_double2(s_cell[c].re, s_cell[c].im);
+  auto up = [&](const void* h, size_t bytes) {
+    void* d = pr->mem.alloc_async<char>(bytes, st);
+    HZ_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st));
+    return d;
+  };
+  std::vector<void*> tmp;
+  auto upd = [&](const std::vector<double>& v) {
+    tmp.push_back(up(v.data(), v.size() * 8));
+    return static_cast<const double*>(tmp.back());
+  };
+  const double *fK = upd(ft.K), *fM = upd(ft.Mm), *fB = upd(ft.B);
+  const double *cK = upd(ct.K), *cM = upd(ct.Mm), *cB = upd(ct.B);
+  tmp.push_back(up(k_cell, nc2 * 8));
+  const double* dk = static_cast<const double*>(tmp.back());
+  tmp.push_back(up(sv.data(), nc2 * 16));
+  const double2* ds = static_cast<const double2*>(tmp.back());
+  pr->cA0 = pr->mem.alloc<double2>(size_t(W2) * pr->N);
+  pr->cAe = pr->mem.alloc<double2>(size_t(W2) * pr->N);
+  pr->wdAe = pr->mem.alloc<double2>(pr->N);
+  pr->cAc = pr->mem.alloc<double2>(size_t(W2) * pr->Nc);
+  launch_assemble_cells(p, 1, pr->M, fK, fM, fB, dk, nullptr, pr->opt.omega, pr->cA0, nullptr, st);
+  launch_assemble_cells(p, 1, pr->M, fK, fM, fB, dk, ds, pr->opt.omega, pr->cAe, pr->wdAe, st);
+  launch_assemble_cells(p, 2, pr->Mc, cK, cM, cB, dk, ds, pr->opt.omega, pr->cAc, nullptr, st);
+  pr->fcAe = pr->mem.alloc<float2>(size_t(W2) * pr->N);
+  pr->fwdAe = pr->mem.alloc<float2>(pr->N);
+  pr->fcAc = pr->mem.alloc<float2>(size_t(W2) * pr->Nc);
+  launch_d2f(pr->cAe, pr->fcAe, long(W2) * pr->N, st);
+  launch_d2f(pr->wdAe, pr->fwdAe, pr->N, st);
+  launch_d2f(pr->cAc, pr->fcAc, long(W2) * pr->Nc, st);
+  HZ_HIP(hipStreamSynchronize(st));   // the host arrays are the caller's / local
+  for (void* d : tmp) pr->mem.release_async(d, st);
 }
 
 template <typename T>
@@ -447,6 +510,7 @@ Level<double> level64(hz_problem* pr, const Scratch<double>& sc) {
   Level<double> l;
   l.fine = DevOp<double>{pr->cAe, pr->wdAe, pr->M};
   l.coarse = DevOp<double>{pr->cAc, nullptr, pr->Mc};
+  l.fine.pn = l.coarse.pn = pr->cells;
   l.rw = pr->rw;
   l.S = pr->S;
   l.cw = pr->cw;
@@ -457,6 +521,7 @@ Level<float> level32(hz_problem* pr, const Scratch<float>& sc) {
   Level<float> l;
   l.fine = DevOp<float>{pr->fcAe, pr->fwdAe, pr->M};
   l.coarse = DevOp<float>{pr->fcAc, nullptr, pr->Mc};
+  l.fine.pn = l.coarse.pn = pr->cells;
   l.rw = pr->frw;
   l.S = pr->Sf;
   l.cw = pr->cw;
@@ -589,6 +654,7 @@ void vcycle_group(hz_problem* const* probs, const int* zp, int nb, const DevOp<T
       CoarseJob<T> j;
       j.S = factor_of<T>(pi);
       j.coef = coarse_coef_of<T>(pi);
+      j.pn = pi->cells;
       j.b = sc.rc + b0 * Nc;
       j.y = sc.ec + b0 * Nc;
       j.gbuf = gb + b0 * Nc;
@@ -631,6 +697,7 @@ void timed_coarse_solve(hz_problem* pr, const Level<T>& lv, const V2<T>* b, V2<T
   CoarseJob<T> j;
   j.S = lv.S;
   j.coef = lv.coarse.coef;
+  j.pn = lv.coarse.pn;
   j.b = b;
   j.y = y;
   j.gbuf = reinterpret_cast<V2<T>*>(lv.cw.g);
@@ -984,6 +1051,7 @@ struct Lockstep {
       DevOp<double> fine{nullptr, nullptr, pr0->M,
                          reinterpret_cast<const double2* const*>(d.ptab),
                          reinterpret_cast<const double2* const*>(d.ptab + cap)};
+      fine.pn = pr0->cells;
       vcycle_group<double>(probs, zp.data(), na, fine, pr0->rw, ws->s64,
                            static_cast<double2*>(ws->gb), ws->V, Addr(0, d_vj), ws->Zd,
                            Addr(0, d_zj), st, phases);
@@ -991,6 +1059,7 @@ struct Lockstep {
       DevOp<float> fine{nullptr, nullptr, pr0->M,
                         reinterpret_cast<const float2* const*>(d.ptab),
                         reinterpret_cast<const float2* const*>(d.ptab + cap)};
+      fine.pn = pr0->cells;
       if (phases & VC_PRE) launch_d2f_b(ws->V, Addr(0, d_vj), ws->s32.ff, Addr(N), N, na, st);
       vcycle_group<float>(probs, zp.data(), na, fine, pr0->frw, ws->s32,
                           static_cast<float2*>(ws->gb), ws->s32.ff, Addr(N), ws->Zf,
@@ -998,8 +1067,9 @@ struct Lockstep {
     }
     if (!(phases & VC_POST)) return;
     // w = A_0 z_j
-    const DevOp<double> a0{nullptr, nullptr, pr0->M, reinterpret_cast<const double2* const*>(d.ptab + 2 * cap),
-                           nullptr};
+    DevOp<double> a0{nullptr, nullptr, pr0->M, reinterpret_cast<const double2* const*>(d.ptab + 2 * cap),
+                     nullptr};
+    a0.pn = pr0->cells;
     apply_a0(a0, p, Addr(0, d_zj), Addr(0, d_w), na, st);
     // CGS2: two passes of h = V^H w, w -= V h; then |w|^2
     launch_mdot_b(ws->V, Addr(0, d_vb), N, 64, d.itab, ws->RW, Addr(0, d_w), N, ws->partial, nblk, na, st);
@@ -1099,8 +1169,9 @@ struct Lockstep {
     // r = F - A_0 u (each solve with its own A_0)
     {
       const hz_problem* pe = probs[S[end[0]].prob];
-      const DevOp<double> a0{nullptr, nullptr, pe->M,
-                             reinterpret_cast<const double2* const*>(d2.ptab), nullptr};
+      DevOp<double> a0{nullptr, nullptr, pe->M,
+                       reinterpret_cast<const double2* const*>(d2.ptab), nullptr};
+      a0.pn = pe->cells;
       launch_stencil<double, double, double, double>(pe->p, ST_RESID, a0, Ub,
                                                      Addr(0, d2.tab + cap), Fb,
                                                      Addr(0, d2.tab + 2 * cap), ws->RW,
@@ -1241,7 +1312,8 @@ void apply_impl(hz_problem* pr, int op, const double2* x, const double2* f, doub
   if (prec == HZ_FP64) {
     Level<double> lv = level64(pr, b.s64);
     lv.cw = b.cw;
-    const DevOp<double> a0{pr->cA0, nullptr, pr->M};
+    DevOp<double> a0{pr->cA0, nullptr, pr->M};
+    a0.pn = pr->cells;
     switch (op) {
       case HZ_OP_A0: launch_stencil<double, double, double, double>(p, ST_APPLY, a0, x, o, nullptr, o, y, o, 1, st); break;
       case HZ_OP_AEPS: launch_stencil<double, double, double, double>(p, ST_APPLY, lv.fine, x, o, nullptr, o, y, o, 1, st); break;
@@ -1269,7 +1341,8 @@ void apply_impl(hz_problem* pr, int op, const double2* x, const double2* f, doub
   float2* yout = fine_out ? b.ay32 : b.cy32;
   switch (op) {
     case HZ_OP_A0: {
-      const DevOp<double> a0{pr->cA0, nullptr, pr->M};
+      DevOp<double> a0{pr->cA0, nullptr, pr->M};
+      a0.pn = pr->cells;
       launch_stencil<double, float, double, double>(p, ST_APPLY, a0, xin, o, nullptr, o, y, o, 1, st);
       return;
     }
@@ -1393,6 +1466,10 @@ size_t hz_footprint_estimate(double k, double h, int p, const hz_options* o) {
   return resident_bytes(n, p, oo.restart, oo.prec);
 }
 
+namespace {
+hz_status finish_create(hz_problem* pr, hipStream_t st, clk::time_point t0, hz_problem** out);
+}
+
 hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_options* o,
                             void* hip_stream, hz_problem** out) {
   if (!out) return fail(HZ_EINVAL, "null output pointer");
@@ -1417,6 +1494,63 @@ hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_option
     pr->L = CoarseLayout{p, n / 2, pr->Mc};
     pr->m = opt.restart;
     upload_tables(pr, st);
+    return finish_create(pr, st, t0, out);
+  } catch (...) {
+    delete pr;
+    return map_exception();
+  }
+}
+
+hz_status hz_create_problem_cells(const double* k_cell, const hz_c64* s_cell, double h, int p,
+                                  const hz_options* o, void* hip_stream, hz_problem** out) {
+  if (!out) return fail(HZ_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (!k_cell || !s_cell) return fail(HZ_EINVAL, "null cell array");
+  hz_options opt;
+  hz_default_options(&opt);
+  if (o) opt = *o;
+  int n = 0;
+  std::string why;
+  if (!valid_problem(1.0, h, p, cd(1, 1), n, why) || !valid_options(opt, why)) return fail(HZ_EINVAL, why);
+  double kmax = 0.0;
+  for (long c = 0; c < long(n) * n; ++c) {
+    const double kv = k_cell[c];
+    const cd sv(s_cell[c].re, s_cell[c].im);
+    if (!(kv > 0) || !std::isfinite(kv))
+      return fail(HZ_EINVAL, "k_cell[" + std::to_string(c) + "] must be finite and > 0");
+    if (!std::isfinite(sv.real()) || !std::isfinite(sv.imag()) || !(sv.imag() > 0))
+      return fail(HZ_EINVAL, "s_cell[" + std::to_string(c) + "] must be finite with Im(s) > 0");
+    kmax = std::max(kmax, kv);
+  }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const auto t0 = clk::now();
+  hz_problem* pr = nullptr;
+  try {
+    pr = new hz_problem();
+    pr->k = kmax; pr->n = n; pr->p = p; pr->s = cd(0, 0); pr->opt = opt;
+    pr->cells = 1;
+    pr->M = p * n + 1;
+    pr->Mc = p * (n / 2) + 1;
+    pr->N = long(pr->M) * pr->M;
+    pr->Nc = long(pr->Mc) * pr->Mc;
+    pr->L = CoarseLayout{p, n / 2, pr->Mc};
+    pr->m = opt.restart;
+    upload_tables(pr, st);
+    upload_cells(pr, k_cell, s_cell, st);
+    return finish_create(pr, st, t0, out);
+  } catch (...) {
+    delete pr;
+    return map_exception();
+  }
+}
+
+namespace {
+
+// Coarse factor, coarse-solve buffers and V-cycle scratch of a problem whose operators are
+// on the device; deletes pr on failure.
+hz_status finish_create(hz_problem* pr, hipStream_t st, clk::time_point t0, hz_problem** out) {
+  const hz_options& opt = pr->opt;
+  try {
     // coarse factor (FP64), then the FP32 copy for mixed-precision problems
     pr->S = opt.prec == HZ_MIXED ? pr->mem.alloc_async<double2>(pr->L.total(), st)
                                  : pr->mem.alloc<double2>(pr->L.total());
@@ -1427,7 +1561,8 @@ hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_option
       wk.W = pr->mem.alloc_async<double2>(2 * sweep_panel_elems(mb), st);
       wk.R = pr->mem.alloc_async<double2>(2 * sweep_pinv_elems(), st);
       wk.flag = pr->mem.alloc_async<int>(1, st);
-      const DevOp<double> cop{pr->cAc, nullptr, pr->Mc};
+      DevOp<double> cop{pr->cAc, nullptr, pr->Mc};
+      cop.pn = pr->cells;
       pr->timing = opt.timing != 0;
       hipEvent_t f0 = nullptr, f1 = nullptr;
       if (pr->timing) {
@@ -1488,6 +1623,8 @@ hz_status hz_create_problem(double k, double h, int p, hz_c64 s, const hz_option
   }
 }
 
+}  // namespace
+
 hz_status hz_problem_info(const hz_problem* pr, long* n_dofs, long* n_coarse, size_t* footprint) {
   if (!pr) return fail(HZ_EINVAL, "null problem");
   if (n_dofs) *n_dofs = pr->N;
@@ -1502,6 +1639,23 @@ hz_status hz_planewave_rhs(const hz_problem* pr, double theta, hz_c64* d_F, void
   try {
     launch_planewave(pr->p, pr->n, pr->k, theta, pr->gl_t, pr->gl_w, pr->lag,
                      reinterpret_cast<double2*>(d_F), static_cast<hipStream_t>(hip_stream));
+    return HZ_OK;
+  } catch (...) {
+    return map_exception();
+  }
+}
+
+hz_status hz_gaussian_rhs(const hz_problem* pr, double sx, double sy, double amp, double width,
+                          hz_c64* d_F, void* hip_stream) {
+  if (!pr || !d_F) return fail(HZ_EINVAL, "null argument");
+  if (!std::isfinite(sx) || !std::isfinite(sy) || !std::isfinite(amp) || !(width >= 0) ||
+      !std::isfinite(width))
+    return fail(HZ_EINVAL, "source centre and amplitude must be finite, width finite and >= 0");
+  try {
+    const double* q = pr->qtab;
+    launch_gauss_rhs(pr->p, pr->n, sx, sy, amp, width, q, q + pr->nq, q + 2 * pr->nq,
+                     q + 3 * pr->nq, pr->qloc, pr->nq, reinterpret_cast<double2*>(d_F),
+                     static_cast<hipStream_t>(hip_stream));
     return HZ_OK;
   } catch (...) {
     return map_exception();
@@ -1604,6 +1758,8 @@ hz_status hz_solve_batched(hz_problem* const* probs, int nprob, const hz_c64* co
     if (!probs[i]) return fail(HZ_EINVAL, "null problem");
     if (probs[i]->n != probs[0]->n || probs[i]->p != probs[0]->p)
       return fail(HZ_EINVAL, "batched problems must share (h, p)");
+    if (probs[i]->cells != probs[0]->cells)
+      return fail(HZ_EINVAL, "batched problems must all have constant k or all per-cell k");
     if (probs[i]->opt.nu != probs[0]->opt.nu)
       return fail(HZ_EINVAL, "batched problems must share nu");
     for (int i2 = 0; i2 < i; ++i2)

@@ -38,18 +38,33 @@ __device__ __forceinline__ double2 crecip(double2 a) {
 // stored): D_j -= A_{j,jn} Sn A_{jn,j}, done in two sparse-dense passes.
 // Tm[r'][c] = sum_{c' in block jn} Sn[r'][c'] A[c'][c],  c in block j. A is symmetric, so
 // A[c'][c] is the coefficient of the stencil of c at offset c' - c.
+// Stencil of coarse point (a, b): the class table row, or with per-point operators (pn) the
+// point's own entries at stride Nc; entry (dy, dx) is at cc[((dy + P) W + dx + P) * stride].
+template <int P>
+__device__ __forceinline__ const double2* stencil_of(const double2* coef, int pn, int a, int b,
+                                                     int Mc, long& stride) {
+  constexpr int W = 2 * P + 1, W2 = W * W;
+  if (pn) {
+    stride = long(Mc) * Mc;
+    return coef + long(b) * Mc + a;
+  }
+  stride = 1;
+  const int cls = (b % P) * P + (a % P);
+  const int reg = region(b, Mc) * 3 + region(a, Mc);
+  return coef + (cls * 9 + reg) * W2;
+}
+
 template <int P>
 __global__ void __launch_bounds__(256)
-k_schur_right(int j, int jn, int nc, int Mc, const double2* __restrict__ coef,
+k_schur_right(int j, int jn, int nc, int Mc, const double2* __restrict__ coef, int pn,
               const double2* __restrict__ Sn, int nn, int ncur, double2* __restrict__ Tm) {
-  constexpr int W = 2 * P + 1, W2 = W * W;
+  constexpr int W = 2 * P + 1;
   const int c = blockIdx.x * 256 + threadIdx.x;
   const int rp = blockIdx.y;
   if (c >= ncur) return;
   const int ac = c % Mc, bc = P * j + c / Mc;
-  const int cls = (bc % P) * P + (ac % P);
-  const int reg = region(bc, Mc) * 3 + region(ac, Mc);
-  const double2* cc = coef + (cls * 9 + reg) * W2;
+  long cs;
+  const double2* cc = stencil_of<P>(coef, pn, ac, bc, Mc, cs);
   const double2* srow = Sn + size_t(rp) * nn;
   const int lo = P * jn, hi = P * jn + (jn < nc ? P : 1);   // lattice rows of block jn
   double2 acc = make_double2(0, 0);
@@ -61,7 +76,7 @@ k_schur_right(int j, int jn, int nc, int Mc, const double2* __restrict__ coef,
     for (int dx = -P; dx <= P; ++dx) {
       const int aa = ac + dx;
       if (aa < 0 || aa >= Mc) continue;
-      const double2 cf = cc[(dy + P) * W + dx + P];
+      const double2 cf = cc[((dy + P) * W + dx + P) * cs];
       if (cf.x == 0.0 && cf.y == 0.0) continue;
       cfma(acc, cf, srow[(bb - lo) * Mc + aa]);
     }
@@ -72,22 +87,21 @@ k_schur_right(int j, int jn, int nc, int Mc, const double2* __restrict__ coef,
 // D[r][c] = (jn < 0 ? A_jj[r][c] : D[r][c]) - sum_{r' in block jn} A[r][r'] Tm[r'][c].
 template <int P>
 __global__ void __launch_bounds__(256)
-k_schur_left(int j, int jn, int nc, int Mc, const double2* __restrict__ coef,
+k_schur_left(int j, int jn, int nc, int Mc, const double2* __restrict__ coef, int pn,
              const double2* __restrict__ Tm, int ncur, double2* __restrict__ D) {
-  constexpr int W = 2 * P + 1, W2 = W * W;
+  constexpr int W = 2 * P + 1;
   const int c = blockIdx.x * 256 + threadIdx.x;
   const int r = blockIdx.y;
   if (c >= ncur) return;
   const int ar = r % Mc, br = P * j + r / Mc;
-  const int cls = (br % P) * P + (ar % P);
-  const int reg = region(br, Mc) * 3 + region(ar, Mc);
-  const double2* cr = coef + (cls * 9 + reg) * W2;
+  long cs;
+  const double2* cr = stencil_of<P>(coef, pn, ar, br, Mc, cs);
   double2 acc;
   if (jn < 0) {
     acc = make_double2(0, 0);
     const int ac = c % Mc, bc = P * j + c / Mc;
     const int dxa = ac - ar, dya = bc - br;
-    if (dxa >= -P && dxa <= P && dya >= -P && dya <= P) acc = cr[(dya + P) * W + dxa + P];
+    if (dxa >= -P && dxa <= P && dya >= -P && dya <= P) acc = cr[((dya + P) * W + dxa + P) * cs];
   } else {
     acc = D[size_t(r) * ncur + c];
     const int lo = P * jn, hi = P * jn + (jn < nc ? P : 1);
@@ -99,7 +113,7 @@ k_schur_left(int j, int jn, int nc, int Mc, const double2* __restrict__ coef,
       for (int dx = -P; dx <= P; ++dx) {
         const int aa = ar + dx;
         if (aa < 0 || aa >= Mc) continue;
-        const double2 cf = cr[(dy + P) * W + dx + P];
+        const double2 cf = cr[((dy + P) * W + dx + P) * cs];
         if (cf.x == 0.0 && cf.y == 0.0) continue;
         const double2 tv = Tm[size_t((bb - lo) * Mc + aa) * ncur + c];
         acc.x -= cf.x * tv.x - cf.y * tv.y;
@@ -591,6 +605,37 @@ __device__ __forceinline__ V2<T> coupling(int c, int j, int jn, int nc, int Mc,
   return acc;
 }
 
+// The same with per-point coefficients (the coarse point's own stencil, read from global
+// memory at stride Nc, offset-major).
+template <int P, typename T>
+__device__ __forceinline__ V2<T> coupling_pn(int c, int j, int jn, int nc, int Mc,
+                                             const V2<T>* __restrict__ coef, const V2<T>* yv) {
+  constexpr int W = 2 * P + 1;
+  int rl = 0;
+  if constexpr (P >= 2) rl += c >= Mc;
+  if constexpr (P >= 3) rl += c >= 2 * Mc;
+  const int ac = c - rl * Mc;
+  const int bc = P * j + rl;
+  const long Nc = long(Mc) * Mc;
+  const V2<T>* cc = coef + long(bc) * Mc + ac;
+  const int lo = P * jn, hi = P * jn + (jn < nc ? P : 1);
+  V2<T> acc = czero<T>();
+#pragma unroll
+  for (int dy = -P; dy <= P; ++dy) {
+    const int bb = bc + dy;
+    if (bb < lo || bb >= hi) continue;
+    const V2<T>* yr = yv + (bb - lo) * Mc;
+#pragma unroll
+    for (int dx = -P; dx <= P; ++dx) {
+      if (P == 1 && !couples(1, 0, 0, dx, dy)) continue;   // the P1 stencil has 7 points
+      const int aa = ac + dx;
+      if (aa < 0 || aa >= Mc) continue;
+      cfma(acc, cc[long((dy + P) * W + dx + P) * Nc], yr[aa]);
+    }
+  }
+  return acc;
+}
+
 // Polls lattice block jn of src (right-hand side h at src + h * sstride) until no value is
 // the sentinel, staging it into yv[h * nmax + .]; executed by the 128 exchange threads. Entry
 // (h, q) of a thread is column c0 + xl + 128 q of right-hand side h: every pending load of a
@@ -720,7 +765,9 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
   const int sw = wave - 2, rg = sw / CG, cg = sw - (sw / CG) * CG;
   const size_t bsz = size_t(P * Mc) * size_t(P * Mc);
   const long Nc = long(Mc) * Mc;
-  for (int i = threadIdx.x; i < NCOEF; i += 512) cl[i] = coef[i];
+  const int pn = job->pn;   // per-point coefficients: read from global memory, not staged
+  if (!pn)
+    for (int i = threadIdx.x; i < NCOEF; i += 512) cl[i] = coef[i];
 
   // exchange waves: dst[h][c] = b_j (forward steps) or 0, c < nj, in slices of 128 EH
   auto stage = [&](const StepPlan& q, V2<T>* dst) __attribute__((always_inline)) {
@@ -751,7 +798,8 @@ k_csolve(int s_begin, int s_end, int nc, int Mc, int Gp, CsJobs<T> jobs, long cs
                   __attribute__((always_inline)) {
     for (int h = 0; h < nrhs; ++h)
       for (int c = threadIdx.x; c < pl.nj; c += 512) {
-        const V2<T> cp = coupling<P, T>(c, pl.j, jn, nc, Mc, cl, yn + h * nmax);
+        const V2<T> cp = pn ? coupling_pn<P, T>(c, pl.j, jn, nc, Mc, coef, yn + h * nmax)
+                            : coupling<P, T>(c, pl.j, jn, nc, Mc, cl, yn + h * nmax);
         V2<T> tv = t[h * nmax + c];
         tv.x += sgn * cp.x;
         tv.y += sgn * cp.y;
@@ -1283,13 +1331,13 @@ void factor_block(const CoarseLayout& L, const DevOp<double>& cop, double2* S, i
   const int n = int(L.size(j));
   double2* D = S + L.off(j);
   const dim3 g2((n + 255) / 256, n);
-  k_schur_left<P><<<g2, 256, 0, st>>>(j, -1, L.nc, L.Mc, cop.coef, T, n, D);
+  k_schur_left<P><<<g2, 256, 0, st>>>(j, -1, L.nc, L.Mc, cop.coef, cop.pn, T, n, D);
   for (int jn : {jn1, jn2}) {
     if (jn < 0) continue;
     const int nn = int(L.size(jn));
     k_schur_right<P><<<dim3((n + 255) / 256, nn), 256, 0, st>>>(j, jn, L.nc, L.Mc, cop.coef,
-                                                                S + L.off(jn), nn, n, T);
-    k_schur_left<P><<<g2, 256, 0, st>>>(j, jn, L.nc, L.Mc, cop.coef, T, n, D);
+                                                                cop.pn, S + L.off(jn), nn, n, T);
+    k_schur_left<P><<<g2, 256, 0, st>>>(j, jn, L.nc, L.Mc, cop.coef, cop.pn, T, n, D);
   }
   // symmetric sweep: first panel and pivot inverse, one launch per pivot tile, final mirror
   const int nt = (n + SB - 1) / SB;
@@ -1400,6 +1448,7 @@ int coarse_solve(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, con
     CoarseJob<T> j;
     j.S = S;
     j.coef = cop.coef;
+    j.pn = cop.pn;
     j.b = b + r0 * cstride;
     j.y = y + r0 * cstride;
     j.gbuf = reinterpret_cast<V2<T>*>(w.g);

@@ -154,7 +154,8 @@ k_jacobi0(DevOp<T> op, const V2<TF>* __restrict__ f, Addr af, V2<T>* __restrict_
   const int cls = (b % P) * P + (a % P);
   const int reg = region(b, M) * 3 + region(a, M);
   const V2<T>* wd = op.wtab ? op.wtab[bz] : op.wdinv;
-  y[ay.at(bz) + i] = cmul<T>(wd[cls * 9 + reg], cvt<T>(f[af.at(bz) + i]));
+  const long wi = op.pn ? i : long(cls * 9 + reg);   // per point, or per (class, region)
+  y[ay.at(bz) + i] = cmul<T>(wd[wi], cvt<T>(f[af.at(bz) + i]));
 }
 
 // Workgroups of a 1D launch over lattice points are dealt round-robin to the 8 XCDs (each
@@ -449,6 +450,10 @@ void set_stencil_tuning(bool on) { tl_tune = on; }
 template <typename T, typename TX, typename TF, typename TY>
 void launch_stencil(int p, int mode, const DevOp<T>& op, const V2<TX>* x, Addr xs,
                     const V2<TF>* f, Addr fs, V2<TY>* y, Addr ys, int nbatch, hipStream_t st) {
+  if (op.pn) {
+    launch_stencil_pn<T, TX, TF, TY>(p, mode, op, x, xs, f, fs, y, ys, nbatch, st);
+    return;
+  }
   if (p == 1) stencil_p<1, T, TX, TF, TY>(mode, op, x, xs, f, fs, y, ys, nbatch, st);
   else if (p == 2) stencil_p<2, T, TX, TF, TY>(mode, op, x, xs, f, fs, y, ys, nbatch, st);
   else stencil_p<3, T, TX, TF, TY>(mode, op, x, xs, f, fs, y, ys, nbatch, st);

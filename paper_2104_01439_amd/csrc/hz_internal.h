@@ -39,6 +39,30 @@ struct LevelTables {
 };
 
 LevelTables build_level_tables(int p, int n, double h);
+
+// Per-cell coefficient tables of one level whose cells are r x r fine cells (r = 1: the fine
+// level, r = 2: the coarse level), fine cell side hf. For a lattice point of class
+// cls = (b mod p) p + (a mod p) in level cell (A0, B0) = (a div p, b div p) and a neighbour
+// offset d = (dy + p)(2p + 1) + (dx + p), entry f = (fy + r) 2r + (fx + r) holds the integrals
+// over fine cell (r A0 + fx, r B0 + fy), fx, fy in [-r, r), of grad phi_i . grad phi_j (K) and
+// phi_i phi_j (Mm): K[(cls W2 + d) 4r^2 + f]. B[(cc (2p+1) + (e + p)) 2r + (fe + r)] is the
+// integral of the boundary traces over fine boundary edge r E0 + fe of a point at position
+// p E0 + cc along a side, neighbour at offset e along the same side.
+struct CellTables {
+  int p = 1, r = 1;
+  std::vector<double> K, Mm, B;
+};
+CellTables build_cell_tables(int p, int r, double hf);
+
+// Collapsed q x q Gauss-Legendre rule on the reference triangle (xi, eta, w), the basis values
+// phi[r * nq + k] and loc[cls * 8 + ((Bc + 1) 2 + (Ac + 1)) 2 + tri]: the local index of a
+// point of class cls in triangle tri of the cell at (Ac, Bc) in {-1, 0}^2 from its own, or -1.
+struct QuadTables {
+  int p = 1, nq = 0;
+  std::vector<double> xi, eta, w, phi;
+  std::vector<int> loc;
+};
+QuadTables build_quad_tables(int p, int q);
 std::vector<cd> combine_operator(const LevelTables& t, double k, cd s);
 
 // ------------------------------------------------------------------------------------------
@@ -66,12 +90,16 @@ struct Addr {
 // A batched launch may give every batch element its own operator (problems of one mesh
 // class with different k or shift): ctab / wtab are then device tables of per-element
 // pointers that replace coef / wdinv.
+// With pn = 1 the operator varies from point to point (heterogeneous k): coef holds one
+// stencil per lattice point, [(2p+1)^2][M*M] (offset-major), and wdinv one multiplier per
+// point, [M*M].
 template <typename T> struct DevOp {
   const V2<T>* coef = nullptr;   // [p*p*9][(2p+1)^2]
   const V2<T>* wdinv = nullptr;  // [p*p*9]
   int M = 0;                     // lattice points per side
   const V2<T>* const* ctab = nullptr;
   const V2<T>* const* wtab = nullptr;
+  int pn = 0;
 };
 
 // Coarse block-tridiagonal factor: block j (j < nc) holds lattice rows p j .. p j + p - 1,
@@ -101,6 +129,10 @@ enum StencilMode { ST_APPLY = 0, ST_RESID = 1, ST_SMOOTH = 2, ST_SMOOTH0 = 3 };
 template <typename T, typename TX, typename TF, typename TY>
 void launch_stencil(int p, int mode, const DevOp<T>& op, const V2<TX>* x, Addr ax,
                     const V2<TF>* f, Addr af, V2<TY>* y, Addr ay, int nbatch, hipStream_t st);
+// The same for per-point operators (op.pn = 1); called by launch_stencil.
+template <typename T, typename TX, typename TF, typename TY>
+void launch_stencil_pn(int p, int mode, const DevOp<T>& op, const V2<TX>* x, Addr ax,
+                       const V2<TF>* f, Addr af, V2<TY>* y, Addr ay, int nbatch, hipStream_t st);
 // y = wdinv * f (the first sweep from a zero guess).
 template <typename T, typename TF>
 void launch_jacobi0(int p, const DevOp<T>& op, const V2<TF>* f, Addr af, V2<T>* y, Addr ay,
@@ -112,6 +144,18 @@ void launch_restrict(int p, int Mf, int Mc, const T* rw, const V2<T>* r, V2<T>* 
 template <typename T>
 void launch_prolong(int p, int Mf, int Mc, const T* rw, const V2<T>* xc, V2<T>* yf, bool add,
                     int nbatch, Addr af, Addr ac, hipStream_t st);
+// Per-point operators from per-cell k and shift (heterogeneous k), on a level of order p with
+// r x r fine cells per level cell and M lattice points per side; kc [nf*nf] real, sc [nf*nf]
+// complex shift multipliers (nullptr: s = 1), nf = r (M - 1) / p fine cells per side.
+// Writes A [(2p+1)^2][M*M] and, when wd is given, wd = omega / diag(A).
+void launch_assemble_cells(int p, int r, int M, const double* tabK, const double* tabM,
+                           const double* tabB, const double* kc, const double2* sc,
+                           double omega, double2* A, double2* wd, hipStream_t st);
+// Load vector of the point source f = amp exp(-width |x - x_s|^2) (g = 0) on the fine lattice:
+// F_i = sum over the triangles T around point i of the quadrature of f phi_i on T.
+void launch_gauss_rhs(int p, int n, double sx, double sy, double amp, double width,
+                      const double* qxi, const double* qeta, const double* qw,
+                      const double* qphi, const int* qloc, int nq, double2* F, hipStream_t st);
 // Plane-wave impedance load vector.
 void launch_planewave(int p, int n, double k, double theta, const double* gl_t,
                       const double* gl_w, const double* lag, double2* F, hipStream_t st);
@@ -152,7 +196,7 @@ template <typename T> struct CoarseJob {
   V2<T>* y = nullptr;
   V2<T>* gbuf = nullptr;
   int nrhs = 1;
-  int pad = 0;
+  int pn = 0;              // coef holds one stencil per coarse point (as DevOp::pn)
 };
 constexpr int kMaxJobs = 16;
 template <typename T> struct CsJobs {

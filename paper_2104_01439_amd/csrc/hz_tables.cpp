@@ -255,6 +255,251 @@ LevelTables build_level_tables(int p, int n, double h) {
   return t;
 }
 
+// ------------------------------------------------------------------------------------------
+// Per-cell coefficient tables (heterogeneous k)
+// ------------------------------------------------------------------------------------------
+
+namespace {
+
+// Bivariate polynomial of total degree <= 6: c[a][b] multiplies x^a y^b.
+struct Poly2 {
+  double c[7][7];
+  Poly2() { std::memset(c, 0, sizeof(c)); }
+};
+
+Poly2 pmul(const Poly2& A, const Poly2& B) {
+  Poly2 r;
+  for (int a1 = 0; a1 <= 6; ++a1)
+    for (int b1 = 0; a1 + b1 <= 6; ++b1) {
+      if (A.c[a1][b1] == 0.0) continue;
+      for (int a2 = 0; a1 + a2 <= 6; ++a2)
+        for (int b2 = 0; a1 + b1 + a2 + b2 <= 6; ++b2) r.c[a1 + a2][b1 + b2] += A.c[a1][b1] * B.c[a2][b2];
+    }
+  return r;
+}
+
+Poly2 paffine(double c0, double cx, double cy) {
+  Poly2 r;
+  r.c[0][0] = c0;
+  r.c[1][0] = cx;
+  r.c[0][1] = cy;
+  return r;
+}
+
+Poly2 ppow(const Poly2& A, int e) {
+  Poly2 r;
+  r.c[0][0] = 1.0;
+  for (int i = 0; i < e; ++i) r = pmul(r, A);
+  return r;
+}
+
+// Integral over the reference triangle {x, y >= 0, x + y <= 1}.
+double pint(const Poly2& A) {
+  double s = 0.0;
+  for (int a = 0; a <= 6; ++a)
+    for (int b = 0; a + b <= 6; ++b)
+      if (A.c[a][b] != 0.0) s += A.c[a][b] * fact(a) * fact(b) / fact(a + b + 2);
+  return s;
+}
+
+// sum_m coef[m] x^ma y^mb (monomials of the element, exponents shifted by (-dx, -dy) and
+// scaled for a derivative), composed with x = lx(xi, eta), y = ly(xi, eta).
+Poly2 compose(const RefElement& el, const double* coef, int der, const Poly2& lx,
+              const Poly2& ly) {
+  Poly2 r;
+  for (int m = 0; m < el.nloc; ++m) {
+    if (coef[m] == 0.0) continue;
+    int a = el.ma[m], b = el.mb[m];
+    double f = coef[m];
+    if (der == 1) { if (a == 0) continue; f *= a; --a; }
+    if (der == 2) { if (b == 0) continue; f *= b; --b; }
+    const Poly2 t = pmul(ppow(lx, a), ppow(ly, b));
+    for (int i = 0; i <= 6; ++i)
+      for (int j = 0; i + j <= 6; ++j) r.c[i][j] += f * t.c[i][j];
+  }
+  return r;
+}
+
+// 1D polynomial coefficients (degree <= p) of the p + 1 equispaced cardinal functions on [0, 1].
+void cardinal_1d(int p, double coef[4][4]) {
+  for (int s = 0; s <= p; ++s) {
+    double c[4] = {1, 0, 0, 0};
+    double den = 1.0;
+    for (int q = 0; q <= p; ++q) {
+      if (q == s) continue;
+      const double tq = double(q) / p;
+      double nc[4] = {0, 0, 0, 0};
+      for (int d = 3; d >= 0; --d) {
+        if (d > 0) nc[d] += c[d - 1];
+        nc[d] -= tq * c[d];
+      }
+      std::memcpy(c, nc, sizeof(c));
+      den *= (double(s) / p - tq);
+    }
+    for (int d = 0; d < 4; ++d) coef[s][d] = c[d] / den;
+  }
+}
+
+}  // namespace
+
+CellTables build_cell_tables(int p, int r, double hf) {
+  CellTables t;
+  t.p = p;
+  t.r = r;
+  const int W = 2 * p + 1, W2 = W * W, NF = 4 * r * r;
+  t.K.assign(size_t(p) * p * W2 * NF, 0.0);
+  t.Mm.assign(t.K.size(), 0.0);
+  t.B.assign(size_t(p) * W * 2 * r, 0.0);
+  RefElement el(p);
+  // Level triangle T of a level cell of side r (fine-cell units): x = J_T xi.
+  // Fine triangle t of sub-cell (sx, sy): x = (sx, sy) + J_t xi.
+  const double JL[2][2] = {{1, 1}, {0, 1}}, JU[2][2] = {{1, 0}, {1, 1}};
+  for (int cb = 0; cb < p; ++cb)
+    for (int ca = 0; ca < p; ++ca) {
+      const int cls = cb * p + ca;
+      for (int Bc = -1; Bc <= 0; ++Bc)
+        for (int Ac = -1; Ac <= 0; ++Ac)
+          for (int tri = 0; tri < 2; ++tri) {
+            int rl = -1;
+            for (int q = 0; q < el.nloc; ++q) {
+              int da, db;
+              local_offset(el, tri, q, da, db);
+              if (p * Ac + da == ca && p * Bc + db == cb) rl = q;
+            }
+            if (rl < 0) continue;
+            const double(*JT)[2] = tri == 0 ? JL : JU;
+            // J_T^{-1} for J_T = r * JT (det JT = 1)
+            const double Ti[2][2] = {{JT[1][1] / r, -JT[0][1] / r}, {-JT[1][0] / r, JT[0][0] / r}};
+            for (int sy = 0; sy < r; ++sy)
+              for (int sx = 0; sx < r; ++sx)
+                for (int ft = 0; ft < 2; ++ft) {
+                  // the fine triangle lies in T when its centroid does
+                  const double gx = sx + (ft == 0 ? 2.0 : 1.0) / 3.0;
+                  const double gy = sy + (ft == 0 ? 1.0 : 2.0) / 3.0;
+                  if (tri == 0 ? !(gy < gx) : !(gy > gx)) continue;
+                  const double(*Jt)[2] = ft == 0 ? JL : JU;
+                  // xi_T = Ti (v0_t + Jt xi) = G xi + g
+                  double G[2][2], g[2];
+                  for (int i = 0; i < 2; ++i) {
+                    g[i] = Ti[i][0] * sx + Ti[i][1] * sy;
+                    for (int j = 0; j < 2; ++j) G[i][j] = Ti[i][0] * Jt[0][j] + Ti[i][1] * Jt[1][j];
+                  }
+                  const Poly2 lx = paffine(g[0], G[0][0], G[0][1]);
+                  const Poly2 ly = paffine(g[1], G[1][0], G[1][1]);
+                  double ci[10], cj[10];
+                  for (int m = 0; m < el.nloc; ++m) ci[m] = el.C[m][rl];
+                  const Poly2 phi_i = compose(el, ci, 0, lx, ly);
+                  // physical gradient (fine units): grad_x = T^{-T} grad_xi
+                  const Poly2 di0 = compose(el, ci, 1, lx, ly), di1 = compose(el, ci, 2, lx, ly);
+                  const int fx = r * Ac + sx, fy = r * Bc + sy;
+                  const int f = (fy + r) * 2 * r + (fx + r);
+                  for (int q = 0; q < el.nloc; ++q) {
+                    int ea, eb;
+                    local_offset(el, tri, q, ea, eb);
+                    const int ox = p * Ac + ea - ca, oy = p * Bc + eb - cb;
+                    for (int m = 0; m < el.nloc; ++m) cj[m] = el.C[m][q];
+                    const Poly2 phi_j = compose(el, cj, 0, lx, ly);
+                    const Poly2 dj0 = compose(el, cj, 1, lx, ly), dj1 = compose(el, cj, 2, lx, ly);
+                    double kv = 0.0;
+                    for (int k = 0; k < 2; ++k) {
+                      // (grad_x phi)_k = Ti[0][k] d/dxi + Ti[1][k] d/deta
+                      Poly2 gi, gj;
+                      for (int a = 0; a <= 6; ++a)
+                        for (int b = 0; a + b <= 6; ++b) {
+                          gi.c[a][b] = Ti[0][k] * di0.c[a][b] + Ti[1][k] * di1.c[a][b];
+                          gj.c[a][b] = Ti[0][k] * dj0.c[a][b] + Ti[1][k] * dj1.c[a][b];
+                        }
+                      kv += pint(pmul(gi, gj));
+                    }
+                    const double mv = hf * hf * pint(pmul(phi_i, phi_j));
+                    const size_t o = (size_t(cls) * W2 + (oy + p) * W + (ox + p)) * NF + f;
+                    t.K[o] += kv;     // |det J_t| = 1 in fine units; stiffness is scale-free
+                    t.Mm[o] += mv;
+                  }
+                }
+          }
+    }
+  // boundary: node at position c = p E0 + cc along a side; level edges E0 - 1, E0 (length
+  // r hf) with local nodes q = 0..p; fine sub-edge s of a level edge covers t in [s/r, (s+1)/r]
+  double coef[4][4];
+  cardinal_1d(p, coef);
+  for (int cc = 0; cc < p; ++cc)
+    for (int erel = -1; erel <= 0; ++erel) {
+      const int qi = cc - p * erel;
+      if (qi < 0 || qi > p) continue;
+      for (int d = -p; d <= p; ++d) {
+        const int qj = cc + d - p * erel;
+        if (qj < 0 || qj > p) continue;
+        double prod[7] = {0, 0, 0, 0, 0, 0, 0};
+        for (int a = 0; a <= p; ++a)
+          for (int b = 0; b <= p; ++b) prod[a + b] += coef[qi][a] * coef[qj][b];
+        for (int s = 0; s < r; ++s) {
+          const double t0 = double(s) / r, t1 = double(s + 1) / r;
+          double v = 0.0;
+          for (int e = 0; e <= 2 * p; ++e)
+            v += prod[e] * (std::pow(t1, e + 1) - std::pow(t0, e + 1)) / (e + 1);
+          const int fe = r * erel + s;
+          t.B[(size_t(cc) * W + (d + p)) * 2 * r + (fe + r)] += r * hf * v;
+        }
+      }
+    }
+  return t;
+}
+
+// Collapsed Gauss-Legendre rule on the reference triangle: xi = u, eta = (1 - u) v with
+// weight w_u w_v (1 - u), q Gauss points per direction on [0, 1]; plus the basis values at
+// the points and, per class and neighbouring triangle, the local index of the point.
+QuadTables build_quad_tables(int p, int q) {
+  QuadTables t;
+  t.p = p;
+  t.nq = q * q;
+  std::vector<double> x(q), w(q);
+  for (int i = 0; i < q; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (q + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1, p1 = z;
+      for (int kk = 2; kk <= q; ++kk) {
+        const double p2 = ((2 * kk - 1) * z * p1 - (kk - 1) * p0) / kk;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = q * (z * p1 - p0) / (z * z - 1);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = 0.5 * (z + 1);
+    w[i] = 1.0 / ((1 - z * z) * dp * dp);
+  }
+  RefElement el(p);
+  t.xi.resize(t.nq);
+  t.eta.resize(t.nq);
+  t.w.resize(t.nq);
+  t.phi.assign(size_t(el.nloc) * t.nq, 0.0);
+  for (int a = 0; a < q; ++a)
+    for (int b = 0; b < q; ++b) {
+      const int k = a * q + b;
+      t.xi[k] = x[a];
+      t.eta[k] = (1 - x[a]) * x[b];
+      t.w[k] = w[a] * w[b] * (1 - x[a]);
+      for (int r = 0; r < el.nloc; ++r) t.phi[size_t(r) * t.nq + k] = el.phi(r, t.xi[k], t.eta[k]);
+    }
+  t.loc.assign(size_t(p) * p * 8, -1);
+  for (int cb = 0; cb < p; ++cb)
+    for (int ca = 0; ca < p; ++ca)
+      for (int Bc = -1; Bc <= 0; ++Bc)
+        for (int Ac = -1; Ac <= 0; ++Ac)
+          for (int tri = 0; tri < 2; ++tri)
+            for (int r = 0; r < el.nloc; ++r) {
+              int da, db;
+              local_offset(el, tri, r, da, db);
+              if (p * Ac + da == ca && p * Bc + db == cb)
+                t.loc[size_t(cb * p + ca) * 8 + ((Bc + 1) * 2 + (Ac + 1)) * 2 + tri] = r;
+            }
+  return t;
+}
+
 std::vector<cd> combine_operator(const LevelTables& t, double k, cd s) {
   std::vector<cd> c(t.K.size());
   const cd k2s = s * (k * k);

@@ -8,6 +8,7 @@ torch is imported before the library so that both share one HIP runtime.
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -103,6 +104,10 @@ _SIGS = {
     "hz_footprint_estimate": (ctypes.c_size_t, [ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                                 ctypes.POINTER(Options)]),
     "hz_planewave_rhs": (ctypes.c_int, [_P, ctypes.c_double, _P, _P]),
+    "hz_create_problem_cells": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int,
+                                               ctypes.POINTER(Options), _P, ctypes.POINTER(_P)]),
+    "hz_gaussian_rhs": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, _P, _P]),
     "hz_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(Options), ctypes.POINTER(Result),
                                 ctypes.POINTER(ctypes.c_double), _P]),
     "hz_apply": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_int, _P]),
@@ -202,6 +207,27 @@ class Problem:
                                        ctypes.byref(self.opts), _stream(), ctypes.byref(self._h)))
         self.M, self.N, self.Mc, self.Nc = sizes(self.n, self.p)
 
+    @classmethod
+    def cells(cls, k_cell, s_cell, h, p, nu=2, omega=0.6, restart=50, maxit=5000, tol=1e-8,
+              prec="fp64", timing=False):
+        """create_problem_cells: k and the shift multiplier per cell of the n x n fine mesh
+        (arrays indexed [row j (y), column i (x)])."""
+        self = cls.__new__(cls)
+        self.h, self.p = float(h), int(p)
+        self.n = int(round(1.0 / h))
+        kc = np.ascontiguousarray(k_cell, dtype=np.float64)
+        sc = np.ascontiguousarray(s_cell, dtype=np.complex128)
+        if kc.shape != (self.n, self.n) or sc.shape != (self.n, self.n):
+            raise ValueError(f"cell arrays must be {self.n} x {self.n}")
+        self.k, self.s = float(kc.max()), None
+        self.opts = options(nu, omega, restart, maxit, tol, prec, timing)
+        self._h = ctypes.c_void_p()
+        _check(lib().hz_create_problem_cells(kc.ctypes.data, sc.ctypes.data, self.h, self.p,
+                                             ctypes.byref(self.opts), _stream(),
+                                             ctypes.byref(self._h)))
+        self.M, self.N, self.Mc, self.Nc = sizes(self.n, self.p)
+        return self
+
     @property
     def handle(self):
         return self._h
@@ -222,6 +248,12 @@ class Problem:
     def planewave_rhs(self, theta, out=None):
         F = self.empty() if out is None else out
         _check(lib().hz_planewave_rhs(self._h, float(theta), _ptr(F), _stream()))
+        return F
+
+    def gaussian_rhs(self, center, amp=2.0, width=1000.0, out=None):
+        F = self.empty() if out is None else out
+        _check(lib().hz_gaussian_rhs(self._h, float(center[0]), float(center[1]), float(amp),
+                                     float(width), _ptr(F), _stream()))
         return F
 
     def solve(self, F, u=None, tol=None, restart=None, maxit=None, prec=None, history=True):

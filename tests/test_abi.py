@@ -110,6 +110,39 @@ def test_null_arguments(hz):
     L.hz_destroy_problem(None)
 
 
+@pytest.mark.parametrize("bad", ["k_zero", "k_nan", "s_real", "s_neg", "odd_n", "null"])
+def test_create_cells_rejects_invalid_cells(hz, bad):
+    """Per-cell k and shift are validated on the host, naming the first bad cell."""
+    import numpy as np
+    n = 8 if bad != "odd_n" else 7
+    kc = np.full((n, n), 5.0)
+    sc = np.full((n, n), 1 + 0.5j)
+    if bad == "k_zero":
+        kc[3, 2] = 0.0
+    elif bad == "k_nan":
+        kc[0, 7] = float("nan")
+    elif bad == "s_real":
+        sc[5, 5] = 1.0
+    elif bad == "s_neg":
+        sc[1, 0] = 1 - 0.2j
+    handle = ctypes.c_void_p()
+    o = hz.options()
+    args = (None, None) if bad == "null" else (kc.ctypes.data, sc.ctypes.data)
+    st = hz.lib().hz_create_problem_cells(*args, 1.0 / n, 1, ctypes.byref(o), None,
+                                          ctypes.byref(handle))
+    assert st == hz.HZ_EINVAL and handle.value is None
+    msg = hz.lib().hz_last_error().decode()
+    if bad == "k_zero":
+        assert "k_cell[26]" in msg
+    if bad == "s_real":
+        assert "s_cell[45]" in msg
+
+
+def test_gaussian_rhs_rejects_null(hz):
+    L = hz.lib()
+    assert L.hz_gaussian_rhs(None, 0.5, 0.5, 2.0, 1000.0, None, None) == hz.HZ_EINVAL
+
+
 def test_inputs_are_seeded():
     from paper_2104_01439_amd import inputs
     a = inputs.random_complex(100, seed=3)
