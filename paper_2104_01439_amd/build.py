@@ -16,6 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhz.so")
 
 SOURCES = ["hz_tables.cpp", "hz_fine.hip", "hz_coarse.hip", "hz_krylov.hip", "hz_cells.hip",
+           "hz_mf.hip",
            "hz_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -145,7 +145,12 @@ struct hz_problem {
   hz_options opt{};
   int M = 0, Mc = 0;
   long N = 0, Nc = 0;
+  long G = 0;                 // coarse-solve work per right-hand side (elements)
   CoarseLayout L;
+  const MfSym* sym = nullptr; // multifrontal coarse factor (else the block-tridiagonal one)
+  MfView* dmf = nullptr;      // device copy of its symbolic data (and hmf, the same view
+  MfView hmf;                 // held on the host: device pointers for host-side launches)
+  size_t fel = 0;             // coarse factor elements
   DevMem mem;
   // FP64 operators and tables
   double2 *cA0 = nullptr, *cAe = nullptr, *wdAe = nullptr, *cAc = nullptr;
@@ -266,9 +271,26 @@ void gauss_legendre10(double* t, double* w) {
   }
 }
 
+// Coarse direct solver: the multifrontal factor (nested dissection) unless HZ_COARSE=band
+// selects the block-tridiagonal factor with the persistent block solve.
+bool use_mf() {
+  static const bool on = [] {
+    const char* e = std::getenv("HZ_COARSE");
+    return !(e && std::string(e) == "band");
+  }();
+  return on;
+}
+
+// Bytes of the device copy of a symbolic factor (nodes, point lists, maps, tasks, view).
+size_t mf_sym_bytes(const MfSym& y) {
+  return y.nodes.size() * sizeof(MfNode) + (y.I.size() + y.B.size() + y.map.size() + y.hn.size()) * 4 +
+         (y.fwd.size() + y.bwd.size()) * sizeof(MfTask) + sizeof(MfView) + 8 * 256;
+}
+
 struct Sizes {
   long N, Nc;
-  size_t factor_elems, maxblock;
+  long G;                  // coarse-solve work per right-hand side (elements)
+  size_t factor_elems, maxblock, sym_bytes;
   int nblk;
 };
 Sizes sizes_of(int n, int p) {
@@ -277,17 +299,26 @@ Sizes sizes_of(int n, int p) {
   z.N = long(M) * M;
   z.Nc = long(Mc) * Mc;
   CoarseLayout L{p, n / 2, Mc};
-  z.factor_elems = L.total();
   z.maxblock = size_t(L.size(0));
+  if (use_mf()) {
+    const MfSym& y = mf_symbolic(p, n / 2);
+    z.factor_elems = size_t(y.numel);
+    z.G = std::max(z.Nc, y.uel);
+    z.sym_bytes = mf_sym_bytes(y);
+  } else {
+    z.factor_elems = L.total();
+    z.G = z.Nc;
+    z.sym_bytes = 0;
+  }
   z.nblk = mdot_blocks(z.N);
   return z;
 }
 
-// Bytes of the V-cycle scratch for `cap` right-hand sides.
-size_t scratch_bytes(long N, long Nc, int cap, int prec) {
+// Bytes of the V-cycle scratch for `cap` right-hand sides (G: coarse-solve work each).
+size_t scratch_bytes(long N, long Nc, long G, int cap, int prec) {
   const size_t it = prec == HZ_MIXED ? 8 : 16;
   return size_t(cap) * ((prec == HZ_MIXED ? 4 : 3) * size_t(N) + 2 * size_t(Nc)) * it +
-         size_t(cap) * Nc * 16;   // forward-sweep buffers
+         size_t(cap) * G * 16;   // coarse-solve work
 }
 
 // Bytes of a Krylov workspace for `cap` solves with restart capacity m (staged: with room
@@ -307,9 +338,9 @@ size_t workspace_bytes(long N, int nblk, int cap, int m, int prec, bool staged) 
 size_t resident_bytes(int n, int p, int m, int prec) {
   const Sizes z = sizes_of(n, p);
   size_t b = z.factor_elems * (prec == HZ_MIXED ? 8 : 16);
-  b += scratch_bytes(z.N, z.Nc, 1, prec);
+  b += scratch_bytes(z.N, z.Nc, z.G, 1, prec);
   b += workspace_bytes(z.N, z.nblk, 1, m, prec, false);
-  b += 64 * 1024 + 4 * size_t(z.Nc) * 16 + 256;                // tables, coarse-solve buffers
+  b += 64 * 1024 + 4 * size_t(z.G) * 16 + 256 + z.sym_bytes;   // tables, coarse-solve buffers
   return b;
 }
 
@@ -415,6 +446,41 @@ void upload_cells(hz_problem* pr, const double* k_cell, const hz_c64* s_cell, hi
   for (void* d : tmp) pr->mem.release_async(d, st);
 }
 
+// Device copy of the problem's symbolic multifrontal data: one allocation holding the nodes,
+// point lists, maps, node order, solve tasks and the view struct the kernels read.
+void upload_symbolic(hz_problem* pr, hipStream_t st) {
+  const MfSym& y = *pr->sym;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t bn = al(y.nodes.size() * sizeof(MfNode)), bI = al(y.I.size() * 4),
+               bB = al(y.B.size() * 4), bm = al(y.map.size() * 4), bh = al(y.hn.size() * 4),
+               bf = al(y.fwd.size() * sizeof(MfTask)), bb = al(y.bwd.size() * sizeof(MfTask)),
+               bv = al(sizeof(MfView));
+  const size_t tot = bn + bI + bB + bm + bh + bf + bb + bv;
+  char* d = pr->mem.alloc<char>(tot);
+  std::vector<char> h(tot, 0);
+  MfView v;
+  size_t o = 0;
+  auto put = [&](const void* src, size_t bytes, size_t span) {
+    std::memcpy(h.data() + o, src, bytes);
+    const char* at = d + o;
+    o += span;
+    return at;
+  };
+  v.nodes = reinterpret_cast<const MfNode*>(put(y.nodes.data(), y.nodes.size() * sizeof(MfNode), bn));
+  v.I = reinterpret_cast<const int*>(put(y.I.data(), y.I.size() * 4, bI));
+  v.B = reinterpret_cast<const int*>(put(y.B.data(), y.B.size() * 4, bB));
+  v.map = reinterpret_cast<const int*>(put(y.map.data(), y.map.size() * 4, bm));
+  v.hn = reinterpret_cast<const int*>(put(y.hn.data(), y.hn.size() * 4, bh));
+  v.fwd = reinterpret_cast<const MfTask*>(put(y.fwd.data(), y.fwd.size() * sizeof(MfTask), bf));
+  v.bwd = reinterpret_cast<const MfTask*>(put(y.bwd.data(), y.bwd.size() * sizeof(MfTask), bb));
+  pr->dmf = reinterpret_cast<MfView*>(const_cast<char*>(put(&v, sizeof(MfView), bv)));
+  HZ_HIP(hipMemcpyAsync(d, h.data(), tot, hipMemcpyHostToDevice, st));
+  HZ_HIP(hipStreamSynchronize(st));   // h is local
+  pr->hmf = v;
+}
+
+const MfView& host_view(const hz_problem* pr) { return pr->hmf; }
+
 template <typename T>
 void alloc_scratch(DevMem& mem, Scratch<T>& sc, int cap, long N, long Nc, bool with_ff) {
   sc.cap = cap;
@@ -433,8 +499,8 @@ void ensure_fp64_work(hz_problem* pr) {
 
 void ensure_mixed_work(hz_problem* pr, hipStream_t st) {
   if (!pr->Sf) {
-    pr->Sf = pr->mem.alloc<float2>(pr->L.total());
-    launch_factor_to_f32(pr->S, pr->Sf, pr->L.total(), st);
+    pr->Sf = pr->mem.alloc<float2>(pr->fel);
+    launch_factor_to_f32(pr->S, pr->Sf, pr->fel, st);
   }
   if (pr->s32.cap) return;
   alloc_scratch<float>(pr->mem, pr->s32, 1, pr->N, pr->Nc, true);
@@ -479,8 +545,8 @@ Region region_at(char* base, int cap) {
   return r;
 }
 
-std::unique_ptr<Workspace> make_workspace(int cap, int m, int prec, long N, long Nc, int rcap,
-                                          bool staged) {
+std::unique_ptr<Workspace> make_workspace(int cap, int m, int prec, long N, long Nc, long G,
+                                          int rcap, bool staged) {
   std::unique_ptr<Workspace> w(new Workspace());
   w->cap = cap; w->m = m; w->prec = prec; w->N = N; w->Nc = Nc; w->nblk = mdot_blocks(N);
   w->V = w->mem.alloc<double2>(size_t(cap) * (m + 1) * N);
@@ -499,7 +565,7 @@ std::unique_ptr<Workspace> make_workspace(int cap, int m, int prec, long N, long
   if (rcap > 0) {
     if (prec == HZ_MIXED) alloc_scratch<float>(w->mem, w->s32, rcap, N, Nc, true);
     else alloc_scratch<double>(w->mem, w->s64, rcap, N, Nc, false);
-    w->gb = w->mem.alloc<double2>(size_t(rcap) * Nc);
+    w->gb = w->mem.alloc<double2>(size_t(rcap) * G);
   }
   HZ_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->pin), size_t(cap) * 192 * 16, hipHostMallocDefault));
   HZ_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->up), 2 * w->up_bytes, hipHostMallocDefault));
@@ -561,6 +627,13 @@ void collect_timing(hz_problem* pr, bool wait) {
 // Algorithmic bytes of one coarse solve job: the stored factor read twice (the last block
 // once) plus, per right-hand side, the coarse vector read and the solution written and
 // re-read.
+// Multifrontal solve: every stored matrix read once (S and G^T forward, G backward), plus per
+// right-hand side the coarse vector read, the solution written and re-read.
+double mf_job_bytes(const MfSym& y, size_t item, int nrhs) {
+  const double mc2 = double(y.Mc) * y.Mc;
+  return double(y.numel) * item + 3.0 * mc2 * item * nrhs;
+}
+
 double csolve_job_bytes(const CoarseLayout& L, size_t item, int nrhs) {
   const double mc2 = double(L.Mc) * L.Mc;
   return (2.0 * double(L.total()) - mc2) * item + 3.0 * mc2 * item * nrhs;
@@ -572,7 +645,9 @@ template <typename T>
 void timed_coarse_jobs(hz_problem* pr, const CoarseJob<T>* jobs, int njobs, hipStream_t st,
                        const CoarseSolveWork* cw = nullptr) {
   double bytes = 0;
-  for (int i = 0; i < njobs; ++i) bytes += csolve_job_bytes(pr->L, sizeof(V2<T>), jobs[i].nrhs);
+  for (int i = 0; i < njobs; ++i)
+    bytes += pr->sym ? mf_job_bytes(*pr->sym, sizeof(V2<T>), jobs[i].nrhs)
+                     : csolve_job_bytes(pr->L, sizeof(V2<T>), jobs[i].nrhs);
   // a caller-given work set (the allocation-free apply) is never timed: no events are made
   const bool timed = pr->timing && !cw;
   if (!cw) cw = &pr->cw;
@@ -581,8 +656,11 @@ void timed_coarse_jobs(hz_problem* pr, const CoarseJob<T>* jobs, int njobs, hipS
     e = take_events(pr);
     HZ_HIP(hipEventRecord(e.first, st));
   }
-  pr->stats.coarse_solves += coarse_solve_jobs<T>(pr->L, jobs, njobs, pr->Nc, cw->err,
-                                                  cw->persistent, st);
+  if (pr->sym)
+    pr->stats.coarse_solves += mf_solve_jobs<T>(*pr->sym, jobs, njobs, pr->Nc, st);
+  else
+    pr->stats.coarse_solves += coarse_solve_jobs<T>(pr->L, jobs, njobs, pr->Nc, cw->err,
+                                                    cw->persistent, st);
   pr->stats.coarse_bytes += bytes;
   if (timed) {
     HZ_HIP(hipEventRecord(e.second, st));
@@ -655,9 +733,11 @@ void vcycle_group(hz_problem* const* probs, const int* zp, int nb, const DevOp<T
       j.S = factor_of<T>(pi);
       j.coef = coarse_coef_of<T>(pi);
       j.pn = pi->cells;
+      j.mf = pi->dmf;
+      j.ustride = pr0->G;
       j.b = sc.rc + b0 * Nc;
       j.y = sc.ec + b0 * Nc;
-      j.gbuf = gb + b0 * Nc;
+      j.gbuf = gb + b0 * pr0->G;
       j.nrhs = b1 - b0;
       jobs.push_back(j);
       b0 = b1;
@@ -698,6 +778,8 @@ void timed_coarse_solve(hz_problem* pr, const Level<T>& lv, const V2<T>* b, V2<T
   j.S = lv.S;
   j.coef = lv.coarse.coef;
   j.pn = lv.coarse.pn;
+  j.mf = pr->dmf;
+  j.ustride = pr->G;
   j.b = b;
   j.y = y;
   j.gbuf = reinterpret_cast<V2<T>*>(lv.cw.g);
@@ -1257,7 +1339,7 @@ hz_status solve_impl(hz_problem* pr, const double2* F, double2* u, const hz_opti
   }
   if (!pr->ws1 || pr->ws1->prec != o.prec) {
     pr->ws1.reset();
-    pr->ws1 = make_workspace(1, pr->m, o.prec, pr->N, pr->Nc, 0, false);
+    pr->ws1 = make_workspace(1, pr->m, o.prec, pr->N, pr->Nc, pr->G, 0, false);
     pr->ws1->s64 = pr->s64;
     pr->ws1->s32 = pr->s32;
     pr->ws1->gb = pr->cw.g;
@@ -1400,11 +1482,11 @@ struct Carver {
     return p;
   }
 };
-ApplyBufs noalloc_carve(char* base, long N, long Nc, int prec, size_t* used) {
+ApplyBufs noalloc_carve(char* base, long N, long Nc, long G, int prec, size_t* used) {
   Carver c{base};
   ApplyBufs b;
   b.cw.err = c.take<int>(64);
-  b.cw.g = c.take<double2>(size_t(Nc));
+  b.cw.g = c.take<double2>(size_t(G));
   if (prec == HZ_FP64) {
     b.s64.cap = 1;
     b.s64.ua = c.take<double2>(N);
@@ -1429,13 +1511,13 @@ ApplyBufs noalloc_carve(char* base, long N, long Nc, int prec, size_t* used) {
   if (used) *used = c.off;
   return b;
 }
-size_t noalloc_bytes(long N, long Nc, int prec) {
+size_t noalloc_bytes(long N, long Nc, long G, int prec) {
   size_t used = 0;
-  (void)noalloc_carve(nullptr, N, Nc, prec, &used);
+  (void)noalloc_carve(nullptr, N, Nc, G, prec, &used);
   return used;
 }
-ApplyBufs noalloc_layout(char* base, long N, long Nc, int prec) {
-  return noalloc_carve(base, N, Nc, prec, nullptr);
+ApplyBufs noalloc_layout(char* base, long N, long Nc, long G, int prec) {
+  return noalloc_carve(base, N, Nc, G, prec, nullptr);
 }
 
 }  // namespace
@@ -1552,15 +1634,18 @@ hz_status finish_create(hz_problem* pr, hipStream_t st, clk::time_point t0, hz_p
   const hz_options& opt = pr->opt;
   try {
     // coarse factor (FP64), then the FP32 copy for mixed-precision problems
-    pr->S = opt.prec == HZ_MIXED ? pr->mem.alloc_async<double2>(pr->L.total(), st)
-                                 : pr->mem.alloc<double2>(pr->L.total());
     {
-      CoarseFactorWork wk;
-      const size_t mb = size_t(pr->L.size(0));
-      wk.T = pr->mem.alloc_async<double2>(2 * mb * mb, st);     // one set per chain
-      wk.W = pr->mem.alloc_async<double2>(2 * sweep_panel_elems(mb), st);
-      wk.R = pr->mem.alloc_async<double2>(2 * sweep_pinv_elems(), st);
-      wk.flag = pr->mem.alloc_async<int>(1, st);
+      const Sizes z = sizes_of(pr->n, pr->p);
+      pr->G = z.G;
+      pr->fel = z.factor_elems;
+    }
+    if (use_mf()) {
+      pr->sym = &mf_symbolic(pr->p, pr->n / 2);
+      upload_symbolic(pr, st);
+    }
+    pr->S = opt.prec == HZ_MIXED ? pr->mem.alloc_async<double2>(pr->fel, st)
+                                 : pr->mem.alloc<double2>(pr->fel);
+    {
       DevOp<double> cop{pr->cAc, nullptr, pr->Mc};
       cop.pn = pr->cells;
       pr->timing = opt.timing != 0;
@@ -1570,7 +1655,24 @@ hz_status finish_create(hz_problem* pr, hipStream_t st, clk::time_point t0, hz_p
         HZ_HIP(hipEventCreate(&f1));
         HZ_HIP(hipEventRecord(f0, st));
       }
-      const hz_status fs = coarse_factor(pr->L, cop, pr->S, wk, st);
+      hz_status fs;
+      if (pr->sym) {
+        int* flag = pr->mem.alloc_async<int>(1, st);
+        fs = mf_factor(*pr->sym, host_view(pr), cop, pr->S, flag, st);
+        pr->mem.release_async(flag, st);
+      } else {
+        CoarseFactorWork wk;
+        const size_t mb = size_t(pr->L.size(0));
+        wk.T = pr->mem.alloc_async<double2>(2 * mb * mb, st);     // one set per chain
+        wk.W = pr->mem.alloc_async<double2>(2 * sweep_panel_elems(mb), st);
+        wk.R = pr->mem.alloc_async<double2>(2 * sweep_pinv_elems(), st);
+        wk.flag = pr->mem.alloc_async<int>(1, st);
+        fs = coarse_factor(pr->L, cop, pr->S, wk, st);
+        pr->mem.release_async(wk.T, st);
+        pr->mem.release_async(wk.W, st);
+        pr->mem.release_async(wk.R, st);
+        pr->mem.release_async(wk.flag, st);
+      }
       if (pr->timing) {
         HZ_HIP(hipEventRecord(f1, st));
         HZ_HIP(hipEventSynchronize(f1));
@@ -1580,16 +1682,12 @@ hz_status finish_create(hz_problem* pr, hipStream_t st, clk::time_point t0, hz_p
         (void)hipEventDestroy(f0);
         (void)hipEventDestroy(f1);
       }
-      pr->mem.release_async(wk.T, st);
-      pr->mem.release_async(wk.W, st);
-      pr->mem.release_async(wk.R, st);
-      pr->mem.release_async(wk.flag, st);
       if (fs != HZ_OK) {
         delete pr;
-        return fail(fs, "zero or non-finite pivot in the coarse block factorisation");
+        return fail(fs, "zero or non-finite pivot in the coarse factorisation");
       }
     }
-    pr->cw.g = pr->mem.alloc<double2>(4 * size_t(pr->Nc));
+    pr->cw.g = pr->mem.alloc<double2>(4 * size_t(pr->G));
     pr->cw.err = pr->mem.alloc<int>(64);
     HZ_HIP(hipMemsetAsync(pr->cw.err, 0, 64 * sizeof(int), st));
     {
@@ -1722,7 +1820,7 @@ hz_status hz_apply_noalloc(const hz_problem* cpr, int op, const hz_c64* d_x, con
   if (prec == HZ_MIXED && !pr->Sf)
     return fail(HZ_EINVAL, "the problem holds no FP32 coarse factor (create it with HZ_MIXED, or "
                            "run one mixed-precision hz_apply or hz_solve first)");
-  const size_t need = noalloc_bytes(pr->N, pr->Nc, prec);
+  const size_t need = noalloc_bytes(pr->N, pr->Nc, pr->G, prec);
   if (need > kScratchBytes)
     return fail(HZ_EINVAL, "the allocation-free apply needs " + std::to_string(need) +
                                " scratch bytes for this problem; its maximum is " +
@@ -1732,7 +1830,7 @@ hz_status hz_apply_noalloc(const hz_problem* cpr, int op, const hz_c64* d_x, con
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   try {
     char* base = noalloc_scratch();
-    ApplyBufs b = noalloc_layout(base, pr->N, pr->Nc, prec);
+    ApplyBufs b = noalloc_layout(base, pr->N, pr->Nc, pr->G, prec);
     b.cw.persistent = pr->cw.persistent;
     b.own = false;
     // the coarse solve's timeout flag must start at zero (the array keeps the last call's
@@ -1791,7 +1889,7 @@ hz_status hz_solve_batched(hz_problem* const* probs, int nprob, const hz_c64* co
       if (opt.prec == HZ_MIXED) ensure_mixed_work(probs[i], st);
     const long N = pr0->N;
     std::unique_ptr<Workspace> ws =
-        make_workspace(int(nsol), opt.restart, opt.prec, N, pr0->Nc, int(nsol), true);
+        make_workspace(int(nsol), opt.restart, opt.prec, N, pr0->Nc, pr0->G, int(nsol), true);
     std::vector<long> off(nsol);
     for (long q = 0; q < nsol; ++q) {
       off[q] = q * N;
@@ -1821,7 +1919,7 @@ size_t hz_batch_workspace_bytes(double h, int p, int nprob, int nrhs_per_prob, c
   const Sizes z = sizes_of(n, p);
   const int nsol = nprob * nrhs_per_prob;
   return workspace_bytes(z.N, z.nblk, nsol, oo.restart, oo.prec, true) +
-         scratch_bytes(z.N, z.Nc, nsol, oo.prec);
+         scratch_bytes(z.N, z.Nc, z.G, nsol, oo.prec);
 }
 
 hz_status hz_problem_stats(hz_problem* pr, hz_stats* out, int reset) {
@@ -1904,7 +2002,7 @@ struct ClassState {
 
 size_t slot_bytes(int n, int p, int m, int prec) {
   const Sizes z = sizes_of(n, p);
-  return workspace_bytes(z.N, z.nblk, 1, m, prec, true) + scratch_bytes(z.N, z.Nc, 1, prec);
+  return workspace_bytes(z.N, z.nblk, 1, m, prec, true) + scratch_bytes(z.N, z.Nc, z.G, 1, prec);
 }
 
 // Slots per pool: as many solves of the class as fit in about 8 GB of workspace (and a
@@ -1919,7 +2017,8 @@ size_t request_bytes(int n, int p, int prec, size_t* setup) {
   const Sizes z = sizes_of(n, p);
   // factor, stencil tables, the problem's own one-solve V-cycle scratch and sweep buffer
   const size_t steady = z.factor_elems * (prec == HZ_MIXED ? 8 : 16) +
-                        scratch_bytes(z.N, z.Nc, 1, prec) + 4 * size_t(z.Nc) * 16 + 256 * 1024;
+                        scratch_bytes(z.N, z.Nc, z.G, 1, prec) + 4 * size_t(z.G) * 16 +
+                        z.sym_bytes + 256 * 1024;
   // a mixed problem holds the FP64 factor and its FP32 copy while it is set up
   *setup = steady + (prec == HZ_MIXED ? z.factor_elems * 16 : 0);
   return steady;
@@ -2118,7 +2217,7 @@ void engine_join(hz_engine* e, EngineRequest* r, hipStream_t st) {
     np->cap = cap;
     np->bytes = size_t(cap) * slot_bytes(r->n, r->p, e->opt.restart, e->opt.prec);
     const hz_problem* pr = r->pr;
-    np->ws = make_workspace(cap, e->opt.restart, e->opt.prec, pr->N, pr->Nc, cap, true);
+    np->ws = make_workspace(cap, e->opt.restart, e->opt.prec, pr->N, pr->Nc, pr->G, cap, true);
     np->probs.assign(cap, nullptr);
     np->member.assign(cap, nullptr);
     np->off.resize(cap);

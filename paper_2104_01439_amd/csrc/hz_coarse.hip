@@ -1323,23 +1323,9 @@ int csolve_jobs_p(const CoarseLayout& L, const CoarseJob<T>* jobs, int njobs, lo
 size_t sweep_panel_elems(size_t nmax) { return 2 * size_t(SB) * ((nmax + SB - 1) / SB) * SB; }
 size_t sweep_pinv_elems() { return 2 * size_t(SB) * SB; }
 
-namespace {
-
-template <int P>
-void factor_block(const CoarseLayout& L, const DevOp<double>& cop, double2* S, int j, int jn1,
-                  int jn2, double2* T, double2* W, double2* R, int* flag, hipStream_t st) {
-  const int n = int(L.size(j));
-  double2* D = S + L.off(j);
-  const dim3 g2((n + 255) / 256, n);
-  k_schur_left<P><<<g2, 256, 0, st>>>(j, -1, L.nc, L.Mc, cop.coef, cop.pn, T, n, D);
-  for (int jn : {jn1, jn2}) {
-    if (jn < 0) continue;
-    const int nn = int(L.size(jn));
-    k_schur_right<P><<<dim3((n + 255) / 256, nn), 256, 0, st>>>(j, jn, L.nc, L.Mc, cop.coef,
-                                                                cop.pn, S + L.off(jn), nn, n, T);
-    k_schur_left<P><<<g2, 256, 0, st>>>(j, jn, L.nc, L.Mc, cop.coef, cop.pn, T, n, D);
-  }
-  // symmetric sweep: first panel and pivot inverse, one launch per pivot tile, final mirror
+// Symmetric sweep of one block: first panel and pivot inverse, one launch per pivot tile,
+// final mirror.
+void sweep_inverse(double2* D, int n, double2* W, double2* R, int* flag, hipStream_t st) {
   const int nt = (n + SB - 1) / SB;
   const size_t ld = size_t(nt) * SB;
   SweepPass a;
@@ -1363,6 +1349,25 @@ void factor_block(const CoarseLayout& L, const DevOp<double>& cop, double2* S, i
     k_sweep_pass<<<1 + (nu + 3) / 4, 256, 0, st>>>(a);
   }
   k_sweep_last<<<nu, 256, 0, st>>>(D, n, nt);
+}
+
+namespace {
+
+template <int P>
+void factor_block(const CoarseLayout& L, const DevOp<double>& cop, double2* S, int j, int jn1,
+                  int jn2, double2* T, double2* W, double2* R, int* flag, hipStream_t st) {
+  const int n = int(L.size(j));
+  double2* D = S + L.off(j);
+  const dim3 g2((n + 255) / 256, n);
+  k_schur_left<P><<<g2, 256, 0, st>>>(j, -1, L.nc, L.Mc, cop.coef, cop.pn, T, n, D);
+  for (int jn : {jn1, jn2}) {
+    if (jn < 0) continue;
+    const int nn = int(L.size(jn));
+    k_schur_right<P><<<dim3((n + 255) / 256, nn), 256, 0, st>>>(j, jn, L.nc, L.Mc, cop.coef,
+                                                                cop.pn, S + L.off(jn), nn, n, T);
+    k_schur_left<P><<<g2, 256, 0, st>>>(j, jn, L.nc, L.Mc, cop.coef, cop.pn, T, n, D);
+  }
+  sweep_inverse(D, n, W, R, flag, st);
 }
 
 template <int P>

@@ -189,6 +189,57 @@ struct CoarseSolveWork {
 // table, nrhs right-hand sides at b + h cstride, solutions at y + h cstride and a forward-sweep
 // buffer at gbuf + h Nc (distinct per job). Up to kMaxJobs jobs of one mesh class share one
 // launch, each on its own set of workgroups; jobs are passed by value (kernel arguments).
+// ------------------------------------------------------------------------------------------
+// Multifrontal coarse factor (nested dissection of the coarse lattice)
+// ------------------------------------------------------------------------------------------
+//
+// The coarse lattice is cut recursively by lattice lines at cell boundaries (points on both
+// sides of such a line share no element, so the line separates them) until a region holds at
+// most kMfLeaf points. Tree node v owns the points I_v (its separator line, or all points of a
+// leaf region) and sees B_v, the points of ancestors' separators on the ring around its
+// region. With F_v the frontal matrix on I_v + B_v (the rows of A_c at I_v plus the children's
+// update matrices), the factor stores S_v = F_II^{-1}, G_v = S_v F_IB (s x m) and its transpose,
+// and passes U_v = F_BB - F_BI G_v to the parent.
+constexpr int kMfLeaf = 16;
+struct MfNode {
+  int s = 0, m = 0;            // |I_v|, |B_v|
+  int ch0 = -1, ch1 = -1;      // children
+  long Ioff = 0, Boff = 0;     // points of I_v in I[], of B_v in B[]
+  long Soff = 0, Goff = 0, GToff = 0;   // S (s x s), G (s x m), G^T (m x s) in the factor
+  long uoff = 0;               // update vector (m) in the per-right-hand-side work
+  long mapoff = -1;            // front positions in the parent of this node's B points
+};
+// One unit of a solve pass at one tree height: rows [r0, r1) of matrix `kind` of node v
+// (kind 0: S, 1: G^T for the forward pass; 2: G for the backward pass), or, for kinds 3
+// (forward) and 4 (backward), the whole small nodes hn[r0 .. r1) (one wave per node).
+struct MfTask {
+  int v, kind, r0, r1;
+};
+struct MfSym {
+  int p = 1, nc = 0, Mc = 0, H = 0;
+  std::vector<MfNode> nodes;              // postorder: children before their parent
+  std::vector<int> parent, height;
+  std::vector<int> I, B, map;
+  long numel = 0, uel = 0;                // factor elements, update elements per right-hand side
+  std::vector<std::vector<int>> at;       // nodes of each height
+  std::vector<int> hn;                    // the same, concatenated by height
+  std::vector<MfTask> fwd, bwd;           // solve tasks, grouped by height
+  std::vector<int> fwd0, bwd0;            // first task of each height (H + 2 entries)
+  int maxf = 0;                           // largest s + m
+};
+// The (cached) symbolic factor of the coarse lattice of order p with nc cells per side.
+const MfSym& mf_symbolic(int p, int nc);
+// Device copy of the symbolic data one problem uses.
+struct MfView {
+  const MfNode* nodes = nullptr;
+  const int* I = nullptr;
+  const int* B = nullptr;
+  const int* map = nullptr;
+  const MfTask* fwd = nullptr;
+  const MfTask* bwd = nullptr;
+  const int* hn = nullptr;
+};
+
 template <typename T> struct CoarseJob {
   const V2<T>* S = nullptr;
   const V2<T>* coef = nullptr;
@@ -197,6 +248,9 @@ template <typename T> struct CoarseJob {
   V2<T>* gbuf = nullptr;
   int nrhs = 1;
   int pn = 0;              // coef holds one stencil per coarse point (as DevOp::pn)
+  const MfView* mf = nullptr;   // multifrontal factor: S is its numeric array, gbuf the
+                                // update vectors (uel per right-hand side, stride ustride)
+  long ustride = 0;
 };
 constexpr int kMaxJobs = 16;
 template <typename T> struct CsJobs {
@@ -214,6 +268,19 @@ template <typename T>
 int coarse_solve(const CoarseLayout& L, const DevOp<T>& cop, const V2<T>* S, const V2<T>* b,
                  V2<T>* y, int nrhs, long cstride, const CoarseSolveWork& w, hipStream_t st);
 void launch_factor_to_f32(const double2* S, float2* Sf, size_t n, hipStream_t st);
+// In-place inverse of a complex symmetric n x n row-major block by the symmetric Gauss-Jordan
+// sweep (W: 2 sweep_panel_elems(n), R: 2 sweep_pinv_elems() elements of work); sets *flag on a
+// zero or non-finite pivot.
+void sweep_inverse(double2* X, int n, double2* W, double2* R, int* flag, hipStream_t st);
+// Multifrontal factorisation of the coarse operator cop into F (sym.numel elements) on the
+// device; returns HZ_OK or HZ_ESINGULAR.
+hz_status mf_factor(const MfSym& sym, const MfView& dv, const DevOp<double>& cop, double2* F,
+                    int* flag, hipStream_t st);
+// Multifrontal solves of njobs jobs (one mesh class; b, y coarse vectors with stride cstride
+// per right-hand side, update vectors at gbuf with stride ustride). Returns the launch count.
+template <typename T>
+int mf_solve_jobs(const MfSym& sym, const CoarseJob<T>* jobs, int njobs, long cstride,
+                  hipStream_t st);
 // Creates the per-device event that orders persistent coarse-solve launches (otherwise made
 // by the first such launch on the device).
 void coarse_order_init(int dev);

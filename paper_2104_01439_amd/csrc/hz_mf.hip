@@ -1,0 +1,874 @@
+// Multifrontal direct solve of the coarse operator (the coarsest level of Sec. 4,
+// Algorithm 1, factored once and reused as Sec. 6 does with its multifrontal LU).
+//
+// Nested dissection of the coarse lattice: a region is cut by a lattice line at a cell
+// boundary (multiple of p) across its longer side; points on the two sides of such a line
+// never share an element, so the line separates the region. Regions of at most kMfLeaf
+// points are leaves. Node v owns the points I_v of its line (or of its leaf region) and
+// couples to B_v, the ancestors' line points on the ring around its region.
+//
+// Factorisation, bottom-up by tree height: the front F_v on I_v + B_v holds the rows of A_c at
+// I_v (and their transposes) plus the children's update matrices (extend-add); then
+//   S_v = F_II^{-1},  G_v = S_v F_IB,  G_v^T,  U_v = F_BB - F_BI G_v  (passed to the parent).
+// Solve: forward (heights ascending) f = [b_I; 0] + children's u, z_I = S_v f_I,
+// u_v = f_B - G_v^T f_I; backward (heights descending) x_I = z_I - G_v x_B.
+// The factor is explicit (inverses and products), so each pass is a set of independent
+// matrix-vector products per height: 2 H + 1 dependent launches per solve.
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <unordered_map>
+
+#include "hz_common.h"
+
+namespace hz {
+
+// ------------------------------------------------------------------------------------------
+// Symbolic analysis (host)
+// ------------------------------------------------------------------------------------------
+
+namespace {
+
+struct Builder {
+  int p, Mc;
+  MfSym* S;
+  std::vector<std::vector<int>> Ipts, Bpts;
+  std::vector<std::pair<int, int>> ch;
+
+  int cut(int lo, int hi) const {   // cell line strictly inside (lo, hi) nearest the middle
+    const double mid = 0.5 * (lo + hi);
+    int best = -1;
+    for (int c = lo + 1; c < hi; ++c)
+      if (c % p == 0 && (best < 0 || std::abs(c - mid) < std::abs(best - mid))) best = c;
+    return best;
+  }
+
+  std::vector<int> ring(int a0, int a1, int b0, int b1) const {
+    std::vector<int> r;
+    for (int b = b0 - 1; b <= b1 + 1; ++b)
+      for (int a = a0 - 1; a <= a1 + 1; ++a) {
+        if (a >= a0 && a <= a1 && b >= b0 && b <= b1) continue;
+        if (a < 0 || a >= Mc || b < 0 || b >= Mc) continue;
+        r.push_back(b * Mc + a);
+      }
+    return r;
+  }
+
+  int add(std::vector<int>&& I, std::vector<int>&& B, int c0, int c1, int h) {
+    Ipts.push_back(std::move(I));
+    Bpts.push_back(std::move(B));
+    ch.push_back({c0, c1});
+    S->height.push_back(h);
+    return int(Ipts.size()) - 1;
+  }
+
+  int rec(int a0, int a1, int b0, int b1) {
+    const int w = a1 - a0 + 1, hgt = b1 - b0 + 1;
+    int c = -1;
+    bool vert = true;
+    if (w * hgt > kMfLeaf) {
+      if (w >= hgt) {
+        c = cut(a0, a1);
+        if (c < 0) { c = cut(b0, b1); vert = false; }
+      } else {
+        c = cut(b0, b1);
+        vert = false;
+        if (c < 0) { c = cut(a0, a1); vert = true; }
+      }
+    }
+    if (c < 0) {
+      std::vector<int> I;
+      for (int b = b0; b <= b1; ++b)
+        for (int a = a0; a <= a1; ++a) I.push_back(b * Mc + a);
+      return add(std::move(I), ring(a0, a1, b0, b1), -1, -1, 0);
+    }
+    int k1, k2;
+    std::vector<int> I;
+    if (vert) {
+      k1 = rec(a0, c - 1, b0, b1);
+      k2 = rec(c + 1, a1, b0, b1);
+      for (int b = b0; b <= b1; ++b) I.push_back(b * Mc + c);
+    } else {
+      k1 = rec(a0, a1, b0, c - 1);
+      k2 = rec(a0, a1, c + 1, b1);
+      for (int a = a0; a <= a1; ++a) I.push_back(c * Mc + a);
+    }
+    const int h = 1 + std::max(S->height[k1], S->height[k2]);
+    return add(std::move(I), ring(a0, a1, b0, b1), k1, k2, h);
+  }
+};
+
+// rows of one solve task: about 4 rows per wave of a 256-thread workgroup
+constexpr int kMfRows = 4;
+
+void build_symbolic(MfSym& S, int p, int nc) {
+  S.p = p;
+  S.nc = nc;
+  S.Mc = p * nc + 1;
+  Builder b{p, S.Mc, &S, {}, {}, {}};
+  const int root = b.rec(0, S.Mc - 1, 0, S.Mc - 1);
+  const int nn = int(b.Ipts.size());
+  if (root != nn - 1) throw std::runtime_error("multifrontal: root is not last");
+  S.nodes.assign(nn, MfNode());
+  S.parent.assign(nn, -1);
+  S.H = S.height[root];
+  long Io = 0, Bo = 0, F = 0, U = 0;
+  for (int v = 0; v < nn; ++v) {
+    MfNode& nd = S.nodes[v];
+    nd.s = int(b.Ipts[v].size());
+    nd.m = int(b.Bpts[v].size());
+    nd.ch0 = b.ch[v].first;
+    nd.ch1 = b.ch[v].second;
+    if (nd.ch0 >= 0) S.parent[nd.ch0] = v;
+    if (nd.ch1 >= 0) S.parent[nd.ch1] = v;
+    nd.Ioff = Io;
+    nd.Boff = Bo;
+    Io += nd.s;
+    Bo += nd.m;
+    nd.Soff = F;
+    F += long(nd.s) * nd.s;
+    nd.Goff = F;
+    F += long(nd.s) * nd.m;
+    nd.GToff = F;
+    F += long(nd.s) * nd.m;
+    nd.uoff = U;
+    U += nd.m;
+    S.maxf = std::max(S.maxf, nd.s + nd.m);
+    S.I.insert(S.I.end(), b.Ipts[v].begin(), b.Ipts[v].end());
+    S.B.insert(S.B.end(), b.Bpts[v].begin(), b.Bpts[v].end());
+  }
+  S.numel = F;
+  S.uel = U;
+  if (Io != long(S.Mc) * S.Mc) throw std::runtime_error("multifrontal: points not partitioned");
+  // front positions of each child's B points in its parent
+  for (int v = 0; v < nn; ++v) {
+    const MfNode& nd = S.nodes[v];
+    if (nd.ch0 < 0) continue;
+    std::unordered_map<int, int> pos;
+    pos.reserve(size_t(nd.s + nd.m) * 2);
+    for (int i = 0; i < nd.s; ++i) pos[b.Ipts[v][i]] = i;
+    for (int k = 0; k < nd.m; ++k) pos[b.Bpts[v][k]] = nd.s + k;
+    for (int c : {nd.ch0, nd.ch1}) {
+      MfNode& cn = S.nodes[c];
+      cn.mapoff = long(S.map.size());
+      for (int g : b.Bpts[c]) {
+        auto it = pos.find(g);
+        if (it == pos.end()) throw std::runtime_error("multifrontal: ring point not in parent front");
+        S.map.push_back(it->second);
+      }
+    }
+  }
+  // nodes by height (also flat, for the small-node tasks), solve tasks by height
+  S.at.assign(S.H + 1, {});
+  for (int v = 0; v < nn; ++v) S.at[S.height[v]].push_back(v);
+  auto is_small = [&](int v) { return S.nodes[v].s + S.nodes[v].m <= 64; };
+  for (int h = 0; h <= S.H; ++h) {   // small nodes first within a height
+    std::stable_partition(S.at[h].begin(), S.at[h].end(), is_small);
+    S.hn.insert(S.hn.end(), S.at[h].begin(), S.at[h].end());
+  }
+  S.fwd0.assign(S.H + 2, 0);
+  S.bwd0.assign(S.H + 2, 0);
+  int hbase = 0;
+  for (int h = 0; h <= S.H; ++h) {
+    S.fwd0[h] = int(S.fwd.size());
+    S.bwd0[h] = int(S.bwd.size());
+    std::vector<int> small;   // positions in hn
+    for (size_t q = 0; q < S.at[h].size(); ++q) {
+      const int v = S.at[h][q];
+      const MfNode& nd = S.nodes[v];
+      if (is_small(v)) {
+        small.push_back(hbase + int(q));
+        continue;
+      }
+      for (int r = 0; r < nd.s; r += kMfRows) S.fwd.push_back({v, 0, r, std::min(nd.s, r + kMfRows)});
+      for (int r = 0; r < nd.m; r += kMfRows) S.fwd.push_back({v, 1, r, std::min(nd.m, r + kMfRows)});
+      if (nd.m > 0)
+        for (int r = 0; r < nd.s; r += kMfRows) S.bwd.push_back({v, 2, r, std::min(nd.s, r + kMfRows)});
+    }
+    // small nodes (s + m <= 64): one wave each, four to a workgroup; r0 .. r1 is a range of
+    // consecutive positions in hn (the small nodes of a height are consecutive there)
+    for (size_t i = 0; i < small.size(); i += 4) {
+      const int n4 = int(std::min<size_t>(4, small.size() - i));
+      if (small[i + n4 - 1] - small[i] != n4 - 1) throw std::runtime_error("multifrontal: task");
+      S.fwd.push_back({-1, 3, small[i], small[i] + n4});
+      S.bwd.push_back({-1, 4, small[i], small[i] + n4});
+    }
+    hbase += int(S.at[h].size());
+  }
+  S.fwd0[S.H + 1] = int(S.fwd.size());
+  S.bwd0[S.H + 1] = int(S.bwd.size());
+}
+
+std::mutex g_sym_mu;
+std::map<std::pair<int, int>, std::unique_ptr<MfSym>> g_sym;
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// Factorisation kernels
+// ------------------------------------------------------------------------------------------
+
+namespace {
+
+__device__ __forceinline__ int mf_region(int a, int M) { return a == 0 ? 0 : (a == M - 1 ? 2 : 1); }
+
+// A_c(g1, g2): the stencil of g1 at offset g2 - g1 (class tables or per-point), zero beyond it.
+template <int P>
+__device__ __forceinline__ double2 coarse_entry(const double2* __restrict__ coef, int pn, int Mc,
+                                                int g1, int g2) {
+  constexpr int W = 2 * P + 1, W2 = W * W;
+  const int b1 = g1 / Mc, a1 = g1 - b1 * Mc, b2 = g2 / Mc, a2 = g2 - b2 * Mc;
+  const int dx = a2 - a1, dy = b2 - b1;
+  if (dx < -P || dx > P || dy < -P || dy > P) return make_double2(0.0, 0.0);
+  const int d = (dy + P) * W + dx + P;
+  if (pn) return coef[long(d) * Mc * Mc + g1];
+  const int cls = (b1 % P) * P + (a1 % P);
+  const int reg = mf_region(b1, Mc) * 3 + mf_region(a1, Mc);
+  return coef[(cls * 9 + reg) * W2 + d];
+}
+
+// Row r of the front of node v: F[r][c] = A_c(I/B point r, I/B point c) when r or c is in I
+// (the row of the point in I, so that F_BI = F_IB^T exactly), zero in the F_BB part.
+template <int P>
+__global__ void __launch_bounds__(256)
+k_mf_front(MfView mv, const double2* __restrict__ coef, int pn, int Mc, const int2* __restrict__ rows,
+           double2* const* __restrict__ fptr) {
+  const int2 t = rows[blockIdx.x];
+  const MfNode nd = mv.nodes[t.x];
+  const int s = nd.s, w = nd.s + nd.m, r = t.y;
+  double2* Fr = fptr[t.x] + long(r) * w;
+  const int gr = r < s ? mv.I[nd.Ioff + r] : mv.B[nd.Boff + r - s];
+  for (int c = threadIdx.x; c < w; c += 256) {
+    double2 v = make_double2(0.0, 0.0);
+    if (r < s || c < s) {
+      const int gc = c < s ? mv.I[nd.Ioff + c] : mv.B[nd.Boff + c - s];
+      v = r < s ? coarse_entry<P>(coef, pn, Mc, gr, gc) : coarse_entry<P>(coef, pn, Mc, gc, gr);
+    }
+    Fr[c] = v;
+  }
+}
+
+// Extend-add of row j of child c's update matrix U_c = F_c[s_c:, s_c:] into its parent's front.
+// One child slot per launch (the two children of a node may hit the same entries).
+__global__ void __launch_bounds__(256)
+k_mf_extend(MfView mv, const int* __restrict__ parent, const int2* __restrict__ rows,
+            double2* const* __restrict__ fptr) {
+  const int2 t = rows[blockIdx.x];
+  const int c = t.x, j = t.y, v = parent[c];
+  const MfNode cn = mv.nodes[c], pnd = mv.nodes[v];
+  const int wc = cn.s + cn.m, wp = pnd.s + pnd.m;
+  const double2* U = fptr[c] + long(cn.s + j) * wc + cn.s;
+  const int* map = mv.map + cn.mapoff;
+  double2* Fp = fptr[v] + long(map[j]) * wp;
+  for (int k = threadIdx.x; k < cn.m; k += 256) {
+    const double2 u = U[k];
+    double2 f = Fp[map[k]];
+    f.x += u.x;
+    f.y += u.y;
+    Fp[map[k]] = f;
+  }
+}
+
+// S_v = F_II^{-1} for s <= 64, one workgroup per node: the symmetric Gauss-Jordan sweep in LDS
+// on the upper triangle mirrored (every pivot X[t][t] -> -1/p, row and column t scaled by 1/p,
+// the rest X[r][c] -= X[r][t] X[t][c] / p), leaving -F_II^{-1}.
+__global__ void __launch_bounds__(256)
+k_mf_gj(MfView mv, const int* __restrict__ list, double2* const* __restrict__ fptr,
+        double2* __restrict__ Fac, int* flag) {
+  extern __shared__ double2 X[];
+  __shared__ double2 rowt[64], colt[64];
+  const int v = list[blockIdx.x];
+  const MfNode nd = mv.nodes[v];
+  const int s = nd.s, w = nd.s + nd.m, ld = s + 1;
+  const double2* Fv = fptr[v];
+  for (int idx = threadIdx.x; idx < s * s; idx += 256) {
+    const int r = idx / s, c = idx - r * s;
+    X[r * ld + c] = Fv[long(min(r, c)) * w + max(r, c)];
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int t = 0; t < s; ++t) {
+    const double2 pv = X[t * ld + t];
+    const double mag = pv.x * pv.x + pv.y * pv.y;
+    if (!(mag > 0.0) || !isfinite(mag)) bad = true;
+    const double2 pinv = make_double2(pv.x / mag, -pv.y / mag);
+    for (int i = threadIdx.x; i < s; i += 256) {
+      rowt[i] = X[t * ld + i];
+      colt[i] = X[i * ld + t];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < s * s; idx += 256) {
+      const int r = idx / s, c = idx - r * s;
+      double2 v;
+      if (r == t) {
+        v = (c == t) ? make_double2(-pinv.x, -pinv.y) : cmul<double>(rowt[c], pinv);
+      } else if (c == t) {
+        v = cmul<double>(colt[r], pinv);
+      } else {
+        const double2 g = cmul<double>(colt[r], pinv);
+        v = X[r * ld + c];
+        v.x -= g.x * rowt[c].x - g.y * rowt[c].y;
+        v.y -= g.x * rowt[c].y + g.y * rowt[c].x;
+      }
+      X[r * ld + c] = v;
+    }
+    __syncthreads();
+  }
+  if (bad && threadIdx.x == 0) atomicOr(flag, 1);
+  double2* Sv = Fac + nd.Soff;
+  for (int idx = threadIdx.x; idx < s * s; idx += 256) {
+    const int r = idx / s, c = idx - r * s;
+    const double2 x = X[min(r, c) * ld + max(r, c)];
+    Sv[idx] = make_double2(-x.x, -x.y);
+  }
+}
+
+// F_II of a large node into its S slot (row-major s x s), for the in-place sweep inverse.
+__global__ void __launch_bounds__(256)
+k_mf_copy_ii(const double2* __restrict__ Fv, int s, int w, double2* __restrict__ Sv) {
+  const long idx = long(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= long(s) * s) return;
+  const int r = int(idx / s), c = int(idx - long(r) * s);
+  Sv[idx] = Fv[long(r) * w + c];
+}
+
+// Batched complex GEMM of varying sizes: C = A B (sub = 0) or C -= A B (sub = 1), all row-major.
+// 64 x 64 output tiles, 256 threads in a 16 x 16 grid with 4 x 4 outputs each, k in steps of 8
+// staged in LDS; each output sums its k terms in ascending order.
+struct GemmDesc {
+  const double2* A;
+  const double2* B;
+  double2* C;
+  int lda, ldb, ldc, M, N, K, sub;
+  long tile0;
+};
+
+__global__ void __launch_bounds__(256)
+k_mf_gemm(const GemmDesc* __restrict__ descs, const int* __restrict__ tdesc) {
+  __shared__ double2 As[8][65], Bs[8][65];
+  const GemmDesc g = descs[tdesc[blockIdx.x]];
+  const long t = long(blockIdx.x) - g.tile0;
+  const int tn = (g.N + 63) / 64;
+  const int row0 = int(t / tn) * 64, col0 = int(t % tn) * 64;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double2 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+  for (int k0 = 0; k0 < g.K; k0 += 8) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = threadIdx.x + 256 * q;
+      const int ra = idx >> 3, ka = idx & 7;
+      As[ka][ra] = (row0 + ra < g.M && k0 + ka < g.K) ? g.A[long(row0 + ra) * g.lda + k0 + ka]
+                                                     : make_double2(0.0, 0.0);
+      const int kb = idx >> 6, cb = idx & 63;
+      Bs[kb][cb] = (k0 + kb < g.K && col0 + cb < g.N) ? g.B[long(k0 + kb) * g.ldb + col0 + cb]
+                                                     : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      double2 a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[k][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cfma(acc[i][j], a[i], b[j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = row0 + ty + 16 * i, c = col0 + tx + 16 * j;
+      if (r >= g.M || c >= g.N) continue;
+      double2* cp = g.C + long(r) * g.ldc + c;
+      if (g.sub) {
+        double2 v = *cp;
+        v.x -= acc[i][j].x;
+        v.y -= acc[i][j].y;
+        *cp = v;
+      } else {
+        *cp = acc[i][j];
+      }
+    }
+}
+
+template <int P>
+void launch_front(const MfView& mv, const DevOp<double>& cop, int Mc, const int2* rows, int nrows,
+                  double2* const* fptr, hipStream_t st) {
+  k_mf_front<P><<<nrows, 256, 0, st>>>(mv, cop.coef, cop.pn, Mc, rows, fptr);
+}
+
+}  // namespace
+
+hz_status mf_factor(const MfSym& sym, const MfView& mv, const DevOp<double>& cop, double2* Fac,
+                    int* flag, hipStream_t st) {
+  const int nn = int(sym.nodes.size());
+  // front arena: the fronts of height h live until their parents (at heights up to
+  // last[h]) have taken their update matrices; first fit over the heights' intervals
+  std::vector<int> last(sym.H + 1, 0);
+  for (int v = 0; v < nn; ++v)
+    if (sym.parent[v] >= 0)
+      last[sym.height[v]] = std::max(last[sym.height[v]], sym.height[sym.parent[v]]);
+  std::vector<long> hsize(sym.H + 1, 0), hoff(sym.H + 1, 0);
+  for (int h = 0; h <= sym.H; ++h)
+    for (int v : sym.at[h]) hsize[h] += long(sym.nodes[v].s + sym.nodes[v].m) * (sym.nodes[v].s + sym.nodes[v].m);
+  std::vector<std::pair<long, long>> live;   // (offset, size) of live heights' blocks
+  std::vector<int> live_h;
+  long arena = 0;
+  for (int h = 0; h <= sym.H; ++h) {
+    for (size_t i = 0; i < live.size();) {     // heights whose parents all precede h
+      if (last[live_h[i]] < h) { live.erase(live.begin() + i); live_h.erase(live_h.begin() + i); }
+      else ++i;
+    }
+    std::vector<std::pair<long, long>> sorted = live;
+    std::sort(sorted.begin(), sorted.end());
+    long off = 0;
+    for (auto& b : sorted) {
+      if (b.first - off >= hsize[h]) break;
+      off = std::max(off, b.first + b.second);
+    }
+    hoff[h] = off;
+    arena = std::max(arena, off + hsize[h]);
+    live.push_back({off, hsize[h]});
+    live_h.push_back(h);
+  }
+  double2* ws = nullptr;
+  HZ_HIP(hipMallocAsync(reinterpret_cast<void**>(&ws), size_t(std::max<long>(arena, 1)) * 16, st));
+  std::vector<double2*> fp(nn, nullptr);
+  for (int h = 0; h <= sym.H; ++h) {
+    long o = hoff[h];
+    for (int v : sym.at[h]) {
+      fp[v] = ws + o;
+      o += long(sym.nodes[v].s + sym.nodes[v].m) * (sym.nodes[v].s + sym.nodes[v].m);
+    }
+  }
+  // host-built launch tables, uploaded once: front rows, extend-add rows per child slot,
+  // small inversions, GEMM descriptors and tile maps, per height
+  std::vector<int2> rows, ext;
+  std::vector<int> gj, parent(sym.parent.begin(), sym.parent.end());
+  std::vector<GemmDesc> gd;
+  std::vector<int> td;
+  struct HL { size_t r0, r1, e0[2], e1[2], g0, g1; size_t d0[2], d1[2], t0[2], t1[2]; };
+  std::vector<HL> hl(sym.H + 1);
+  size_t maxbig = 0;
+  for (int h = 0; h <= sym.H; ++h) {
+    HL& L = hl[h];
+    L.r0 = rows.size();
+    for (int v : sym.at[h])
+      for (int r = 0; r < sym.nodes[v].s + sym.nodes[v].m; ++r) rows.push_back(make_int2(v, r));
+    L.r1 = rows.size();
+    for (int slot = 0; slot < 2; ++slot) {
+      L.e0[slot] = ext.size();
+      for (int v : sym.at[h]) {
+        const int c = slot == 0 ? sym.nodes[v].ch0 : sym.nodes[v].ch1;
+        if (c < 0) continue;
+        for (int j = 0; j < sym.nodes[c].m; ++j) ext.push_back(make_int2(c, j));
+      }
+      L.e1[slot] = ext.size();
+    }
+    L.g0 = gj.size();
+    for (int v : sym.at[h])
+      if (sym.nodes[v].s <= 64) gj.push_back(v);
+      else maxbig = std::max(maxbig, size_t(sym.nodes[v].s));
+    L.g1 = gj.size();
+    for (int phase = 0; phase < 2; ++phase) {
+      L.d0[phase] = gd.size();
+      L.t0[phase] = td.size();
+      for (int v : sym.at[h]) {
+        const MfNode& nd = sym.nodes[v];
+        if (nd.m == 0) continue;
+        const int s = nd.s, m = nd.m, w = s + m;
+        double2* F = fp[v];
+        std::vector<GemmDesc> add;
+        if (phase == 0) {
+          add.push_back({Fac + nd.Soff, F + s, Fac + nd.Goff, s, w, m, s, m, s, 0, 0});        // G = S F_IB
+          add.push_back({F + long(s) * w, Fac + nd.Soff, Fac + nd.GToff, w, s, s, m, s, s, 0, 0});  // G^T = F_BI S
+        } else {
+          add.push_back({F + long(s) * w, Fac + nd.Goff, F + long(s) * w + s, w, m, w, m, m, s, 1, 0});  // U
+        }
+        for (GemmDesc d : add) {
+          d.tile0 = long(td.size() - L.t0[phase]);
+          const long nt = long((d.M + 63) / 64) * ((d.N + 63) / 64);
+          for (long q = 0; q < nt; ++q) td.push_back(int(gd.size() - L.d0[phase]));
+          gd.push_back(d);
+        }
+      }
+      L.d1[phase] = gd.size();
+      L.t1[phase] = td.size();
+    }
+  }
+  // one upload: pointers, row tasks, extend rows, inversion list, parents, GEMM tables
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t b_fp = al(size_t(nn) * 8), b_rows = al(rows.size() * 8), b_ext = al(ext.size() * 8),
+               b_gj = al(gj.size() * 4), b_par = al(parent.size() * 4),
+               b_gd = al(gd.size() * sizeof(GemmDesc)), b_td = al(td.size() * 4);
+  std::vector<char> hb(b_fp + b_rows + b_ext + b_gj + b_par + b_gd + b_td, 0);
+  size_t o = 0;
+  std::memcpy(hb.data() + o, fp.data(), nn * 8); o += b_fp;
+  std::memcpy(hb.data() + o, rows.data(), rows.size() * 8); o += b_rows;
+  std::memcpy(hb.data() + o, ext.data(), ext.size() * 8); o += b_ext;
+  std::memcpy(hb.data() + o, gj.data(), gj.size() * 4); o += b_gj;
+  std::memcpy(hb.data() + o, parent.data(), parent.size() * 4); o += b_par;
+  std::memcpy(hb.data() + o, gd.data(), gd.size() * sizeof(GemmDesc)); o += b_gd;
+  std::memcpy(hb.data() + o, td.data(), td.size() * 4);
+  char* db = nullptr;
+  HZ_HIP(hipMallocAsync(reinterpret_cast<void**>(&db), hb.size(), st));
+  HZ_HIP(hipMemcpyAsync(db, hb.data(), hb.size(), hipMemcpyHostToDevice, st));
+  o = 0;
+  double2* const* d_fp = reinterpret_cast<double2* const*>(db + o); o += b_fp;
+  const int2* d_rows = reinterpret_cast<const int2*>(db + o); o += b_rows;
+  const int2* d_ext = reinterpret_cast<const int2*>(db + o); o += b_ext;
+  const int* d_gj = reinterpret_cast<const int*>(db + o); o += b_gj;
+  const int* d_par = reinterpret_cast<const int*>(db + o); o += b_par;
+  const GemmDesc* d_gd = reinterpret_cast<const GemmDesc*>(db + o); o += b_gd;
+  const int* d_td = reinterpret_cast<const int*>(db + o);
+  // sweep work for the large inversions
+  double2 *W = nullptr, *R = nullptr;
+  if (maxbig > 0) {
+    HZ_HIP(hipMallocAsync(reinterpret_cast<void**>(&W), 2 * sweep_panel_elems(maxbig) * 16, st));
+    HZ_HIP(hipMallocAsync(reinterpret_cast<void**>(&R), 2 * sweep_pinv_elems() * 16, st));
+  }
+  HZ_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+  const int p = sym.p, Mc = sym.Mc;
+  for (int h = 0; h <= sym.H; ++h) {
+    const HL& L = hl[h];
+    const int nr = int(L.r1 - L.r0);
+    if (nr > 0) {
+      if (p == 1) launch_front<1>(mv, cop, Mc, d_rows + L.r0, nr, d_fp, st);
+      else if (p == 2) launch_front<2>(mv, cop, Mc, d_rows + L.r0, nr, d_fp, st);
+      else launch_front<3>(mv, cop, Mc, d_rows + L.r0, nr, d_fp, st);
+      HZ_HIP(hipGetLastError());
+    }
+    for (int slot = 0; slot < 2; ++slot) {
+      const int ne = int(L.e1[slot] - L.e0[slot]);
+      if (ne > 0) k_mf_extend<<<ne, 256, 0, st>>>(mv, d_par, d_ext + L.e0[slot], d_fp);
+    }
+    const int ng = int(L.g1 - L.g0);
+    if (ng > 0) {
+      static std::once_flag once;
+      std::call_once(once, [] {
+        HZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_gj),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 65 * 16));
+      });
+      int smax = 0;
+      for (size_t q = L.g0; q < L.g1; ++q) smax = std::max(smax, sym.nodes[gj[q]].s);
+      k_mf_gj<<<ng, 256, size_t(smax) * (smax + 1) * 16, st>>>(mv, d_gj + L.g0, d_fp, Fac, flag);
+    }
+    for (int v : sym.at[h]) {
+      const MfNode& nd = sym.nodes[v];
+      if (nd.s <= 64) continue;
+      const long n2 = long(nd.s) * nd.s;
+      k_mf_copy_ii<<<unsigned((n2 + 255) / 256), 256, 0, st>>>(fp[v], nd.s, nd.s + nd.m, Fac + nd.Soff);
+      sweep_inverse(Fac + nd.Soff, nd.s, W, R, flag, st);
+    }
+    for (int phase = 0; phase < 2; ++phase) {
+      const int nt = int(L.t1[phase] - L.t0[phase]);
+      if (nt > 0) k_mf_gemm<<<nt, 256, 0, st>>>(d_gd + L.d0[phase], d_td + L.t0[phase]);
+    }
+    HZ_HIP(hipGetLastError());
+  }
+  int hflag = 0;
+  HZ_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HZ_HIP(hipStreamSynchronize(st));
+  if (W) (void)hipFreeAsync(W, st);
+  if (R) (void)hipFreeAsync(R, st);
+  (void)hipFreeAsync(db, st);
+  (void)hipFreeAsync(ws, st);
+  return hflag ? HZ_ESINGULAR : HZ_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Solve kernels
+// ------------------------------------------------------------------------------------------
+
+namespace {
+
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// One launch per tree height and pass; workgroup (task, job, right-hand-side group). Large
+// nodes: the workgroup assembles the node's front vector in LDS and each wave forms rows of
+// one matrix (lanes over the columns, then a butterfly sum). Small nodes (s + m <= 64): one
+// wave per node, lane r forms row r (lanes read consecutive entries of a stored row).
+template <typename T, int NR, bool FWD>
+__global__ void __launch_bounds__(256)
+k_mf_solve(CsJobs<T> jobs, int task0, long cstride) {
+  extern __shared__ char smem[];
+  V2<T>* f = reinterpret_cast<V2<T>*>(smem);
+  const CoarseJob<T>* job = &jobs.j[blockIdx.y];
+  const int hb = blockIdx.z * NR;
+  const int nr = min(NR, job->nrhs - hb);
+  if (nr <= 0) return;
+  const MfView mv = *job->mf;
+  const MfTask t = (FWD ? mv.fwd : mv.bwd)[task0 + blockIdx.x];
+  const V2<T>* __restrict__ Fac = job->S;
+  const V2<T>* b = job->b + long(hb) * cstride;
+  V2<T>* y = job->y + long(hb) * cstride;
+  V2<T>* u = job->gbuf + long(hb) * job->ustride;
+  const long us = job->ustride;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (t.kind <= 2) {
+    const MfNode nd = mv.nodes[t.v];
+    const int s = nd.s, m = nd.m, w = s + m;
+    if (FWD) {
+      for (int i = threadIdx.x; i < w; i += 256)
+        for (int h = 0; h < nr; ++h)
+          f[h * w + i] = i < s ? b[h * cstride + mv.I[nd.Ioff + i]] : czero<T>();
+      __syncthreads();
+      for (int slot = 0; slot < 2; ++slot) {
+        const int c = slot == 0 ? nd.ch0 : nd.ch1;
+        if (c >= 0) {
+          const MfNode cn = mv.nodes[c];
+          for (int j = threadIdx.x; j < cn.m; j += 256) {
+            const int pos = mv.map[cn.mapoff + j];
+            for (int h = 0; h < nr; ++h) {
+              const V2<T> uv = u[h * us + cn.uoff + j];
+              f[h * w + pos].x += uv.x;
+              f[h * w + pos].y += uv.y;
+            }
+          }
+        }
+        __syncthreads();
+      }
+      const V2<T>* X = Fac + (t.kind == 0 ? nd.Soff : nd.GToff);
+      for (int r = t.r0 + wave; r < t.r1; r += 4) {
+        V2<T> acc[NR];
+#pragma unroll
+        for (int h = 0; h < NR; ++h) acc[h] = czero<T>();
+        const V2<T>* xr = X + long(r) * s;
+        for (int k = lane; k < s; k += 64) {
+          const V2<T> xv = xr[k];
+#pragma unroll
+          for (int h = 0; h < NR; ++h)
+            if (h < nr) cfma(acc[h], xv, f[h * w + k]);
+        }
+#pragma unroll
+        for (int h = 0; h < NR; ++h) {
+          acc[h].x = wave_sum(acc[h].x);
+          acc[h].y = wave_sum(acc[h].y);
+        }
+        if (lane == 0)
+          for (int h = 0; h < nr; ++h) {
+            if (t.kind == 0) {
+              y[h * cstride + mv.I[nd.Ioff + r]] = acc[h];
+            } else {
+              const V2<T> fb = f[h * w + s + r];
+              V2<T> o;
+              o.x = fb.x - acc[h].x;
+              o.y = fb.y - acc[h].y;
+              u[h * us + nd.uoff + r] = o;
+            }
+          }
+      }
+    } else {
+      for (int k = threadIdx.x; k < m; k += 256)
+        for (int h = 0; h < nr; ++h) f[h * m + k] = y[h * cstride + mv.B[nd.Boff + k]];
+      __syncthreads();
+      const V2<T>* X = Fac + nd.Goff;
+      for (int r = t.r0 + wave; r < t.r1; r += 4) {
+        V2<T> acc[NR];
+#pragma unroll
+        for (int h = 0; h < NR; ++h) acc[h] = czero<T>();
+        const V2<T>* xr = X + long(r) * m;
+        for (int k = lane; k < m; k += 64) {
+          const V2<T> xv = xr[k];
+#pragma unroll
+          for (int h = 0; h < NR; ++h)
+            if (h < nr) cfma(acc[h], xv, f[h * m + k]);
+        }
+#pragma unroll
+        for (int h = 0; h < NR; ++h) {
+          acc[h].x = wave_sum(acc[h].x);
+          acc[h].y = wave_sum(acc[h].y);
+        }
+        if (lane == 0)
+          for (int h = 0; h < nr; ++h) {
+            const long gi = h * cstride + mv.I[nd.Ioff + r];
+            V2<T> z = y[gi];
+            z.x -= acc[h].x;
+            z.y -= acc[h].y;
+            y[gi] = z;
+          }
+      }
+    }
+    return;
+  }
+  // small nodes: wave `wave` takes node hn[r0 + wave]; every thread passes every barrier
+  const bool has = t.r0 + wave < t.r1;
+  const int v = has ? mv.hn[t.r0 + wave] : 0;
+  const MfNode nd = mv.nodes[v];
+  const int s = nd.s, m = nd.m;
+  V2<T>* fw = f + wave * (NR * 64);
+  if (FWD) {
+    if (has && lane < s + m)
+      for (int h = 0; h < nr; ++h)
+        fw[h * 64 + lane] = lane < s ? b[h * cstride + mv.I[nd.Ioff + lane]] : czero<T>();
+    __syncthreads();
+    for (int slot = 0; slot < 2; ++slot) {
+      const int c = slot == 0 ? nd.ch0 : nd.ch1;
+      if (has && c >= 0) {
+        const MfNode cn = mv.nodes[c];
+        if (lane < cn.m) {
+          const int pos = mv.map[cn.mapoff + lane];
+          for (int h = 0; h < nr; ++h) {
+            const V2<T> uv = u[h * us + cn.uoff + lane];
+            fw[h * 64 + pos].x += uv.x;
+            fw[h * 64 + pos].y += uv.y;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (has && lane < s + m) {
+      V2<T> acc[NR];
+#pragma unroll
+      for (int h = 0; h < NR; ++h) acc[h] = czero<T>();
+      if (lane < s) {
+        const V2<T>* Sv = Fac + nd.Soff;     // symmetric: row k, entry lane = S[lane][k]
+        for (int k = 0; k < s; ++k) {
+          const V2<T> xv = Sv[long(k) * s + lane];
+#pragma unroll
+          for (int h = 0; h < NR; ++h)
+            if (h < nr) cfma(acc[h], xv, fw[h * 64 + k]);
+        }
+        for (int h = 0; h < nr; ++h) y[h * cstride + mv.I[nd.Ioff + lane]] = acc[h];
+      } else {
+        const int rr = lane - s;
+        const V2<T>* Gv = Fac + nd.Goff;     // (G^T f_I)[rr] = sum_i G[i][rr] f[i]
+        for (int i = 0; i < s; ++i) {
+          const V2<T> xv = Gv[long(i) * m + rr];
+#pragma unroll
+          for (int h = 0; h < NR; ++h)
+            if (h < nr) cfma(acc[h], xv, fw[h * 64 + i]);
+        }
+        for (int h = 0; h < nr; ++h) {
+          const V2<T> fb = fw[h * 64 + s + rr];
+          V2<T> o;
+          o.x = fb.x - acc[h].x;
+          o.y = fb.y - acc[h].y;
+          u[h * us + nd.uoff + rr] = o;
+        }
+      }
+    }
+  } else {
+    if (has && lane < m)
+      for (int h = 0; h < nr; ++h) fw[h * 64 + lane] = y[h * cstride + mv.B[nd.Boff + lane]];
+    __syncthreads();
+    if (has && m > 0 && lane < s) {
+      V2<T> acc[NR];
+#pragma unroll
+      for (int h = 0; h < NR; ++h) acc[h] = czero<T>();
+      const V2<T>* GTv = Fac + nd.GToff;     // (G x_B)[lane] = sum_k G^T[k][lane] x_B[k]
+      for (int k = 0; k < m; ++k) {
+        const V2<T> xv = GTv[long(k) * s + lane];
+#pragma unroll
+        for (int h = 0; h < NR; ++h)
+          if (h < nr) cfma(acc[h], xv, fw[h * 64 + k]);
+      }
+      for (int h = 0; h < nr; ++h) {
+        const long gi = h * cstride + mv.I[nd.Ioff + lane];
+        V2<T> z = y[gi];
+        z.x -= acc[h].x;
+        z.y -= acc[h].y;
+        y[gi] = z;
+      }
+    }
+  }
+}
+
+template <typename T, int NR>
+int mf_launch_all(const MfSym& sym, const CsJobs<T>& jj, int njobs, int maxr, long cstride,
+                  hipStream_t st) {
+  const size_t item = sizeof(V2<T>);
+  const size_t lds = std::max<size_t>(size_t(NR) * sym.maxf, 4 * size_t(NR) * 64) * item;
+  const unsigned gz = unsigned((maxr + NR - 1) / NR);
+  int launches = 0;
+  for (int h = 0; h <= sym.H; ++h) {
+    const int n = sym.fwd0[h + 1] - sym.fwd0[h];
+    if (n > 0) {
+      k_mf_solve<T, NR, true><<<dim3(n, njobs, gz), 256, lds, st>>>(jj, sym.fwd0[h], cstride);
+      ++launches;
+    }
+  }
+  for (int h = sym.H; h >= 0; --h) {
+    const int n = sym.bwd0[h + 1] - sym.bwd0[h];
+    if (n > 0) {
+      k_mf_solve<T, NR, false><<<dim3(n, njobs, gz), 256, lds, st>>>(jj, sym.bwd0[h], cstride);
+      ++launches;
+    }
+  }
+  HZ_HIP(hipGetLastError());
+  return launches;
+}
+
+template <typename T, int NR>
+void mf_set_lds(size_t bytes) {
+  static std::mutex mu;
+  static size_t done = 0;
+  std::lock_guard<std::mutex> g(mu);
+  if (bytes <= done) return;
+  HZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_solve<T, NR, true>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+  HZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_solve<T, NR, false>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+  done = bytes;
+}
+
+}  // namespace
+
+template <typename T>
+int mf_solve_jobs(const MfSym& sym, const CoarseJob<T>* jobs, int njobs, long cstride,
+                  hipStream_t st) {
+  int launches = 0;
+  const size_t item = sizeof(V2<T>);
+  for (int j0 = 0; j0 < njobs; j0 += kMaxJobs) {
+    const int nj = std::min(kMaxJobs, njobs - j0);
+    CsJobs<T> jj;
+    int maxr = 0;
+    for (int i = 0; i < nj; ++i) {
+      jj.j[i] = jobs[j0 + i];
+      maxr = std::max(maxr, jobs[j0 + i].nrhs);
+    }
+    // right-hand sides per workgroup: as many as the front vectors' LDS allows (<= 4)
+    const size_t per = std::max<size_t>(sym.maxf, 4 * 64) * item;
+    int NR = 4;
+    while (NR > 1 && size_t(NR) * per > 128 * 1024) NR /= 2;
+    if (size_t(NR) * per > 160 * 1024) throw std::runtime_error("multifrontal: front exceeds LDS");
+    if (maxr == 1) NR = 1;
+    if (NR == 4) { mf_set_lds<T, 4>(4 * per); launches += mf_launch_all<T, 4>(sym, jj, nj, maxr, cstride, st); }
+    else if (NR == 2) { mf_set_lds<T, 2>(2 * per); launches += mf_launch_all<T, 2>(sym, jj, nj, maxr, cstride, st); }
+    else { mf_set_lds<T, 1>(per); launches += mf_launch_all<T, 1>(sym, jj, nj, maxr, cstride, st); }
+  }
+  return launches;
+}
+
+template int mf_solve_jobs<double>(const MfSym&, const CoarseJob<double>*, int, long, hipStream_t);
+template int mf_solve_jobs<float>(const MfSym&, const CoarseJob<float>*, int, long, hipStream_t);
+
+const MfSym& mf_symbolic(int p, int nc) {
+  std::lock_guard<std::mutex> g(g_sym_mu);
+  auto& slot = g_sym[{p, nc}];
+  if (!slot) {
+    std::unique_ptr<MfSym> s(new MfSym());
+    build_symbolic(*s, p, nc);
+    slot = std::move(s);
+  }
+  return *slot;
+}
+
+}  // namespace hz
