@@ -329,7 +329,7 @@ size_t workspace_bytes(long N, int nblk, int cap, int m, int prec, bool staged) 
   b += size_t(cap) * m * N * (prec == HZ_MIXED ? 8 : 16);       // Z
   b += 2 * size_t(cap) * N * 16;                                // r, w
   if (staged) b += 2 * size_t(cap) * N * 16;                    // F, u
-  b += size_t(cap) * (size_t(nblk) * 64 * 16 + 192 * 16 + 64 * 16 + 8);
+  b += size_t(cap) * (size_t(fused_blocks(N)) * 64 * 16 + 192 * 16 + 64 * 16 + 8);
   b += 2 * size_t(cap) * (Workspace::kTabs * 8 + 2 * 4 + 8 + 3 * 8 + 64 * 16) + 4096;
   return b;
 }
@@ -557,7 +557,7 @@ std::unique_ptr<Workspace> make_workspace(int cap, int m, int prec, long N, long
   }
   if (prec == HZ_MIXED) w->Zf = w->mem.alloc<float2>(size_t(cap) * m * N);
   else w->Zd = w->mem.alloc<double2>(size_t(cap) * m * N);
-  w->partial = w->mem.alloc<double2>(size_t(cap) * w->nblk * 64);
+  w->partial = w->mem.alloc<double2>(size_t(cap) * fused_blocks(N) * 64);
   w->hbuf = w->mem.alloc<double2>(size_t(cap) * 192);
   w->up_bytes = region_bytes(cap);
   // device mirror of the two upload regions
@@ -840,6 +840,7 @@ struct Lockstep {
   std::vector<cd> y;
   clk::time_point t0;
   bool issued = false;
+  int round_nv = 64;        // largest basis size of the round's projections
 
   ~Lockstep() {
     drop_graphs();
@@ -985,7 +986,8 @@ struct Lockstep {
       h.ptab[cap + z] = mixed ? static_cast<const void*>(pz->fwdAe) : static_cast<const void*>(pz->wdAe);
       h.ptab[2 * cap + z] = pz->cA0;
     }
-    (void)maxnv;
+    // vectors of this round's projections (a replayed graph must cover every round: 64)
+    round_nv = use_graphs() ? 64 : maxnv;
     if (!use_graphs()) {
       enqueue_round(na, st, VC_ALL);
       return true;
@@ -1154,12 +1156,12 @@ struct Lockstep {
     a0.pn = pr0->cells;
     apply_a0(a0, p, Addr(0, d_zj), Addr(0, d_w), na, st);
     // CGS2: two passes of h = V^H w, w -= V h; then |w|^2
+    // (the first pass's update and the second pass's projection share one read of V)
     launch_mdot_b(ws->V, Addr(0, d_vb), N, 64, d.itab, ws->RW, Addr(0, d_w), N, ws->partial, nblk, na, st);
     launch_reduce_b(ws->partial, nblk, 64, d.itab, ws->hbuf, 192, na, st);
-    launch_maxpy_b(ws->V, Addr(0, d_vb), N, 64, d.itab, ws->hbuf, 192, ws->RW, Addr(0, d_w), N,
-                   nullptr, nblk, na, st);
-    launch_mdot_b(ws->V, Addr(0, d_vb), N, 64, d.itab, ws->RW, Addr(0, d_w), N, ws->partial, nblk, na, st);
-    launch_reduce_b(ws->partial, nblk, 64, d.itab, ws->hbuf + 64, 192, na, st);
+    launch_maxpy_mdot_b(ws->V, Addr(0, d_vb), N, round_nv, d.itab, ws->hbuf, 192, ws->RW,
+                        Addr(0, d_w), N, ws->partial, na, st);
+    launch_reduce_b(ws->partial, fused_blocks(N), 64, d.itab, ws->hbuf + 64, 192, na, st);
     launch_maxpy_b(ws->V, Addr(0, d_vb), N, 64, d.itab, ws->hbuf + 64, 192, ws->RW, Addr(0, d_w), N,
                    ws->partial, nblk, na, st);
     launch_reduce_b(ws->partial, nblk, 1, nullptr, ws->hbuf + 128, 192, na, st);

@@ -686,29 +686,6 @@ __device__ __forceinline__ void gather_block(const V2<T>* src, long sstride, int
   }
 }
 
-// Sum over each row of 16 lanes (every lane of the row gets it): a butterfly of lane
-// permutations within the row (mirror, half mirror, then the two quad exchanges), each step
-// moving the two 32-bit halves of a value with DPP.
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-  const long long bits = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, int(bits), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, int(bits >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
-}
-template <int CTRL>
-__device__ __forceinline__ float dpp_move(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <typename T>
-__device__ __forceinline__ T row16_sum(T v) {
-  v += dpp_move<0x140>(v);   // row_mirror: lane i <- 15 - i
-  v += dpp_move<0x141>(v);   // row_half_mirror: lane i <- 7 - i within each half row
-  v += dpp_move<0x4E>(v);    // quad_perm [2, 3, 0, 1]
-  v += dpp_move<0xB1>(v);    // quad_perm [1, 0, 3, 2]
-  return v;
-}
-
 // 512 threads. Waves 0-1 ("exchange waves") gather neighbour results (polling) into LDS and
 // publish the results; while a step computes they stage the next step's right-hand side
 // (or zeros) into the LDS buffer the step no longer needs, so the two buffers swap roles from

@@ -210,8 +210,9 @@ struct MfNode {
   long mapoff = -1;            // front positions in the parent of this node's B points
 };
 // One unit of a solve pass at one tree height: rows [r0, r1) of matrix `kind` of node v
-// (kind 0: S, 1: G^T for the forward pass; 2: G for the backward pass), or, for kinds 3
-// (forward) and 4 (backward), the whole small nodes hn[r0 .. r1) (one wave per node).
+// (kind 0: S, 1: G^T for the forward pass; 2: G for the backward pass; one wave per row), or
+// rows [r0, r1) of [S; G^T] of node v, one thread per row (kind 5, forward, s <= 64), or,
+// for kinds 3 (forward) and 4 (backward), the whole small nodes hn[r0 .. r1) (one wave each).
 struct MfTask {
   int v, kind, r0, r1;
 };
@@ -226,6 +227,7 @@ struct MfSym {
   std::vector<MfTask> fwd, bwd;           // solve tasks, grouped by height
   std::vector<int> fwd0, bwd0;            // first task of each height (H + 2 entries)
   int maxf = 0;                           // largest s + m
+  std::vector<int> fmax, bmax;            // per height: largest s + m, m of a non-small node
 };
 // The (cached) symbolic factor of the coarse lattice of order p with nc cells per side.
 const MfSym& mf_symbolic(int p, int nc);
@@ -293,6 +295,12 @@ void set_stencil_tuning(bool on);
 // its partial sums at partial + z nblk 64, its small vectors (h, y) at z hs, and its own
 // vector count nvt[z] when the table is given (0 = nothing to do), else nv.
 int mdot_blocks(long N);
+int fused_blocks(long N);     // blocks (partial sums) of launch_maxpy_mdot_b
+// w -= V h, then partial sums of V^H w (the new w) from the same read of V; nv bounds the
+// per-instance counts nvt (the kernel keeps up to 64 basis entries per element in registers).
+void launch_maxpy_mdot_b(const double2* V, Addr av, long ldv, int nv, const int* nvt,
+                         const double2* h, long hs, double2* w, Addr aw, long N,
+                         double2* partial, int nbatch, hipStream_t st);
 template <typename TV>
 void launch_mdot(const V2<TV>* V, long ldv, int nv, const double2* w, long N, double2* partial,
                  int nblk, hipStream_t st);

@@ -125,6 +125,67 @@ k_maxpy(const double2* __restrict__ V, Addr av, long ldv, int nv, const int* __r
   }
 }
 
+// The first pass's update and the second pass's projection from one read of V:
+// w' = w - V h (the same arithmetic as k_maxpy) and partial[b][i] = sum over the
+// workgroup's elements of conj(V[i]) w'. One element per thread: its column of V (up to NVB
+// basis vectors) stays in registers between the two. The per-vector sums over the workgroup
+// run as DPP sums over rows of 16 lanes, then over the 16 row results in a fixed order.
+template <int NVB>
+__global__ void __launch_bounds__(256, 1)
+k_maxpy_mdot(const double2* __restrict__ V, Addr av, long ldv, int nv, const int* __restrict__ nvt,
+             const double2* __restrict__ h, long hstride, double2* __restrict__ w, Addr aw, long N,
+             double2* __restrict__ partial, int nblk) {
+  __shared__ double2 hs[64];
+  __shared__ double red[2][64][16];
+  const int bz = blockIdx.y;
+  if (nvt) nv = nvt[bz];
+  if (nv <= 0) return;
+  V += av.at(bz);
+  w += aw.at(bz);
+  h += bz * hstride;
+  partial += long(bz) * nblk * 64;
+  if (threadIdx.x < nv) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  const long k = long(blockIdx.x) * 256 + threadIdx.x;
+  const bool in = k < N;
+  double2 vv[NVB];
+  double2 acc = in ? w[k] : make_double2(0, 0);
+#pragma unroll
+  for (int i = 0; i < NVB; ++i)
+    vv[i] = (i < nv && in) ? V[i * ldv + k] : make_double2(0, 0);
+#pragma unroll
+  for (int i = 0; i < NVB; ++i) {
+    if (i < nv) {
+      const double2 hh = hs[i];
+      acc.x -= vv[i].x * hh.x - vv[i].y * hh.y;
+      acc.y -= vv[i].x * hh.y + vv[i].y * hh.x;
+    }
+  }
+  if (in) w[k] = acc;
+  const int row = threadIdx.x >> 4, lane16 = threadIdx.x & 15;
+#pragma unroll
+  for (int i = 0; i < NVB; ++i) {
+    if (i < nv) {
+      double2 d = make_double2(0, 0);
+      cfma_conj(d, vv[i], acc);
+      d.x = row16_sum(d.x);
+      d.y = row16_sum(d.y);
+      if (lane16 == 0) { red[0][i][row] = d.x; red[1][i][row] = d.y; }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    const int i = threadIdx.x;
+    double2 sm = make_double2(0, 0);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      sm.x += red[0][i][q];
+      sm.y += red[1][i][q];
+    }
+    partial[long(blockIdx.x) * 64 + i] = sm;
+  }
+}
+
 __global__ void k_scale(const double2* __restrict__ w, Addr aw, const double* __restrict__ s,
                         double2* __restrict__ v, Addr av, long N) {
   const long i = long(blockIdx.x) * 256 + threadIdx.x;
@@ -177,6 +238,26 @@ __global__ void k_copy(const double2* __restrict__ x, Addr ax, double2* __restri
 }  // namespace
 
 int mdot_blocks(long N) { return int((N + CHUNK - 1) / CHUNK); }
+int fused_blocks(long N) { return int((N + 255) / 256); }
+
+void launch_maxpy_mdot_b(const double2* V, Addr av, long ldv, int nv, const int* nvt,
+                         const double2* h, long hs, double2* w, Addr aw, long N,
+                         double2* partial, int nbatch, hipStream_t st) {
+  if (nbatch <= 0) return;
+  const dim3 g(unsigned(fused_blocks(N)), nbatch);
+  const int nb = fused_blocks(N);
+#define HZ_MM(B) k_maxpy_mdot<B><<<g, 256, 0, st>>>(V, av, ldv, nv, nvt, h, hs, w, aw, N, partial, nb)
+  if (nv <= 8) HZ_MM(8);
+  else if (nv <= 16) HZ_MM(16);
+  else if (nv <= 24) HZ_MM(24);
+  else if (nv <= 32) HZ_MM(32);
+  else if (nv <= 40) HZ_MM(40);
+  else if (nv <= 48) HZ_MM(48);
+  else if (nv <= 56) HZ_MM(56);
+  else HZ_MM(64);
+#undef HZ_MM
+  HZ_HIP(hipGetLastError());
+}
 
 template <typename TV>
 void launch_mdot(const V2<TV>* V, long ldv, int nv, const double2* w, long N, double2* partial,

@@ -102,8 +102,13 @@ struct Builder {
   }
 };
 
-// rows of one solve task: about 4 rows per wave of a 256-thread workgroup
-constexpr int kMfRows = 4;
+// Rows of one wave-per-row solve task: about 32 KB of the matrix, a multiple of the four
+// waves, 4 .. 64.
+int task_rows(int len) {
+  int r = (32768 / 16 + len - 1) / std::max(len, 1);
+  r = (r + 3) / 4 * 4;
+  return std::min(64, std::max(4, r));
+}
 
 void build_symbolic(MfSym& S, int p, int nc) {
   S.p = p;
@@ -184,10 +189,19 @@ void build_symbolic(MfSym& S, int p, int nc) {
         small.push_back(hbase + int(q));
         continue;
       }
-      for (int r = 0; r < nd.s; r += kMfRows) S.fwd.push_back({v, 0, r, std::min(nd.s, r + kMfRows)});
-      for (int r = 0; r < nd.m; r += kMfRows) S.fwd.push_back({v, 1, r, std::min(nd.m, r + kMfRows)});
-      if (nd.m > 0)
-        for (int r = 0; r < nd.s; r += kMfRows) S.bwd.push_back({v, 2, r, std::min(nd.s, r + kMfRows)});
+      if (nd.s <= 64) {
+        // short rows: thread per row over [S; G^T] rows, 256 rows per task
+        for (int r = 0; r < nd.s + nd.m; r += 256)
+          S.fwd.push_back({v, 5, r, std::min(nd.s + nd.m, r + 256)});
+      } else {
+        const int R = task_rows(nd.s);
+        for (int r = 0; r < nd.s; r += R) S.fwd.push_back({v, 0, r, std::min(nd.s, r + R)});
+        for (int r = 0; r < nd.m; r += R) S.fwd.push_back({v, 1, r, std::min(nd.m, r + R)});
+      }
+      if (nd.m > 0) {
+        const int R = task_rows(nd.m);
+        for (int r = 0; r < nd.s; r += R) S.bwd.push_back({v, 2, r, std::min(nd.s, r + R)});
+      }
     }
     // small nodes (s + m <= 64): one wave each, four to a workgroup; r0 .. r1 is a range of
     // consecutive positions in hn (the small nodes of a height are consecutive there)
@@ -201,6 +215,14 @@ void build_symbolic(MfSym& S, int p, int nc) {
   }
   S.fwd0[S.H + 1] = int(S.fwd.size());
   S.bwd0[S.H + 1] = int(S.bwd.size());
+  S.fmax.assign(S.H + 1, 0);
+  S.bmax.assign(S.H + 1, 0);
+  for (int v = 0; v < nn; ++v) {
+    const MfNode& nd = S.nodes[v];
+    if (is_small(v)) continue;
+    S.fmax[S.height[v]] = std::max(S.fmax[S.height[v]], nd.s + nd.m);
+    S.bmax[S.height[v]] = std::max(S.bmax[S.height[v]], nd.m);
+  }
 }
 
 std::mutex g_sym_mu;
@@ -622,7 +644,7 @@ k_mf_solve(CsJobs<T> jobs, int task0, long cstride) {
   V2<T>* u = job->gbuf + long(hb) * job->ustride;
   const long us = job->ustride;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (t.kind <= 2) {
+  if (t.kind <= 2 || t.kind == 5) {
     const MfNode nd = mv.nodes[t.v];
     const int s = nd.s, m = nd.m, w = s + m;
     if (FWD) {
@@ -644,6 +666,37 @@ k_mf_solve(CsJobs<T> jobs, int task0, long cstride) {
           }
         }
         __syncthreads();
+      }
+      if (t.kind == 5) {
+        // thread per row: rows r < s of S (symmetric: walk row k, entry r), rows s + r' of
+        // G^T f_I (walk row i of G, entry r'); consecutive threads read consecutive entries
+        const int r = t.r0 + int(threadIdx.x);
+        if (r < t.r1) {
+          V2<T> acc[NR];
+#pragma unroll
+          for (int h = 0; h < NR; ++h) acc[h] = czero<T>();
+          const bool zr = r < s;
+          const V2<T>* X = zr ? Fac + nd.Soff + r : Fac + nd.Goff + (r - s);
+          const int ld = zr ? s : m;
+          for (int k = 0; k < s; ++k) {
+            const V2<T> xv = X[long(k) * ld];
+#pragma unroll
+            for (int h = 0; h < NR; ++h)
+              if (h < nr) cfma(acc[h], xv, f[h * w + k]);
+          }
+          for (int h = 0; h < nr; ++h) {
+            if (zr) {
+              y[h * cstride + mv.I[nd.Ioff + r]] = acc[h];
+            } else {
+              const V2<T> fb = f[h * w + r];
+              V2<T> o;
+              o.x = fb.x - acc[h].x;
+              o.y = fb.y - acc[h].y;
+              u[h * us + nd.uoff + (r - s)] = o;
+            }
+          }
+        }
+        return;
       }
       const V2<T>* X = Fac + (t.kind == 0 ? nd.Soff : nd.GToff);
       for (int r = t.r0 + wave; r < t.r1; r += 4) {
@@ -795,20 +848,25 @@ template <typename T, int NR>
 int mf_launch_all(const MfSym& sym, const CsJobs<T>& jj, int njobs, int maxr, long cstride,
                   hipStream_t st) {
   const size_t item = sizeof(V2<T>);
-  const size_t lds = std::max<size_t>(size_t(NR) * sym.maxf, 4 * size_t(NR) * 64) * item;
   const unsigned gz = unsigned((maxr + NR - 1) / NR);
   int launches = 0;
+  // LDS of a height: its largest front vector (forward) or ring (backward), or the small
+  // nodes' wave regions; small requests keep more workgroups resident per CU
+  auto lds_of = [&](int h, bool fwd) {
+    const int mx = fwd ? sym.fmax[h] : sym.bmax[h];
+    return std::max<size_t>(size_t(NR) * mx, 4 * size_t(NR) * 64) * item;
+  };
   for (int h = 0; h <= sym.H; ++h) {
     const int n = sym.fwd0[h + 1] - sym.fwd0[h];
     if (n > 0) {
-      k_mf_solve<T, NR, true><<<dim3(n, njobs, gz), 256, lds, st>>>(jj, sym.fwd0[h], cstride);
+      k_mf_solve<T, NR, true><<<dim3(n, njobs, gz), 256, lds_of(h, true), st>>>(jj, sym.fwd0[h], cstride);
       ++launches;
     }
   }
   for (int h = sym.H; h >= 0; --h) {
     const int n = sym.bwd0[h + 1] - sym.bwd0[h];
     if (n > 0) {
-      k_mf_solve<T, NR, false><<<dim3(n, njobs, gz), 256, lds, st>>>(jj, sym.bwd0[h], cstride);
+      k_mf_solve<T, NR, false><<<dim3(n, njobs, gz), 256, lds_of(h, false), st>>>(jj, sym.bwd0[h], cstride);
       ++launches;
     }
   }
