@@ -31,9 +31,9 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(path="profiles/k_csolve_p1_k400_n2048_traffic.txt"):
-    """HBM bytes per launch of the coarse solve from the committed counter summary, or None
-    when the kernel source has changed since the counters were taken."""
+def measured_traffic(path="profiles/k_mf_solve_p1_k400_n2048_traffic.txt"):
+    """HBM bytes per coarse system of the multifrontal solve from the committed counter
+    summary, or None when the kernel source has changed since the counters were taken."""
     import hashlib
     try:
         with open(os.path.join(ROOT, path)) as f:
@@ -43,7 +43,7 @@ def measured_traffic(path="profiles/k_csolve_p1_k400_n2048_traffic.txt"):
             h = hashlib.sha256(f.read()).hexdigest()[:16]
         if h != kv["kernel_source_sha256_16"].strip():
             return None
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv["traffic_bytes_per_system"])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -254,15 +254,19 @@ def run_gpu(cfg, steps, warmup, prec):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
-    # Dominant kernel: the coarse block triangular solve (one persistent launch per
-    # V-cycle). Device time from HIP event pairs around every launch on the solve stream
-    # during the timed steps; bytes are the algorithmic factor reads per launch.
+    # Dominant kernel: the multifrontal coarse solve (k_mf_solve, one launch per tree height
+    # and pass). Device time from HIP event pairs around every coarse solve on the solve
+    # stream during the timed steps; bytes are the algorithmic factor and vector traffic.
+    # Unit: one coarse system (its 2H+1 launches).
+    systems = sum(x["coarse_systems"] for x in stats)
     launches = sum(x["coarse_solves"] for x in stats)
-    cs_ms = sum(x["coarse_solve_ms"] for x in stats) / max(launches, 1)
+    cs_ms = sum(x["coarse_solve_ms"] for x in stats) / max(systems, 1)
     factor_ms = sum(x["factor_ms"] for x in stats) / max(len(stats), 1)
-    cs_bytes = sum(x["coarse_bytes"] for x in stats) / max(launches, 1)
+    factor_flop = sum(x["factor_flop"] for x in stats) / max(len(stats), 1)
+    cs_bytes = sum(x["coarse_bytes"] for x in stats) / max(systems, 1)
     return dict(seconds=dt, iterations=its, info=info, coarse_ms=cs_ms, coarse_bytes=cs_bytes,
-                coarse_launches=launches, factor_ms=factor_ms)
+                coarse_systems=systems, launches_per_system=launches / max(systems, 1),
+                factor_ms=factor_ms, factor_flop=factor_flop)
 
 
 def near_optimal_beta(betas, its, rhos):
@@ -349,14 +353,14 @@ def run_sweep(cfg, steps, warmup, prec):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     bstar = near_optimal_beta(betas, its, rhos)
+    systems = sum(x["coarse_systems"] for x in stats)
     launches = sum(x["coarse_solves"] for x in stats)
-    cs_ms = sum(x["coarse_solve_ms"] for x in stats) / max(launches, 1)
+    cs_ms = sum(x["coarse_solve_ms"] for x in stats) / max(systems, 1)
     vcyc = sum(x["vcycles"] for x in stats)
-    nrhs_per_launch = vcyc / max(launches, 1)
     return dict(seconds=dt, solves=steps * len(betas) * nr, its=its, bstar=bstar,
                 sigma=2 + math.log(bstar) / math.log(k), group=gsize, setup_s=setup_s,
-                coarse_ms=cs_ms, coarse_launches=launches, nrhs_per_launch=nrhs_per_launch,
-                coarse_bytes=sum(x["coarse_bytes"] for x in stats) / max(launches, 1),
+                coarse_ms=cs_ms, coarse_systems=systems, launches_per_system=launches / max(systems, 1),
+                coarse_bytes=sum(x["coarse_bytes"] for x in stats) / max(systems, 1),
                 factor_ms=sum(x["factor_ms"] for x in stats) / max(len(stats), 1),
                 betas=betas, thetas=thetas, converged=conv)
 
@@ -615,6 +619,96 @@ def main_search(a):
     print(json.dumps(out), flush=True)
 
 
+def pn_stencil_rates(pr, reps=20):
+    """Live device time of the per-point (heterogeneous k) fine passes of a P1 problem, against
+    their algorithmic bytes."""
+    import torch
+    from paper_2104_01439_amd import inputs
+    from paper_2104_01439_amd.roofline import STENCIL_PN_BYTES_PER_DOF_P1 as B
+    x = torch.from_numpy(inputs.random_complex(pr.N, seed=5)).cuda()
+    f = torch.from_numpy(inputs.random_complex(pr.N, seed=6)).cuda()
+    yf = pr.empty()
+    out = {}
+    for name, (op, b, bpd) in {"A0 apply": ("A0", None, B["a0_apply"]),
+                               "Jacobi sweep": ("JACOBI", f, B["jacobi_sweep"])}.items():
+        for _ in range(3):
+            pr.apply(op, x, b, y=yf)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            pr.apply(op, x, b, y=yf)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = bpd * pr.N / (ms * 1e-3) / 1e9
+        out[name] = {"us": 1e3 * ms, "bytes_per_dof": bpd, "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS}
+    return out
+
+
+def main_wedge(a):
+    """Heterogeneous wavenumber (Sec. 6 setting): the wedge profile k = k_max mu(x), the point
+    source at (0.5, 0.55), g = 0, one problem per shift policy eps in {k, k^1.5, k^2,
+    k^sigma_p(k)} applied per cell; FGMRES(50) to 1e-8, at most 500 iterations. value: solves/s
+    with the map's shift."""
+    import torch
+    from paper_2104_01439_amd import hz, inputs, shiftmap
+
+    torch.cuda.set_device(0)
+    cfg = inputs.CFG_WEDGE
+    n, p, h = cfg["n"], cfg["p"], 1.0 / cfg["n"]
+    kc = cfg["kmax"] * inputs.wedge_mu(n)
+    rows, stencils = {}, None
+    for pol in ("k", "k1.5", "k2", "map"):
+        sc = shiftmap.cell_shifts(kc, h, p, pol)
+        log(f"wedge: policy {pol}: creating (P{p}, h = 1/{n}, k_max {cfg['kmax']}) ...")
+        t0 = time.perf_counter()
+        pr = hz.Problem.cells(kc, sc, h, p, nu=cfg["nu"], omega=cfg["omega"],
+                              restart=cfg["restart"], maxit=500, tol=cfg["tol"], timing=True)
+        setup = time.perf_counter() - t0
+        F = pr.gaussian_rhs(cfg["source"])
+        for _ in range(a.warmup):
+            pr.solve(F, history=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            u, r = pr.solve(F, history=False)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.steps
+        st = pr.stats()
+        rows[pol] = {"iterations": r["iterations"], "converged": r["converged"],
+                     "rel_res_true": r["rel_res_true"], "setup_s": setup,
+                     "factor_ms": st["factor_ms"], "solve_s": dt}
+        log(f"  {r['iterations']} iterations, {dt:.3f} s per solve, set-up {setup:.2f} s")
+        if pol == "map":
+            stencils = pn_stencil_rates(pr)
+        pr.close()
+    m = rows["map"]
+    out = {
+        "metric": "FGMRES solves/s",
+        "value": 1.0 / m["solve_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * m["solve_s"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic three-layer wedge profile, Gaussian point source, g = 0",
+        "config": {"workload": cfg["name"], "kmax": cfg["kmax"], "n": n, "p": p,
+                   "source": list(cfg["source"]), "tol": cfg["tol"], "restart": cfg["restart"],
+                   "maxit": 500, "shift": "eps = k^sigma_p(k, ell) per cell"},
+        "policies": rows,
+        "stencil_passes_per_point": stencils,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    release()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -642,6 +736,8 @@ def main():
         return main_serving(a)
     if a.workload == "shift_search":
         return main_search(a)
+    if a.workload == inputs.CFG_WEDGE["name"]:
+        return main_wedge(a)
     if a.workload == inputs.CFG_MIXED["name"] and a.prec == "compare":
         return main_precision(a, inputs.CFG_MIXED)
     if a.workload == inputs.CFG_SWEEP["name"]:
@@ -659,7 +755,7 @@ def main():
         log(f"cpu baseline: projected {cpu['projected_s_per_solve']:.0f} s per solve "
             f"({cpu['cores']} threads), {cpu['one_thread']['projected_s_per_solve']:.0f} s "
             "on one thread")
-    fflop = factor_flops(cfg["n"], cfg["p"])
+    fflop = g["factor_flop"]
     ftf = fflop / (g["factor_ms"] * 1e-3) / 1e12
     cs_gbs = g["coarse_bytes"] / (g["coarse_ms"] * 1e-3) / 1e9
     out = {
@@ -679,17 +775,19 @@ def main():
                    "shift": str(cfg["s"]), "tol": cfg["tol"], "restart": cfg["restart"],
                    "nu": cfg["nu"], "omega": cfg["omega"], "precision": a.prec,
                    "iterations": g["iterations"]},
-        "roofline": {"kernel": "coarse block triangular solve (k_csolve)", "bound": "hbm",
+        "roofline": {"kernel": "multifrontal coarse solve (k_mf_solve, one launch per tree "
+                               "height and pass; unit: one coarse system)", "bound": "hbm",
                      "achieved": cs_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": cs_gbs / HBM_PEAK_GBS,
                      "traffic": measured_traffic() if (cfg["name"] == "p1_k400_n2048" and
                                                        a.prec == "fp64") else None,
-                     "bytes_per_launch": g["coarse_bytes"], "avg_launch_ms": g["coarse_ms"],
-                     "launches": g["coarse_launches"]},
+                     "bytes_per_system": g["coarse_bytes"], "ms_per_system": g["coarse_ms"],
+                     "systems": g["coarse_systems"],
+                     "launches_per_system": g["launches_per_system"]},
         "setup_factor_ms": g["factor_ms"],
-        "factorisation": {"kernel": "coarse block factorisation (Schur complements, "
-                                    "Gauss-Jordan panels and FP64 MFMA updates)",
-                          "bound": "mfma", "ms": g["factor_ms"], "flop": fflop,
+        "factorisation": {"kernel": "multifrontal factorisation (front assembly, extend-add, "
+                                    "Gauss-Jordan and FP64 MFMA sweep inverses, complex GEMMs)",
+                          "bound": "fp64", "ms": g["factor_ms"], "flop": fflop,
                           "achieved_tflops": ftf, "peak_tflops": FP64_MFMA_PEAK_TFLOPS,
                           "frac": ftf / FP64_MFMA_PEAK_TFLOPS},
         "stencil_passes": stencils,
@@ -729,12 +827,13 @@ def main_sweep(a, cfg):
                    "shifts": len(g["betas"]), "angles": len(g["thetas"]), "tol": cfg["tol"],
                    "restart": cfg["restart"], "nu": cfg["nu"], "omega": cfg["omega"],
                    "precision": a.prec, "shifts_per_batch": g["group"]},
-        "roofline": {"kernel": "coarse block triangular solves, several shifts x RHS per launch (k_csolve)",
+        "roofline": {"kernel": "multifrontal coarse solves, several shifts x right-hand sides "
+                               "per launch (k_mf_solve; unit: one coarse system)",
                      "bound": "hbm", "achieved": cs_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": cs_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": g["coarse_bytes"], "avg_launch_ms": g["coarse_ms"],
-                     "launches": g["coarse_launches"],
-                     "solves_per_launch": g["nrhs_per_launch"]},
+                     "bytes_per_system": g["coarse_bytes"], "ms_per_system": g["coarse_ms"],
+                     "systems": g["coarse_systems"],
+                     "launches_per_system": g["launches_per_system"]},
         "setup_factor_ms": g["factor_ms"],
         "sweep": {"beta_star": g["bstar"], "sigma_star": g["sigma"],
                   "mean_iterations_per_beta": [float(np.mean(x)) for x in g["its"]],

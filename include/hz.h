@@ -88,13 +88,17 @@ typedef struct {
  * solve books the coarse-solve launches of all its problems on its first problem. */
 typedef struct {
   long vcycles;              /* V-cycles run by solves and by hz_apply(HZ_OP_VCYCLE)      */
-  long coarse_solves;        /* launches of the coarse block-triangular solve kernel       */
-  double coarse_solve_ms;    /* their summed device time (HIP events around each launch)  */
+  long coarse_solves;        /* kernel launches of the coarse direct solves                */
+  double coarse_solve_ms;    /* their summed device time (HIP events around each solve)   */
   double factor_ms;          /* device time of the coarse assembly and factorisation       */
-  double coarse_bytes;       /* algorithmic bytes of those launches: each solved system's
-                                factor read twice (last block once) plus 3 coarse vectors
-                                per right-hand side                                         */
+  double coarse_bytes;       /* algorithmic bytes of those solves: every stored factor
+                                entry read once (multifrontal: S and G^T forward, G
+                                backward; block-tridiagonal: each inverse twice, the last
+                                once) plus 3 coarse vectors per right-hand side             */
   long graph_rounds;         /* FGMRES rounds replayed from a captured HIP graph           */
+  long coarse_systems;       /* coarse systems solved (right-hand sides of those solves)   */
+  double factor_flop;        /* algorithmic flops of the factorisation (complex
+                                multiply-adds of the inverses and products, 8 flops each)  */
 } hz_stats;
 
 /* Operators exposed by hz_apply (parity hooks; all act on the problem's own data). Each is one
@@ -211,9 +215,9 @@ hz_status hz_apply(const hz_problem* pr, int op, const hz_c64* d_x, const hz_c64
  * arguments, layouts, results (the same kernels with the same arithmetic) and errors as
  * hz_apply, plus:
  *   * the kernels' scratch (V-cycle iterates, residual, coarse vectors, the coarse solve's
- *     forward-sweep buffer and timeout flag, FP32 staging) lives in one fixed device array
+ *     update vectors and timeout flag, FP32 staging) lives in one fixed device array
  *     of 64 MiB per GPU, held from the first call on that GPU until the process ends; a
- *     problem needing more (above about 1.1 M fine dofs in FP64, 0.98 M in HZ_MIXED) is
+ *     problem needing more (above about 0.96 M fine dofs in FP64, 0.86 M in HZ_MIXED for P1) is
  *     rejected with HZ_EINVAL and a message giving both sizes;
  *   * HZ_MIXED needs the problem's FP32 coarse factor to exist already (a problem created
  *     with HZ_MIXED, or one mixed hz_apply / hz_solve earlier), else HZ_EINVAL;

@@ -634,6 +634,13 @@ double mf_job_bytes(const MfSym& y, size_t item, int nrhs) {
   return double(y.numel) * item + 3.0 * mc2 * item * nrhs;
 }
 
+// Block-tridiagonal factor: per block j the Schur complement products and the inverse of the
+// (p Mc)^2 block, about 3 (p Mc)^3 complex multiply-adds.
+double band_factor_flop(const CoarseLayout& L) {
+  const double b = double(L.p) * L.Mc;
+  return 8.0 * 3.0 * b * b * b * L.nc;
+}
+
 double csolve_job_bytes(const CoarseLayout& L, size_t item, int nrhs) {
   const double mc2 = double(L.Mc) * L.Mc;
   return (2.0 * double(L.total()) - mc2) * item + 3.0 * mc2 * item * nrhs;
@@ -662,6 +669,7 @@ void timed_coarse_jobs(hz_problem* pr, const CoarseJob<T>* jobs, int njobs, hipS
     pr->stats.coarse_solves += coarse_solve_jobs<T>(pr->L, jobs, njobs, pr->Nc, cw->err,
                                                     cw->persistent, st);
   pr->stats.coarse_bytes += bytes;
+  for (int i = 0; i < njobs; ++i) pr->stats.coarse_systems += jobs[i].nrhs;
   if (timed) {
     HZ_HIP(hipEventRecord(e.second, st));
     pr->ev_pending.push_back(e);
@@ -1688,6 +1696,7 @@ hz_status finish_create(hz_problem* pr, hipStream_t st, clk::time_point t0, hz_p
         delete pr;
         return fail(fs, "zero or non-finite pivot in the coarse factorisation");
       }
+      pr->stats.factor_flop = pr->sym ? pr->sym->flop : band_factor_flop(pr->L);
     }
     pr->cw.g = pr->mem.alloc<double2>(4 * size_t(pr->G));
     pr->cw.err = pr->mem.alloc<int>(64);
@@ -1932,9 +1941,10 @@ hz_status hz_problem_stats(hz_problem* pr, hz_stats* out, int reset) {
     collect_timing(pr, true);
     *out = pr->stats;
     if (reset) {
-      const double f = pr->stats.factor_ms;
+      const double f = pr->stats.factor_ms, ff = pr->stats.factor_flop;
       pr->stats = hz_stats{};
       pr->stats.factor_ms = f;
+      pr->stats.factor_flop = ff;
     }
     return HZ_OK;
   } catch (...) {

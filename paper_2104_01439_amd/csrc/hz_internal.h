@@ -222,6 +222,7 @@ struct MfSym {
   std::vector<int> parent, height;
   std::vector<int> I, B, map;
   long numel = 0, uel = 0;                // factor elements, update elements per right-hand side
+  double flop = 0;                        // factorisation: 8 (s^3 + 2 s^2 m + m^2 s) per node
   std::vector<std::vector<int>> at;       // nodes of each height
   std::vector<int> hn;                    // the same, concatenated by height
   std::vector<MfTask> fwd, bwd;           // solve tasks, grouped by height

@@ -143,6 +143,10 @@ void build_symbolic(MfSym& S, int p, int nc) {
     nd.uoff = U;
     U += nd.m;
     S.maxf = std::max(S.maxf, nd.s + nd.m);
+    {
+      const double ds = nd.s, dm = nd.m;
+      S.flop += 8.0 * (ds * ds * ds + 2.0 * ds * ds * dm + dm * dm * ds);
+    }
     S.I.insert(S.I.end(), b.Ipts[v].begin(), b.Ipts[v].end());
     S.B.insert(S.B.end(), b.Bpts[v].begin(), b.Bpts[v].end());
   }

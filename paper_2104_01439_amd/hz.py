@@ -36,7 +36,8 @@ class Options(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("vcycles", ctypes.c_long), ("coarse_solves", ctypes.c_long),
                 ("coarse_solve_ms", ctypes.c_double), ("factor_ms", ctypes.c_double),
-                ("coarse_bytes", ctypes.c_double), ("graph_rounds", ctypes.c_long)]
+                ("coarse_bytes", ctypes.c_double), ("graph_rounds", ctypes.c_long),
+                ("coarse_systems", ctypes.c_long), ("factor_flop", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

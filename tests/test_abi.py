@@ -46,11 +46,13 @@ def test_footprint_model(hz):
     assert hz.footprint_estimate(10.0, 1 / 63, 1) == 0
     assert hz.footprint_estimate(10.0, 1 / 64, 4) == 0
     assert hz.footprint_estimate(-1.0, 1 / 64, 1) == 0
-    # FP64 P1 n=2048: factor 1024 blocks of 1025^2 + one 1025^2 block, 16 B each
+    # FP64 P1 n=2048: Krylov basis and preconditioned vectors, (51 + 50) fine vectors, plus
+    # the multifrontal coarse factor (about 1.2e8 complex entries, 16 B each: far below the
+    # 1025 x 1025 x 1025 x 16 B = 17.2 GB of dense block inverses of the block-tridiagonal
+    # factor)
     fp = hz.footprint_estimate(400.0, 1 / 2048, 1, prec="fp64")
-    factor = (1024 * 1025 ** 2 + 1025 ** 2) * 16
     krylov = (51 + 50) * 2049 ** 2 * 16
-    assert factor + krylov < fp < factor + krylov + 1.0e9
+    assert krylov + 1.5e9 < fp < krylov + 3.5e9
     fm = hz.footprint_estimate(400.0, 1 / 2048, 1, prec="mixed")
     assert fm < fp
     # grows with n and p
@@ -62,11 +64,12 @@ def test_batch_workspace_model(hz):
     assert hz.batch_workspace_bytes(1 / 63, 1, 2, 4) == 0
     assert hz.batch_workspace_bytes(1 / 64, 1, 0, 4) == 0
     # P2 n=512: per solve V (51) + Z (50) + r, w, F, u, V-cycle scratch (3 fine, 2 coarse
-    # vectors) and a coarse forward-sweep buffer, FP64
+    # vectors) and the coarse solve's work (the multifrontal update vectors: between one and
+    # four coarse vectors), FP64
     N, Nc = 1025 ** 2, 513 ** 2
     b = hz.batch_workspace_bytes(1 / 512, 2, 8, 4, prec="fp64")
-    per = (51 + 50 + 4 + 3) * N * 16 + 3 * Nc * 16
-    assert 32 * per < b < 32 * per + 1e8
+    per = (51 + 50 + 4 + 3) * N * 16 + 2 * Nc * 16
+    assert 32 * (per + Nc * 16) <= b < 32 * (per + 4 * Nc * 16) + 1e8
     assert hz.batch_workspace_bytes(1 / 512, 2, 8, 4, prec="mixed") < b
     assert hz.batch_workspace_bytes(1 / 512, 2, 8, 4) > hz.batch_workspace_bytes(1 / 512, 2, 4, 4)
 
