@@ -283,7 +283,8 @@ bool use_mf() {
 
 // Bytes of the device copy of a symbolic factor (nodes, point lists, maps, tasks, view).
 size_t mf_sym_bytes(const MfSym& y) {
-  return y.nodes.size() * sizeof(MfNode) + (y.I.size() + y.B.size() + y.map.size() + y.hn.size()) * 4 +
+  return y.nodes.size() * sizeof(MfNode) +
+         (y.I.size() + y.B.size() + y.map.size() + y.hn.size() + y.inv.size()) * 4 +
          (y.fwd.size() + y.bwd.size()) * sizeof(MfTask) + sizeof(MfView) + 8 * 256;
 }
 
@@ -454,8 +455,8 @@ void upload_symbolic(hz_problem* pr, hipStream_t st) {
   const size_t bn = al(y.nodes.size() * sizeof(MfNode)), bI = al(y.I.size() * 4),
                bB = al(y.B.size() * 4), bm = al(y.map.size() * 4), bh = al(y.hn.size() * 4),
                bf = al(y.fwd.size() * sizeof(MfTask)), bb = al(y.bwd.size() * sizeof(MfTask)),
-               bv = al(sizeof(MfView));
-  const size_t tot = bn + bI + bB + bm + bh + bf + bb + bv;
+               bi = al(y.inv.size() * 4), bv = al(sizeof(MfView));
+  const size_t tot = bn + bI + bB + bm + bh + bf + bb + bi + bv;
   char* d = pr->mem.alloc<char>(tot);
   std::vector<char> h(tot, 0);
   MfView v;
@@ -473,6 +474,7 @@ void upload_symbolic(hz_problem* pr, hipStream_t st) {
   v.hn = reinterpret_cast<const int*>(put(y.hn.data(), y.hn.size() * 4, bh));
   v.fwd = reinterpret_cast<const MfTask*>(put(y.fwd.data(), y.fwd.size() * sizeof(MfTask), bf));
   v.bwd = reinterpret_cast<const MfTask*>(put(y.bwd.data(), y.bwd.size() * sizeof(MfTask), bb));
+  v.inv = reinterpret_cast<const int*>(put(y.inv.data(), y.inv.size() * 4, bi));
   pr->dmf = reinterpret_cast<MfView*>(const_cast<char*>(put(&v, sizeof(MfView), bv)));
   HZ_HIP(hipMemcpyAsync(d, h.data(), tot, hipMemcpyHostToDevice, st));
   HZ_HIP(hipStreamSynchronize(st));   // h is local

@@ -208,6 +208,8 @@ struct MfNode {
   long Soff = 0, Goff = 0, GToff = 0;   // S (s x s), G (s x m), G^T (m x s) in the factor
   long uoff = 0;               // update vector (m) in the per-right-hand-side work
   long mapoff = -1;            // front positions in the parent of this node's B points
+  long invoff = -1;            // per front position: the child 0 and child 1 entries landing
+                               // there (2 ints, -1 for none), for nodes with children
 };
 // One unit of a solve pass at one tree height: rows [r0, r1) of matrix `kind` of node v
 // (kind 0: S, 1: G^T for the forward pass; 2: G for the backward pass; one wave per row), or
@@ -220,7 +222,7 @@ struct MfSym {
   int p = 1, nc = 0, Mc = 0, H = 0;
   std::vector<MfNode> nodes;              // postorder: children before their parent
   std::vector<int> parent, height;
-  std::vector<int> I, B, map;
+  std::vector<int> I, B, map, inv;
   long numel = 0, uel = 0;                // factor elements, update elements per right-hand side
   double flop = 0;                        // factorisation: 8 (s^3 + 2 s^2 m + m^2 s) per node
   std::vector<std::vector<int>> at;       // nodes of each height
@@ -229,6 +231,8 @@ struct MfSym {
   std::vector<int> fwd0, bwd0;            // first task of each height (H + 2 entries)
   int maxf = 0;                           // largest s + m
   std::vector<int> fmax, bmax;            // per height: largest s + m, m of a non-small node
+  std::vector<char> fbig, bbig;           // per height: prefetch rows (all tasks one wave per
+                                          // row, and at most 768 of them)
 };
 // The (cached) symbolic factor of the coarse lattice of order p with nc cells per side.
 const MfSym& mf_symbolic(int p, int nc);
@@ -241,6 +245,7 @@ struct MfView {
   const MfTask* fwd = nullptr;
   const MfTask* bwd = nullptr;
   const int* hn = nullptr;
+  const int* inv = nullptr;
 };
 
 template <typename T> struct CoarseJob {

@@ -161,14 +161,21 @@ void build_symbolic(MfSym& S, int p, int nc) {
     pos.reserve(size_t(nd.s + nd.m) * 2);
     for (int i = 0; i < nd.s; ++i) pos[b.Ipts[v][i]] = i;
     for (int k = 0; k < nd.m; ++k) pos[b.Bpts[v][k]] = nd.s + k;
+    const long inv0 = long(S.inv.size());
+    S.inv.resize(S.inv.size() + 2 * size_t(nd.s + nd.m), -1);
+    S.nodes[v].invoff = inv0;
+    int slot = 0;
     for (int c : {nd.ch0, nd.ch1}) {
       MfNode& cn = S.nodes[c];
       cn.mapoff = long(S.map.size());
+      int j = 0;
       for (int g : b.Bpts[c]) {
         auto it = pos.find(g);
         if (it == pos.end()) throw std::runtime_error("multifrontal: ring point not in parent front");
         S.map.push_back(it->second);
+        S.inv[inv0 + 2 * it->second + slot] = j++;
       }
+      ++slot;
     }
   }
   // nodes by height (also flat, for the small-node tasks), solve tasks by height
@@ -221,6 +228,19 @@ void build_symbolic(MfSym& S, int p, int nc) {
   S.bwd0[S.H + 1] = int(S.bwd.size());
   S.fmax.assign(S.H + 1, 0);
   S.bmax.assign(S.H + 1, 0);
+  S.fbig.assign(S.H + 1, 1);
+  S.bbig.assign(S.H + 1, 1);
+  for (int v = 0; v < nn; ++v) {
+    const MfNode& nd = S.nodes[v];
+    if (is_small(v) || nd.s <= 64) S.fbig[S.height[v]] = 0;
+    if (is_small(v)) S.bbig[S.height[v]] = 0;
+  }
+  // the row prefetch costs occupancy (about 180 registers): worth it only where a height has
+  // few workgroups to overlap (at most 3 per compute unit)
+  for (int h = 0; h <= S.H; ++h) {
+    if (S.fwd0[h + 1] - S.fwd0[h] > 768) S.fbig[h] = 0;
+    if (S.bwd0[h + 1] - S.bwd0[h] > 768) S.bbig[h] = 0;
+  }
   for (int v = 0; v < nn; ++v) {
     const MfNode& nd = S.nodes[v];
     if (is_small(v)) continue;
@@ -621,6 +641,9 @@ hz_status mf_factor(const MfSym& sym, const MfView& mv, const DevOp<double>& cop
 
 namespace {
 
+// Column groups of 64 requested ahead per wave on the large-node heights (rows up to 1536).
+constexpr int kMfPf = 24;
+
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -629,9 +652,13 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
 
 // One launch per tree height and pass; workgroup (task, job, right-hand-side group). Large
 // nodes: the workgroup assembles the node's front vector in LDS and each wave forms rows of
-// one matrix (lanes over the columns, then a butterfly sum). Small nodes (s + m <= 64): one
-// wave per node, lane r forms row r (lanes read consecutive entries of a stored row).
-template <typename T, int NR, bool FWD>
+// one matrix (lanes over the columns, then a butterfly sum); with PF > 0 (heights whose tasks
+// are all of that kind) each wave requests the first PF column groups of its first row before
+// the front vector is gathered, so that the row streams in while the gather waits. Small nodes
+// (s + m <= 64): one wave per node, lane r forms row r (lanes read consecutive entries of a
+// stored row). The front vector is f_i = (b at I_v, or 0) + child 0's u + child 1's u at
+// position i, in that order, through the node's inverse maps.
+template <typename T, int NR, bool FWD, int PF>
 __global__ void __launch_bounds__(256)
 k_mf_solve(CsJobs<T> jobs, int task0, long cstride) {
   extern __shared__ char smem[];
@@ -651,117 +678,131 @@ k_mf_solve(CsJobs<T> jobs, int task0, long cstride) {
   if (t.kind <= 2 || t.kind == 5) {
     const MfNode nd = mv.nodes[t.v];
     const int s = nd.s, m = nd.m, w = s + m;
+    const V2<T>* X = Fac + (t.kind == 0 ? nd.Soff : t.kind == 1 ? nd.GToff : nd.Goff);
+    const int len = t.kind == 2 ? m : s;                // row length of the matrix
+    const int vl = FWD ? w : m;                          // LDS vector per right-hand side
+    V2<T> pre[PF > 0 ? PF : 1];
+    if constexpr (PF > 0) {
+      const int r = t.r0 + wave;
+      const V2<T>* xr = X + long(r) * len;
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        const int k = lane + 64 * q;
+        pre[q] = (r < t.r1 && k < len) ? xr[k] : czero<T>();
+      }
+    }
     if (FWD) {
-      for (int i = threadIdx.x; i < w; i += 256)
-        for (int h = 0; h < nr; ++h)
-          f[h * w + i] = i < s ? b[h * cstride + mv.I[nd.Ioff + i]] : czero<T>();
-      __syncthreads();
-      for (int slot = 0; slot < 2; ++slot) {
-        const int c = slot == 0 ? nd.ch0 : nd.ch1;
-        if (c >= 0) {
-          const MfNode cn = mv.nodes[c];
-          for (int j = threadIdx.x; j < cn.m; j += 256) {
-            const int pos = mv.map[cn.mapoff + j];
-            for (int h = 0; h < nr; ++h) {
-              const V2<T> uv = u[h * us + cn.uoff + j];
-              f[h * w + pos].x += uv.x;
-              f[h * w + pos].y += uv.y;
-            }
+      const bool kids = nd.invoff >= 0;
+      const long u0 = kids ? mv.nodes[nd.ch0].uoff : 0, u1 = kids ? mv.nodes[nd.ch1].uoff : 0;
+      for (int i = threadIdx.x; i < w; i += 256) {
+        const int j0 = kids ? mv.inv[nd.invoff + 2 * i] : -1;
+        const int j1 = kids ? mv.inv[nd.invoff + 2 * i + 1] : -1;
+        const int gi = i < s ? mv.I[nd.Ioff + i] : 0;
+        for (int h = 0; h < nr; ++h) {
+          V2<T> v = i < s ? b[h * cstride + gi] : czero<T>();
+          if (j0 >= 0) {
+            const V2<T> a = u[h * us + u0 + j0];
+            v.x += a.x;
+            v.y += a.y;
           }
+          if (j1 >= 0) {
+            const V2<T> a = u[h * us + u1 + j1];
+            v.x += a.x;
+            v.y += a.y;
+          }
+          f[h * w + i] = v;
         }
-        __syncthreads();
       }
-      if (t.kind == 5) {
-        // thread per row: rows r < s of S (symmetric: walk row k, entry r), rows s + r' of
-        // G^T f_I (walk row i of G, entry r'); consecutive threads read consecutive entries
-        const int r = t.r0 + int(threadIdx.x);
-        if (r < t.r1) {
-          V2<T> acc[NR];
-#pragma unroll
-          for (int h = 0; h < NR; ++h) acc[h] = czero<T>();
-          const bool zr = r < s;
-          const V2<T>* X = zr ? Fac + nd.Soff + r : Fac + nd.Goff + (r - s);
-          const int ld = zr ? s : m;
-          for (int k = 0; k < s; ++k) {
-            const V2<T> xv = X[long(k) * ld];
-#pragma unroll
-            for (int h = 0; h < NR; ++h)
-              if (h < nr) cfma(acc[h], xv, f[h * w + k]);
-          }
-          for (int h = 0; h < nr; ++h) {
-            if (zr) {
-              y[h * cstride + mv.I[nd.Ioff + r]] = acc[h];
-            } else {
-              const V2<T> fb = f[h * w + r];
-              V2<T> o;
-              o.x = fb.x - acc[h].x;
-              o.y = fb.y - acc[h].y;
-              u[h * us + nd.uoff + (r - s)] = o;
-            }
-          }
-        }
-        return;
-      }
-      const V2<T>* X = Fac + (t.kind == 0 ? nd.Soff : nd.GToff);
-      for (int r = t.r0 + wave; r < t.r1; r += 4) {
+    } else {
+      for (int k = threadIdx.x; k < m; k += 256)
+        for (int h = 0; h < nr; ++h) f[h * m + k] = y[h * cstride + mv.B[nd.Boff + k]];
+    }
+    __syncthreads();
+    if (FWD && t.kind == 5) {
+      // thread per row: rows r < s of S (symmetric: walk row k, entry r), rows s + r' of
+      // G^T f_I (walk row i of G, entry r'); consecutive threads read consecutive entries
+      const int r = t.r0 + int(threadIdx.x);
+      if (r < t.r1) {
         V2<T> acc[NR];
 #pragma unroll
         for (int h = 0; h < NR; ++h) acc[h] = czero<T>();
-        const V2<T>* xr = X + long(r) * s;
-        for (int k = lane; k < s; k += 64) {
-          const V2<T> xv = xr[k];
+        const bool zr = r < s;
+        const V2<T>* Xc = zr ? Fac + nd.Soff + r : Fac + nd.Goff + (r - s);
+        const int ld = zr ? s : m;
+        for (int k = 0; k < s; ++k) {
+          const V2<T> xv = Xc[long(k) * ld];
 #pragma unroll
           for (int h = 0; h < NR; ++h)
             if (h < nr) cfma(acc[h], xv, f[h * w + k]);
         }
 #pragma unroll
         for (int h = 0; h < NR; ++h) {
-          acc[h].x = wave_sum(acc[h].x);
-          acc[h].y = wave_sum(acc[h].y);
-        }
-        if (lane == 0)
-          for (int h = 0; h < nr; ++h) {
-            if (t.kind == 0) {
-              y[h * cstride + mv.I[nd.Ioff + r]] = acc[h];
-            } else {
-              const V2<T> fb = f[h * w + s + r];
-              V2<T> o;
-              o.x = fb.x - acc[h].x;
-              o.y = fb.y - acc[h].y;
-              u[h * us + nd.uoff + r] = o;
-            }
+          if (h >= nr) continue;
+          if (zr) {
+            y[h * cstride + mv.I[nd.Ioff + r]] = acc[h];
+          } else {
+            const V2<T> fb = f[h * w + r];
+            V2<T> o;
+            o.x = fb.x - acc[h].x;
+            o.y = fb.y - acc[h].y;
+            u[h * us + nd.uoff + (r - s)] = o;
           }
-      }
-    } else {
-      for (int k = threadIdx.x; k < m; k += 256)
-        for (int h = 0; h < nr; ++h) f[h * m + k] = y[h * cstride + mv.B[nd.Boff + k]];
-      __syncthreads();
-      const V2<T>* X = Fac + nd.Goff;
-      for (int r = t.r0 + wave; r < t.r1; r += 4) {
-        V2<T> acc[NR];
-#pragma unroll
-        for (int h = 0; h < NR; ++h) acc[h] = czero<T>();
-        const V2<T>* xr = X + long(r) * m;
-        for (int k = lane; k < m; k += 64) {
-          const V2<T> xv = xr[k];
-#pragma unroll
-          for (int h = 0; h < NR; ++h)
-            if (h < nr) cfma(acc[h], xv, f[h * m + k]);
         }
+      }
+      return;
+    }
+    bool first = true;
+    for (int r = t.r0 + wave; r < t.r1; r += 4) {
+      V2<T> acc[NR];
+#pragma unroll
+      for (int h = 0; h < NR; ++h) acc[h] = czero<T>();
+      const V2<T>* xr = X + long(r) * len;
+      int k0 = lane;
+      if constexpr (PF > 0) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+          const int k = lane + 64 * q;
+          if (k < len) {
+            const V2<T> xv = first ? pre[q] : xr[k];
+#pragma unroll
+            for (int h = 0; h < NR; ++h)
+              if (h < nr) cfma(acc[h], xv, f[h * vl + k]);
+          }
+        }
+        k0 = lane + 64 * PF;
+      }
+      for (int k = k0; k < len; k += 64) {
+        const V2<T> xv = xr[k];
+#pragma unroll
+        for (int h = 0; h < NR; ++h)
+          if (h < nr) cfma(acc[h], xv, f[h * vl + k]);
+      }
+      first = false;
+#pragma unroll
+      for (int h = 0; h < NR; ++h) {
+        acc[h].x = wave_sum(acc[h].x);
+        acc[h].y = wave_sum(acc[h].y);
+      }
+      if (lane == 0)
 #pragma unroll
         for (int h = 0; h < NR; ++h) {
-          acc[h].x = wave_sum(acc[h].x);
-          acc[h].y = wave_sum(acc[h].y);
-        }
-        if (lane == 0)
-          for (int h = 0; h < nr; ++h) {
+          if (h >= nr) continue;
+          if (!FWD) {
             const long gi = h * cstride + mv.I[nd.Ioff + r];
             V2<T> z = y[gi];
             z.x -= acc[h].x;
             z.y -= acc[h].y;
             y[gi] = z;
+          } else if (t.kind == 0) {
+            y[h * cstride + mv.I[nd.Ioff + r]] = acc[h];
+          } else {
+            const V2<T> fb = f[h * w + s + r];
+            V2<T> o;
+            o.x = fb.x - acc[h].x;
+            o.y = fb.y - acc[h].y;
+            u[h * us + nd.uoff + r] = o;
           }
-      }
+        }
     }
     return;
   }
@@ -803,7 +844,9 @@ k_mf_solve(CsJobs<T> jobs, int task0, long cstride) {
           for (int h = 0; h < NR; ++h)
             if (h < nr) cfma(acc[h], xv, fw[h * 64 + k]);
         }
-        for (int h = 0; h < nr; ++h) y[h * cstride + mv.I[nd.Ioff + lane]] = acc[h];
+#pragma unroll
+        for (int h = 0; h < NR; ++h)
+          if (h < nr) y[h * cstride + mv.I[nd.Ioff + lane]] = acc[h];
       } else {
         const int rr = lane - s;
         const V2<T>* Gv = Fac + nd.Goff;     // (G^T f_I)[rr] = sum_i G[i][rr] f[i]
@@ -813,7 +856,9 @@ k_mf_solve(CsJobs<T> jobs, int task0, long cstride) {
           for (int h = 0; h < NR; ++h)
             if (h < nr) cfma(acc[h], xv, fw[h * 64 + i]);
         }
-        for (int h = 0; h < nr; ++h) {
+#pragma unroll
+        for (int h = 0; h < NR; ++h) {
+          if (h >= nr) continue;
           const V2<T> fb = fw[h * 64 + s + rr];
           V2<T> o;
           o.x = fb.x - acc[h].x;
@@ -837,7 +882,9 @@ k_mf_solve(CsJobs<T> jobs, int task0, long cstride) {
         for (int h = 0; h < NR; ++h)
           if (h < nr) cfma(acc[h], xv, fw[h * 64 + k]);
       }
-      for (int h = 0; h < nr; ++h) {
+#pragma unroll
+      for (int h = 0; h < NR; ++h) {
+        if (h >= nr) continue;
         const long gi = h * cstride + mv.I[nd.Ioff + lane];
         V2<T> z = y[gi];
         z.x -= acc[h].x;
@@ -863,14 +910,18 @@ int mf_launch_all(const MfSym& sym, const CsJobs<T>& jj, int njobs, int maxr, lo
   for (int h = 0; h <= sym.H; ++h) {
     const int n = sym.fwd0[h + 1] - sym.fwd0[h];
     if (n > 0) {
-      k_mf_solve<T, NR, true><<<dim3(n, njobs, gz), 256, lds_of(h, true), st>>>(jj, sym.fwd0[h], cstride);
+      const dim3 g(n, njobs, gz);
+      if (sym.fbig[h]) k_mf_solve<T, NR, true, kMfPf><<<g, 256, lds_of(h, true), st>>>(jj, sym.fwd0[h], cstride);
+      else k_mf_solve<T, NR, true, 0><<<g, 256, lds_of(h, true), st>>>(jj, sym.fwd0[h], cstride);
       ++launches;
     }
   }
   for (int h = sym.H; h >= 0; --h) {
     const int n = sym.bwd0[h + 1] - sym.bwd0[h];
     if (n > 0) {
-      k_mf_solve<T, NR, false><<<dim3(n, njobs, gz), 256, lds_of(h, false), st>>>(jj, sym.bwd0[h], cstride);
+      const dim3 g(n, njobs, gz);
+      if (sym.bbig[h]) k_mf_solve<T, NR, false, kMfPf><<<g, 256, lds_of(h, false), st>>>(jj, sym.bwd0[h], cstride);
+      else k_mf_solve<T, NR, false, 0><<<g, 256, lds_of(h, false), st>>>(jj, sym.bwd0[h], cstride);
       ++launches;
     }
   }
@@ -884,9 +935,13 @@ void mf_set_lds(size_t bytes) {
   static size_t done = 0;
   std::lock_guard<std::mutex> g(mu);
   if (bytes <= done) return;
-  HZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_solve<T, NR, true>),
+  HZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_solve<T, NR, true, 0>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
-  HZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_solve<T, NR, false>),
+  HZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_solve<T, NR, false, 0>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+  HZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_solve<T, NR, true, kMfPf>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+  HZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_solve<T, NR, false, kMfPf>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
   done = bytes;
 }
