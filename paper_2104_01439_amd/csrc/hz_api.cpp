@@ -447,41 +447,11 @@ void upload_cells(hz_problem* pr, const double* k_cell, const hz_c64* s_cell, hi
   for (void* d : tmp) pr->mem.release_async(d, st);
 }
 
-// Device copy of the problem's symbolic multifrontal data: one allocation holding the nodes,
-// point lists, maps, node order, solve tasks and the view struct the kernels read.
+// The problem's view of its mesh class's symbolic multifrontal data (shared, per device).
 void upload_symbolic(hz_problem* pr, hipStream_t st) {
-  const MfSym& y = *pr->sym;
-  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t bn = al(y.nodes.size() * sizeof(MfNode)), bI = al(y.I.size() * 4),
-               bB = al(y.B.size() * 4), bm = al(y.map.size() * 4), bh = al(y.hn.size() * 4),
-               bf = al(y.fwd.size() * sizeof(MfTask)), bb = al(y.bwd.size() * sizeof(MfTask)),
-               bi = al(y.inv.size() * 4), bv = al(sizeof(MfView));
-  const size_t tot = bn + bI + bB + bm + bh + bf + bb + bi + bv;
-  char* d = pr->mem.alloc<char>(tot);
-  std::vector<char> h(tot, 0);
-  MfView v;
-  size_t o = 0;
-  auto put = [&](const void* src, size_t bytes, size_t span) {
-    std::memcpy(h.data() + o, src, bytes);
-    const char* at = d + o;
-    o += span;
-    return at;
-  };
-  v.nodes = reinterpret_cast<const MfNode*>(put(y.nodes.data(), y.nodes.size() * sizeof(MfNode), bn));
-  v.I = reinterpret_cast<const int*>(put(y.I.data(), y.I.size() * 4, bI));
-  v.B = reinterpret_cast<const int*>(put(y.B.data(), y.B.size() * 4, bB));
-  v.map = reinterpret_cast<const int*>(put(y.map.data(), y.map.size() * 4, bm));
-  v.hn = reinterpret_cast<const int*>(put(y.hn.data(), y.hn.size() * 4, bh));
-  v.fwd = reinterpret_cast<const MfTask*>(put(y.fwd.data(), y.fwd.size() * sizeof(MfTask), bf));
-  v.bwd = reinterpret_cast<const MfTask*>(put(y.bwd.data(), y.bwd.size() * sizeof(MfTask), bb));
-  v.inv = reinterpret_cast<const int*>(put(y.inv.data(), y.inv.size() * 4, bi));
-  pr->dmf = reinterpret_cast<MfView*>(const_cast<char*>(put(&v, sizeof(MfView), bv)));
-  HZ_HIP(hipMemcpyAsync(d, h.data(), tot, hipMemcpyHostToDevice, st));
-  HZ_HIP(hipStreamSynchronize(st));   // h is local
-  pr->hmf = v;
+  pr->dmf = mf_device_view(*pr->sym, &pr->hmf, st);
 }
 
-const MfView& host_view(const hz_problem* pr) { return pr->hmf; }
 
 template <typename T>
 void alloc_scratch(DevMem& mem, Scratch<T>& sc, int cap, long N, long Nc, bool with_ff) {
@@ -1670,7 +1640,7 @@ hz_status finish_create(hz_problem* pr, hipStream_t st, clk::time_point t0, hz_p
       hz_status fs;
       if (pr->sym) {
         int* flag = pr->mem.alloc_async<int>(1, st);
-        fs = mf_factor(*pr->sym, host_view(pr), cop, pr->S, flag, st);
+        fs = mf_factor(*pr->sym, cop, pr->S, flag, st);
         pr->mem.release_async(flag, st);
       } else {
         CoarseFactorWork wk;

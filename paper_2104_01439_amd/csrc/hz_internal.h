@@ -280,10 +280,14 @@ void launch_factor_to_f32(const double2* S, float2* Sf, size_t n, hipStream_t st
 // sweep (W: 2 sweep_panel_elems(n), R: 2 sweep_pinv_elems() elements of work); sets *flag on a
 // zero or non-finite pivot.
 void sweep_inverse(double2* X, int n, double2* W, double2* R, int* flag, hipStream_t st);
+// Device copy of the symbolic data (and of the factorisation's launch tables) of a mesh
+// class on the current device, built on first use with stream st and kept until the process
+// ends; returns the view on the device and, in host_copy, the same view held on the host.
+MfView* mf_device_view(const MfSym& sym, MfView* host_copy, hipStream_t st);
 // Multifrontal factorisation of the coarse operator cop into F (sym.numel elements) on the
 // device; returns HZ_OK or HZ_ESINGULAR.
-hz_status mf_factor(const MfSym& sym, const MfView& dv, const DevOp<double>& cop, double2* F,
-                    int* flag, hipStream_t st);
+hz_status mf_factor(const MfSym& sym, const DevOp<double>& cop, double2* F, int* flag,
+                    hipStream_t st);
 // Multifrontal solves of njobs jobs (one mesh class; b, y coarse vectors with stride cstride
 // per right-hand side, update vectors at gbuf with stride ustride). Returns the launch count.
 template <typename T>

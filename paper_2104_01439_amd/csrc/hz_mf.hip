@@ -19,6 +19,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <tuple>
 #include <mutex>
 #include <stdexcept>
 #include <unordered_map>
@@ -282,11 +283,11 @@ __device__ __forceinline__ double2 coarse_entry(const double2* __restrict__ coef
 template <int P>
 __global__ void __launch_bounds__(256)
 k_mf_front(MfView mv, const double2* __restrict__ coef, int pn, int Mc, const int2* __restrict__ rows,
-           double2* const* __restrict__ fptr) {
+           double2* __restrict__ arena, const long* __restrict__ foff) {
   const int2 t = rows[blockIdx.x];
   const MfNode nd = mv.nodes[t.x];
   const int s = nd.s, w = nd.s + nd.m, r = t.y;
-  double2* Fr = fptr[t.x] + long(r) * w;
+  double2* Fr = arena + foff[t.x] + long(r) * w;
   const int gr = r < s ? mv.I[nd.Ioff + r] : mv.B[nd.Boff + r - s];
   for (int c = threadIdx.x; c < w; c += 256) {
     double2 v = make_double2(0.0, 0.0);
@@ -302,14 +303,14 @@ k_mf_front(MfView mv, const double2* __restrict__ coef, int pn, int Mc, const in
 // One child slot per launch (the two children of a node may hit the same entries).
 __global__ void __launch_bounds__(256)
 k_mf_extend(MfView mv, const int* __restrict__ parent, const int2* __restrict__ rows,
-            double2* const* __restrict__ fptr) {
+            double2* __restrict__ arena, const long* __restrict__ foff) {
   const int2 t = rows[blockIdx.x];
   const int c = t.x, j = t.y, v = parent[c];
   const MfNode cn = mv.nodes[c], pnd = mv.nodes[v];
   const int wc = cn.s + cn.m, wp = pnd.s + pnd.m;
-  const double2* U = fptr[c] + long(cn.s + j) * wc + cn.s;
+  const double2* U = arena + foff[c] + long(cn.s + j) * wc + cn.s;
   const int* map = mv.map + cn.mapoff;
-  double2* Fp = fptr[v] + long(map[j]) * wp;
+  double2* Fp = arena + foff[v] + long(map[j]) * wp;
   for (int k = threadIdx.x; k < cn.m; k += 256) {
     const double2 u = U[k];
     double2 f = Fp[map[k]];
@@ -323,14 +324,14 @@ k_mf_extend(MfView mv, const int* __restrict__ parent, const int2* __restrict__ 
 // on the upper triangle mirrored (every pivot X[t][t] -> -1/p, row and column t scaled by 1/p,
 // the rest X[r][c] -= X[r][t] X[t][c] / p), leaving -F_II^{-1}.
 __global__ void __launch_bounds__(256)
-k_mf_gj(MfView mv, const int* __restrict__ list, double2* const* __restrict__ fptr,
-        double2* __restrict__ Fac, int* flag) {
+k_mf_gj(MfView mv, const int* __restrict__ list, const double2* __restrict__ arena,
+        const long* __restrict__ foff, double2* __restrict__ Fac, int* flag) {
   extern __shared__ double2 X[];
   __shared__ double2 rowt[64], colt[64];
   const int v = list[blockIdx.x];
   const MfNode nd = mv.nodes[v];
   const int s = nd.s, w = nd.s + nd.m, ld = s + 1;
-  const double2* Fv = fptr[v];
+  const double2* Fv = arena + foff[v];
   for (int idx = threadIdx.x; idx < s * s; idx += 256) {
     const int r = idx / s, c = idx - r * s;
     X[r * ld + c] = Fv[long(min(r, c)) * w + max(r, c)];
@@ -385,18 +386,28 @@ k_mf_copy_ii(const double2* __restrict__ Fv, int s, int w, double2* __restrict__
 // Batched complex GEMM of varying sizes: C = A B (sub = 0) or C -= A B (sub = 1), all row-major.
 // 64 x 64 output tiles, 256 threads in a 16 x 16 grid with 4 x 4 outputs each, k in steps of 8
 // staged in LDS; each output sums its k terms in ascending order.
+// Operands are offsets into the factor (F) or the front arena (W): flags bit 0 / 1 / 2 set
+// when A / B / C lie in the arena, bit 3 for C -= A B.
 struct GemmDesc {
-  const double2* A;
-  const double2* B;
-  double2* C;
-  int lda, ldb, ldc, M, N, K, sub;
+  long a, b, c;
+  int lda, ldb, ldc, M, N, K, flags;
   long tile0;
 };
 
 __global__ void __launch_bounds__(256)
-k_mf_gemm(const GemmDesc* __restrict__ descs, const int* __restrict__ tdesc) {
+k_mf_gemm(const GemmDesc* __restrict__ descs, const int* __restrict__ tdesc, double2* Fbase,
+          double2* Wbase) {
   __shared__ double2 As[8][65], Bs[8][65];
-  const GemmDesc g = descs[tdesc[blockIdx.x]];
+  const GemmDesc gd = descs[tdesc[blockIdx.x]];
+  struct {
+    const double2* A;
+    const double2* B;
+    double2* C;
+    int lda, ldb, ldc, M, N, K, sub;
+    long tile0;
+  } g{(gd.flags & 1 ? Wbase : Fbase) + gd.a, (gd.flags & 2 ? Wbase : Fbase) + gd.b,
+      (gd.flags & 4 ? Wbase : Fbase) + gd.c, gd.lda, gd.ldb, gd.ldc, gd.M, gd.N, gd.K,
+      (gd.flags >> 3) & 1, gd.tile0};
   const long t = long(blockIdx.x) - g.tile0;
   const int tn = (g.N + 63) / 64;
   const int row0 = int(t / tn) * 64, col0 = int(t % tn) * 64;
@@ -452,14 +463,43 @@ k_mf_gemm(const GemmDesc* __restrict__ descs, const int* __restrict__ tdesc) {
 
 template <int P>
 void launch_front(const MfView& mv, const DevOp<double>& cop, int Mc, const int2* rows, int nrows,
-                  double2* const* fptr, hipStream_t st) {
-  k_mf_front<P><<<nrows, 256, 0, st>>>(mv, cop.coef, cop.pn, Mc, rows, fptr);
+                  double2* arena, const long* foff, hipStream_t st) {
+  k_mf_front<P><<<nrows, 256, 0, st>>>(mv, cop.coef, cop.pn, Mc, rows, arena, foff);
 }
 
-}  // namespace
+// Everything of a factorisation and a solve that depends only on the mesh class, on one
+// device: the symbolic view (node table, point lists, maps, node order, tasks) and the
+// factorisation's launch tables (front offsets in the arena, front rows, extend-add rows,
+// small inversions, parents, GEMM descriptors and tile maps, per height). Built once per
+// (device, p, n_c) and kept until the process ends.
+struct MfHeightLaunch {
+  size_t r0, r1, e0[2], e1[2], g0, g1, d0[2], d1[2], t0[2], t1[2];
+  int smax;                     // largest separator of the small inversions
+  std::vector<int> big;         // nodes inverted by the sweep
+  std::vector<long> bigoff;     // their fronts' offsets in the arena
+};
+struct MfPlan {
+  MfView view;                  // device pointers
+  MfView* dview = nullptr;      // the same struct on the device
+  long arena = 0;               // front arena elements
+  size_t maxbig = 0;
+  std::vector<MfHeightLaunch> hl;
+  const long* foff = nullptr;
+  const int2 *rows = nullptr, *ext = nullptr;
+  const int *gj = nullptr, *parent = nullptr, *td = nullptr;
+  const GemmDesc* gd = nullptr;
+};
 
-hz_status mf_factor(const MfSym& sym, const MfView& mv, const DevOp<double>& cop, double2* Fac,
-                    int* flag, hipStream_t st) {
+std::mutex g_plan_mu;
+std::map<std::tuple<int, int, int>, std::unique_ptr<MfPlan>> g_plans;
+
+const MfPlan& mf_plan(const MfSym& sym, hipStream_t st) {
+  int dev = 0;
+  HZ_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> guard(g_plan_mu);
+  auto& slot = g_plans[std::make_tuple(dev, sym.p, sym.nc)];
+  if (slot) return *slot;
+  std::unique_ptr<MfPlan> P(new MfPlan());
   const int nn = int(sym.nodes.size());
   // front arena: the fronts of height h live until their parents (at heights up to
   // last[h]) have taken their update matrices; first fit over the heights' intervals
@@ -472,7 +512,6 @@ hz_status mf_factor(const MfSym& sym, const MfView& mv, const DevOp<double>& cop
     for (int v : sym.at[h]) hsize[h] += long(sym.nodes[v].s + sym.nodes[v].m) * (sym.nodes[v].s + sym.nodes[v].m);
   std::vector<std::pair<long, long>> live;   // (offset, size) of live heights' blocks
   std::vector<int> live_h;
-  long arena = 0;
   for (int h = 0; h <= sym.H; ++h) {
     for (size_t i = 0; i < live.size();) {     // heights whose parents all precede h
       if (last[live_h[i]] < h) { live.erase(live.begin() + i); live_h.erase(live_h.begin() + i); }
@@ -486,31 +525,25 @@ hz_status mf_factor(const MfSym& sym, const MfView& mv, const DevOp<double>& cop
       off = std::max(off, b.first + b.second);
     }
     hoff[h] = off;
-    arena = std::max(arena, off + hsize[h]);
+    P->arena = std::max(P->arena, off + hsize[h]);
     live.push_back({off, hsize[h]});
     live_h.push_back(h);
   }
-  double2* ws = nullptr;
-  HZ_HIP(hipMallocAsync(reinterpret_cast<void**>(&ws), size_t(std::max<long>(arena, 1)) * 16, st));
-  std::vector<double2*> fp(nn, nullptr);
+  std::vector<long> fo(nn, 0);
   for (int h = 0; h <= sym.H; ++h) {
     long o = hoff[h];
     for (int v : sym.at[h]) {
-      fp[v] = ws + o;
+      fo[v] = o;
       o += long(sym.nodes[v].s + sym.nodes[v].m) * (sym.nodes[v].s + sym.nodes[v].m);
     }
   }
-  // host-built launch tables, uploaded once: front rows, extend-add rows per child slot,
-  // small inversions, GEMM descriptors and tile maps, per height
   std::vector<int2> rows, ext;
   std::vector<int> gj, parent(sym.parent.begin(), sym.parent.end());
   std::vector<GemmDesc> gd;
   std::vector<int> td;
-  struct HL { size_t r0, r1, e0[2], e1[2], g0, g1; size_t d0[2], d1[2], t0[2], t1[2]; };
-  std::vector<HL> hl(sym.H + 1);
-  size_t maxbig = 0;
+  P->hl.assign(sym.H + 1, MfHeightLaunch());
   for (int h = 0; h <= sym.H; ++h) {
-    HL& L = hl[h];
+    MfHeightLaunch& L = P->hl[h];
     L.r0 = rows.size();
     for (int v : sym.at[h])
       for (int r = 0; r < sym.nodes[v].s + sym.nodes[v].m; ++r) rows.push_back(make_int2(v, r));
@@ -525,9 +558,17 @@ hz_status mf_factor(const MfSym& sym, const MfView& mv, const DevOp<double>& cop
       L.e1[slot] = ext.size();
     }
     L.g0 = gj.size();
-    for (int v : sym.at[h])
-      if (sym.nodes[v].s <= 64) gj.push_back(v);
-      else maxbig = std::max(maxbig, size_t(sym.nodes[v].s));
+    L.smax = 0;
+    for (int v : sym.at[h]) {
+      if (sym.nodes[v].s <= 64) {
+        gj.push_back(v);
+        L.smax = std::max(L.smax, sym.nodes[v].s);
+      } else {
+        L.big.push_back(v);
+        L.bigoff.push_back(fo[v]);
+        P->maxbig = std::max(P->maxbig, size_t(sym.nodes[v].s));
+      }
+    }
     L.g1 = gj.size();
     for (int phase = 0; phase < 2; ++phase) {
       L.d0[phase] = gd.size();
@@ -536,13 +577,14 @@ hz_status mf_factor(const MfSym& sym, const MfView& mv, const DevOp<double>& cop
         const MfNode& nd = sym.nodes[v];
         if (nd.m == 0) continue;
         const int s = nd.s, m = nd.m, w = s + m;
-        double2* F = fp[v];
+        const long F = fo[v];
         std::vector<GemmDesc> add;
         if (phase == 0) {
-          add.push_back({Fac + nd.Soff, F + s, Fac + nd.Goff, s, w, m, s, m, s, 0, 0});        // G = S F_IB
-          add.push_back({F + long(s) * w, Fac + nd.Soff, Fac + nd.GToff, w, s, s, m, s, s, 0, 0});  // G^T = F_BI S
+          add.push_back({nd.Soff, F + s, nd.Goff, s, w, m, s, m, s, 2, 0});                // G = S F_IB
+          add.push_back({F + long(s) * w, nd.Soff, nd.GToff, w, s, s, m, s, s, 1, 0});     // G^T = F_BI S
         } else {
-          add.push_back({F + long(s) * w, Fac + nd.Goff, F + long(s) * w + s, w, m, w, m, m, s, 1, 0});  // U
+          add.push_back({F + long(s) * w, nd.Goff, F + long(s) * w + s, w, m, w, m, m, s,
+                         1 | 4 | 8, 0});                                                   // U
         }
         for (GemmDesc d : add) {
           d.tile0 = long(td.size() - L.t0[phase]);
@@ -555,51 +597,87 @@ hz_status mf_factor(const MfSym& sym, const MfView& mv, const DevOp<double>& cop
       L.t1[phase] = td.size();
     }
   }
-  // one upload: pointers, row tasks, extend rows, inversion list, parents, GEMM tables
+  // one device buffer: the symbolic arrays and view, then the factorisation's tables
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t b_fp = al(size_t(nn) * 8), b_rows = al(rows.size() * 8), b_ext = al(ext.size() * 8),
-               b_gj = al(gj.size() * 4), b_par = al(parent.size() * 4),
-               b_gd = al(gd.size() * sizeof(GemmDesc)), b_td = al(td.size() * 4);
-  std::vector<char> hb(b_fp + b_rows + b_ext + b_gj + b_par + b_gd + b_td, 0);
+  std::vector<std::pair<const void*, size_t>> parts = {
+      {sym.nodes.data(), sym.nodes.size() * sizeof(MfNode)}, {sym.I.data(), sym.I.size() * 4},
+      {sym.B.data(), sym.B.size() * 4}, {sym.map.data(), sym.map.size() * 4},
+      {sym.hn.data(), sym.hn.size() * 4}, {sym.fwd.data(), sym.fwd.size() * sizeof(MfTask)},
+      {sym.bwd.data(), sym.bwd.size() * sizeof(MfTask)}, {sym.inv.data(), sym.inv.size() * 4},
+      {nullptr, sizeof(MfView)},
+      {fo.data(), fo.size() * 8}, {rows.data(), rows.size() * 8}, {ext.data(), ext.size() * 8},
+      {gj.data(), gj.size() * 4}, {parent.data(), parent.size() * 4},
+      {gd.data(), gd.size() * sizeof(GemmDesc)}, {td.data(), td.size() * 4}};
+  size_t tot = 0;
+  for (auto& q : parts) tot += al(q.second);
+  char* d = nullptr;
+  HZ_HIP(hipMalloc(reinterpret_cast<void**>(&d), std::max<size_t>(tot, 256)));
+  std::vector<char> h(tot, 0);
+  std::vector<char*> at;
   size_t o = 0;
-  std::memcpy(hb.data() + o, fp.data(), nn * 8); o += b_fp;
-  std::memcpy(hb.data() + o, rows.data(), rows.size() * 8); o += b_rows;
-  std::memcpy(hb.data() + o, ext.data(), ext.size() * 8); o += b_ext;
-  std::memcpy(hb.data() + o, gj.data(), gj.size() * 4); o += b_gj;
-  std::memcpy(hb.data() + o, parent.data(), parent.size() * 4); o += b_par;
-  std::memcpy(hb.data() + o, gd.data(), gd.size() * sizeof(GemmDesc)); o += b_gd;
-  std::memcpy(hb.data() + o, td.data(), td.size() * 4);
-  char* db = nullptr;
-  HZ_HIP(hipMallocAsync(reinterpret_cast<void**>(&db), hb.size(), st));
-  HZ_HIP(hipMemcpyAsync(db, hb.data(), hb.size(), hipMemcpyHostToDevice, st));
-  o = 0;
-  double2* const* d_fp = reinterpret_cast<double2* const*>(db + o); o += b_fp;
-  const int2* d_rows = reinterpret_cast<const int2*>(db + o); o += b_rows;
-  const int2* d_ext = reinterpret_cast<const int2*>(db + o); o += b_ext;
-  const int* d_gj = reinterpret_cast<const int*>(db + o); o += b_gj;
-  const int* d_par = reinterpret_cast<const int*>(db + o); o += b_par;
-  const GemmDesc* d_gd = reinterpret_cast<const GemmDesc*>(db + o); o += b_gd;
-  const int* d_td = reinterpret_cast<const int*>(db + o);
+  for (auto& q : parts) {
+    if (q.first) std::memcpy(h.data() + o, q.first, q.second);
+    at.push_back(d + o);
+    o += al(q.second);
+  }
+  MfView& v = P->view;
+  v.nodes = reinterpret_cast<const MfNode*>(at[0]);
+  v.I = reinterpret_cast<const int*>(at[1]);
+  v.B = reinterpret_cast<const int*>(at[2]);
+  v.map = reinterpret_cast<const int*>(at[3]);
+  v.hn = reinterpret_cast<const int*>(at[4]);
+  v.fwd = reinterpret_cast<const MfTask*>(at[5]);
+  v.bwd = reinterpret_cast<const MfTask*>(at[6]);
+  v.inv = reinterpret_cast<const int*>(at[7]);
+  P->dview = reinterpret_cast<MfView*>(at[8]);
+  std::memcpy(h.data() + (at[8] - d), &v, sizeof(MfView));
+  P->foff = reinterpret_cast<const long*>(at[9]);
+  P->rows = reinterpret_cast<const int2*>(at[10]);
+  P->ext = reinterpret_cast<const int2*>(at[11]);
+  P->gj = reinterpret_cast<const int*>(at[12]);
+  P->parent = reinterpret_cast<const int*>(at[13]);
+  P->gd = reinterpret_cast<const GemmDesc*>(at[14]);
+  P->td = reinterpret_cast<const int*>(at[15]);
+  HZ_HIP(hipMemcpyAsync(d, h.data(), tot, hipMemcpyHostToDevice, st));
+  HZ_HIP(hipStreamSynchronize(st));   // h is local
+  slot = std::move(P);
+  return *slot;
+}
+
+}  // namespace
+
+MfView* mf_device_view(const MfSym& sym, MfView* host_copy, hipStream_t st) {
+  const MfPlan& P = mf_plan(sym, st);
+  if (host_copy) *host_copy = P.view;
+  return P.dview;
+}
+
+hz_status mf_factor(const MfSym& sym, const DevOp<double>& cop, double2* Fac, int* flag,
+                    hipStream_t st) {
+  const MfPlan& P = mf_plan(sym, st);
+  const MfView& mv = P.view;
+  double2* ws = nullptr;
+  HZ_HIP(hipMallocAsync(reinterpret_cast<void**>(&ws), size_t(std::max<long>(P.arena, 1)) * 16, st));
   // sweep work for the large inversions
   double2 *W = nullptr, *R = nullptr;
-  if (maxbig > 0) {
-    HZ_HIP(hipMallocAsync(reinterpret_cast<void**>(&W), 2 * sweep_panel_elems(maxbig) * 16, st));
+  if (P.maxbig > 0) {
+    HZ_HIP(hipMallocAsync(reinterpret_cast<void**>(&W), 2 * sweep_panel_elems(P.maxbig) * 16, st));
     HZ_HIP(hipMallocAsync(reinterpret_cast<void**>(&R), 2 * sweep_pinv_elems() * 16, st));
   }
   HZ_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
   const int p = sym.p, Mc = sym.Mc;
   for (int h = 0; h <= sym.H; ++h) {
-    const HL& L = hl[h];
+    const MfHeightLaunch& L = P.hl[h];
     const int nr = int(L.r1 - L.r0);
     if (nr > 0) {
-      if (p == 1) launch_front<1>(mv, cop, Mc, d_rows + L.r0, nr, d_fp, st);
-      else if (p == 2) launch_front<2>(mv, cop, Mc, d_rows + L.r0, nr, d_fp, st);
-      else launch_front<3>(mv, cop, Mc, d_rows + L.r0, nr, d_fp, st);
+      if (p == 1) launch_front<1>(mv, cop, Mc, P.rows + L.r0, nr, ws, P.foff, st);
+      else if (p == 2) launch_front<2>(mv, cop, Mc, P.rows + L.r0, nr, ws, P.foff, st);
+      else launch_front<3>(mv, cop, Mc, P.rows + L.r0, nr, ws, P.foff, st);
       HZ_HIP(hipGetLastError());
     }
     for (int slot = 0; slot < 2; ++slot) {
       const int ne = int(L.e1[slot] - L.e0[slot]);
-      if (ne > 0) k_mf_extend<<<ne, 256, 0, st>>>(mv, d_par, d_ext + L.e0[slot], d_fp);
+      if (ne > 0) k_mf_extend<<<ne, 256, 0, st>>>(mv, P.parent, P.ext + L.e0[slot], ws, P.foff);
     }
     const int ng = int(L.g1 - L.g0);
     if (ng > 0) {
@@ -608,20 +686,19 @@ hz_status mf_factor(const MfSym& sym, const MfView& mv, const DevOp<double>& cop
         HZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_gj),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 65 * 16));
       });
-      int smax = 0;
-      for (size_t q = L.g0; q < L.g1; ++q) smax = std::max(smax, sym.nodes[gj[q]].s);
-      k_mf_gj<<<ng, 256, size_t(smax) * (smax + 1) * 16, st>>>(mv, d_gj + L.g0, d_fp, Fac, flag);
+      k_mf_gj<<<ng, 256, size_t(L.smax) * (L.smax + 1) * 16, st>>>(mv, P.gj + L.g0, ws, P.foff,
+                                                                    Fac, flag);
     }
-    for (int v : sym.at[h]) {
-      const MfNode& nd = sym.nodes[v];
-      if (nd.s <= 64) continue;
+    for (size_t q = 0; q < L.big.size(); ++q) {
+      const MfNode& nd = sym.nodes[L.big[q]];
       const long n2 = long(nd.s) * nd.s;
-      k_mf_copy_ii<<<unsigned((n2 + 255) / 256), 256, 0, st>>>(fp[v], nd.s, nd.s + nd.m, Fac + nd.Soff);
+      k_mf_copy_ii<<<unsigned((n2 + 255) / 256), 256, 0, st>>>(ws + L.bigoff[q], nd.s,
+                                                              nd.s + nd.m, Fac + nd.Soff);
       sweep_inverse(Fac + nd.Soff, nd.s, W, R, flag, st);
     }
     for (int phase = 0; phase < 2; ++phase) {
       const int nt = int(L.t1[phase] - L.t0[phase]);
-      if (nt > 0) k_mf_gemm<<<nt, 256, 0, st>>>(d_gd + L.d0[phase], d_td + L.t0[phase]);
+      if (nt > 0) k_mf_gemm<<<nt, 256, 0, st>>>(P.gd + L.d0[phase], P.td + L.t0[phase], Fac, ws);
     }
     HZ_HIP(hipGetLastError());
   }
@@ -630,7 +707,6 @@ hz_status mf_factor(const MfSym& sym, const MfView& mv, const DevOp<double>& cop
   HZ_HIP(hipStreamSynchronize(st));
   if (W) (void)hipFreeAsync(W, st);
   if (R) (void)hipFreeAsync(R, st);
-  (void)hipFreeAsync(db, st);
   (void)hipFreeAsync(ws, st);
   return hflag ? HZ_ESINGULAR : HZ_OK;
 }
@@ -692,9 +768,15 @@ k_mf_solve(CsJobs<T> jobs, int task0, long cstride) {
       }
     }
     if (FWD) {
+      // the task's rows read f_I and, for rows of G^T f_I, f_B at those rows only: gather
+      // positions [0, s) and [lo, hi)
       const bool kids = nd.invoff >= 0;
       const long u0 = kids ? mv.nodes[nd.ch0].uoff : 0, u1 = kids ? mv.nodes[nd.ch1].uoff : 0;
-      for (int i = threadIdx.x; i < w; i += 256) {
+      const int lo = t.kind == 1 ? s + t.r0 : t.kind == 5 ? max(s, t.r0) : s;
+      const int hi = t.kind == 1 ? s + t.r1 : t.kind == 5 ? max(s, t.r1) : s;
+      const int ng = s + (hi - lo);
+      for (int q = threadIdx.x; q < ng; q += 256) {
+        const int i = q < s ? q : lo + (q - s);
         const int j0 = kids ? mv.inv[nd.invoff + 2 * i] : -1;
         const int j1 = kids ? mv.inv[nd.invoff + 2 * i + 1] : -1;
         const int gi = i < s ? mv.I[nd.Ioff + i] : 0;
