@@ -284,8 +284,10 @@ bool use_mf() {
 // Bytes of the device copy of a symbolic factor (nodes, point lists, maps, tasks, view).
 size_t mf_sym_bytes(const MfSym& y) {
   return y.nodes.size() * sizeof(MfNode) +
-         (y.I.size() + y.B.size() + y.map.size() + y.hn.size() + y.inv.size()) * 4 +
-         (y.fwd.size() + y.bwd.size()) * sizeof(MfTask) + sizeof(MfView) + 8 * 256;
+         (y.I.size() + y.B.size() + y.map.size() + y.hn.size() + y.inv.size() +
+          y.sub_lev.size() + y.sub_bloc.size()) * 4 + y.sub_hdr.size() * sizeof(MfSubHdr) +
+         y.sub_node.size() * sizeof(MfSubNode) +
+         (y.fwd.size() + y.bwd.size()) * sizeof(MfTask) + sizeof(MfView) + 12 * 256;
 }
 
 struct Sizes {

@@ -114,6 +114,7 @@ k_stencil_pn(DevOp<T> op, const V2<TX>* __restrict__ x, Addr ax, const V2<TF>* _
     if (bb < 0 || bb >= M) continue;
 #pragma unroll
     for (int dx = -P; dx <= P; ++dx) {
+      if (P == 1 && !couples(1, 0, 0, dx, dy)) continue;   // structurally zero for P1
       const int aa = a + dx;
       if (aa < 0 || aa >= M) continue;
       const V2<T> c = coef[size_t((dy + P) * W + dx + P) * N + i];

@@ -218,6 +218,20 @@ struct MfNode {
 struct MfTask {
   int v, kind, r0, r1;
 };
+// One node of a bottom subtree: factor offsets, |I_v|, |B_v|, the offsets of its points, its
+// inverse map (-1 for a leaf) and ring entries within the subtree's, and the LDS offsets of
+// its children's and its own update vectors (-1: leaf / the subtree's root).
+struct MfSubNode {
+  long so, go, gto;
+  int s, m, pI, pinv, pB, lu0, lu1, lu;
+};
+// One bottom subtree: its records sub_node[q0 .. q0 + nrec), points I[i0 .. i0 + np), inverse
+// map entries inv[inv0 .. inv0 + ninv), ring entries B[b0 .. b0 + nbm) (the root's, last, are
+// mroot at uoff_root in the update vectors) and their local indices sub_bloc[bl0 ..).
+struct MfSubHdr {
+  long uoff_root = 0, i0 = 0, inv0 = 0, b0 = 0, bl0 = 0;
+  int q0 = 0, nrec = 0, np = 0, ninv = 0, nbm = 0, mroot = 0;
+};
 struct MfSym {
   int p = 1, nc = 0, Mc = 0, H = 0;
   std::vector<MfNode> nodes;              // postorder: children before their parent
@@ -229,6 +243,19 @@ struct MfSym {
   std::vector<int> hn;                    // the same, concatenated by height
   std::vector<MfTask> fwd, bwd;           // solve tasks, grouped by height
   std::vector<int> fwd0, bwd0;            // first task of each height (H + 2 entries)
+  // Bottom subtrees: the heights 0 .. T (every node small, T <= 3) run as one launch per pass,
+  // one workgroup per subtree rooted at a node of height <= T whose parent is higher (its
+  // nodes are consecutive in postorder, so are their points, ring lists and inverse maps).
+  // sub_node holds each subtree's nodes by ascending height, sub_lev the first of each height
+  // 0 .. T + 1 per subtree, sub_bloc per ring entry of a subtree's nodes its index in the
+  // subtree's local vector (its points, then the root's ring).
+  int T = -1;
+  std::vector<MfSubHdr> sub_hdr;
+  std::vector<MfSubNode> sub_node;
+  std::vector<int> sub_lev;               // nsub * (T + 2)
+  std::vector<int> sub_bloc;
+  MfSubHdr sub_max;                       // per field, the largest over the subtrees
+  int sub_lds = 0;                        // largest update storage of a subtree (elements)
   int maxf = 0;                           // largest s + m
   std::vector<int> fmax, bmax;            // per height: largest s + m, m of a non-small node
   std::vector<char> fbig, bbig;           // per height: prefetch rows (all tasks one wave per
@@ -246,6 +273,10 @@ struct MfView {
   const MfTask* bwd = nullptr;
   const int* hn = nullptr;
   const int* inv = nullptr;
+  const MfSubHdr* sub_hdr = nullptr;
+  const MfSubNode* sub_node = nullptr;
+  const int* sub_lev = nullptr;
+  const int* sub_bloc = nullptr;
 };
 
 template <typename T> struct CoarseJob {

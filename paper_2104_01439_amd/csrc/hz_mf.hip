@@ -227,6 +227,96 @@ void build_symbolic(MfSym& S, int p, int nc) {
   }
   S.fwd0[S.H + 1] = int(S.fwd.size());
   S.bwd0[S.H + 1] = int(S.bwd.size());
+  // bottom subtrees: T = the largest height up to which every node is small, at most 3 (a
+  // workgroup walks up to 15 nodes; taller subtrees would serialise more than the launches
+  // they save)
+  {
+    int T = -1;
+    for (int h = 0; h <= std::min(S.H, 3); ++h) {
+      bool all = true;
+      for (int v : S.at[h]) all = all && is_small(v);
+      if (!all) break;
+      T = h;
+    }
+    if (T == S.H) T = S.H - 1;          // keep the root out (it has no parent to hand u to)
+    S.T = T;
+    std::vector<int> size(nn, 1);       // subtree sizes: a subtree is [v - size + 1, v]
+    for (int v = 0; v < nn; ++v)
+      if (S.nodes[v].ch0 >= 0) size[v] += size[S.nodes[v].ch0] + size[S.nodes[v].ch1];
+    MfSubHdr& mx = S.sub_max;
+    for (int v = 0; T >= 0 && v < nn; ++v) {
+      if (S.height[v] > T) continue;
+      const int pa = S.parent[v];
+      if (pa >= 0 && S.height[pa] <= T) continue;   // not a subtree root
+      const int v0 = v - size[v] + 1;
+      std::vector<int> list;
+      for (int x = v0; x <= v; ++x) list.push_back(x);
+      std::stable_sort(list.begin(), list.end(),
+                       [&](int a, int c) { return S.height[a] < S.height[c]; });
+      MfSubHdr hd;
+      hd.q0 = int(S.sub_node.size());
+      hd.nrec = int(list.size());
+      hd.i0 = S.nodes[v0].Ioff;
+      hd.np = int(S.nodes[v].Ioff + S.nodes[v].s - hd.i0);
+      hd.b0 = S.nodes[v0].Boff;
+      hd.nbm = int(S.nodes[v].Boff + S.nodes[v].m - hd.b0);
+      hd.mroot = S.nodes[v].m;
+      hd.uoff_root = S.nodes[v].uoff;
+      hd.bl0 = long(S.sub_bloc.size());
+      hd.inv0 = -1;
+      long inv1 = 0;
+      for (int x = v0; x <= v; ++x)
+        if (S.nodes[x].invoff >= 0) {
+          if (hd.inv0 < 0) hd.inv0 = S.nodes[x].invoff;
+          inv1 = S.nodes[x].invoff + 2 * (S.nodes[x].s + S.nodes[x].m);
+        }
+      if (hd.inv0 < 0) hd.inv0 = 0;
+      hd.ninv = int(std::max<long>(0, inv1 - hd.inv0));
+      std::map<int, int> lu;                          // LDS offset of each node's u
+      int lds = 0;
+      for (int x : list) {
+        lu[x] = x == v ? -1 : lds;
+        if (x != v) lds += S.nodes[x].m;
+      }
+      S.sub_lds = std::max(S.sub_lds, lds);
+      for (int x : list) {
+        const MfNode& nd = S.nodes[x];
+        MfSubNode r;
+        r.so = nd.Soff;
+        r.go = nd.Goff;
+        r.gto = nd.GToff;
+        r.s = nd.s;
+        r.m = nd.m;
+        r.pI = int(nd.Ioff - hd.i0);
+        r.pinv = nd.invoff >= 0 ? int(nd.invoff - hd.inv0) : -1;
+        r.pB = int(nd.Boff - hd.b0);
+        r.lu0 = nd.ch0 >= 0 ? lu[nd.ch0] : -1;
+        r.lu1 = nd.ch1 >= 0 ? lu[nd.ch1] : -1;
+        r.lu = lu[x];
+        S.sub_node.push_back(r);
+      }
+      // local indices of the ring entries: the subtree's points, then the root's ring
+      std::unordered_map<int, int> loc;
+      for (int t = 0; t < hd.np; ++t) loc[S.I[hd.i0 + t]] = t;
+      for (int t = 0; t < hd.mroot; ++t) loc[S.B[hd.b0 + hd.nbm - hd.mroot + t]] = hd.np + t;
+      for (int t = 0; t < hd.nbm; ++t) {
+        auto it = loc.find(S.B[hd.b0 + t]);
+        if (it == loc.end()) throw std::runtime_error("multifrontal: subtree ring point");
+        S.sub_bloc.push_back(it->second);
+      }
+      int q = 0;
+      for (int h = 0; h <= T + 1; ++h) {
+        while (q < int(list.size()) && S.height[list[q]] < h) ++q;
+        S.sub_lev.push_back(hd.q0 + q);
+      }
+      mx.nrec = std::max(mx.nrec, hd.nrec);
+      mx.np = std::max(mx.np, hd.np);
+      mx.ninv = std::max(mx.ninv, hd.ninv);
+      mx.nbm = std::max(mx.nbm, hd.nbm);
+      mx.mroot = std::max(mx.mroot, hd.mroot);
+      S.sub_hdr.push_back(hd);
+    }
+  }
   S.fmax.assign(S.H + 1, 0);
   S.bmax.assign(S.H + 1, 0);
   S.fbig.assign(S.H + 1, 1);
@@ -604,6 +694,10 @@ const MfPlan& mf_plan(const MfSym& sym, hipStream_t st) {
       {sym.B.data(), sym.B.size() * 4}, {sym.map.data(), sym.map.size() * 4},
       {sym.hn.data(), sym.hn.size() * 4}, {sym.fwd.data(), sym.fwd.size() * sizeof(MfTask)},
       {sym.bwd.data(), sym.bwd.size() * sizeof(MfTask)}, {sym.inv.data(), sym.inv.size() * 4},
+      {sym.sub_hdr.data(), sym.sub_hdr.size() * sizeof(MfSubHdr)},
+      {sym.sub_node.data(), sym.sub_node.size() * sizeof(MfSubNode)},
+      {sym.sub_lev.data(), sym.sub_lev.size() * 4},
+      {sym.sub_bloc.data(), sym.sub_bloc.size() * 4},
       {nullptr, sizeof(MfView)},
       {fo.data(), fo.size() * 8}, {rows.data(), rows.size() * 8}, {ext.data(), ext.size() * 8},
       {gj.data(), gj.size() * 4}, {parent.data(), parent.size() * 4},
@@ -629,15 +723,19 @@ const MfPlan& mf_plan(const MfSym& sym, hipStream_t st) {
   v.fwd = reinterpret_cast<const MfTask*>(at[5]);
   v.bwd = reinterpret_cast<const MfTask*>(at[6]);
   v.inv = reinterpret_cast<const int*>(at[7]);
-  P->dview = reinterpret_cast<MfView*>(at[8]);
-  std::memcpy(h.data() + (at[8] - d), &v, sizeof(MfView));
-  P->foff = reinterpret_cast<const long*>(at[9]);
-  P->rows = reinterpret_cast<const int2*>(at[10]);
-  P->ext = reinterpret_cast<const int2*>(at[11]);
-  P->gj = reinterpret_cast<const int*>(at[12]);
-  P->parent = reinterpret_cast<const int*>(at[13]);
-  P->gd = reinterpret_cast<const GemmDesc*>(at[14]);
-  P->td = reinterpret_cast<const int*>(at[15]);
+  v.sub_hdr = reinterpret_cast<const MfSubHdr*>(at[8]);
+  v.sub_node = reinterpret_cast<const MfSubNode*>(at[9]);
+  v.sub_lev = reinterpret_cast<const int*>(at[10]);
+  v.sub_bloc = reinterpret_cast<const int*>(at[11]);
+  P->dview = reinterpret_cast<MfView*>(at[12]);
+  std::memcpy(h.data() + (at[12] - d), &v, sizeof(MfView));
+  P->foff = reinterpret_cast<const long*>(at[13]);
+  P->rows = reinterpret_cast<const int2*>(at[14]);
+  P->ext = reinterpret_cast<const int2*>(at[15]);
+  P->gj = reinterpret_cast<const int*>(at[16]);
+  P->parent = reinterpret_cast<const int*>(at[17]);
+  P->gd = reinterpret_cast<const GemmDesc*>(at[18]);
+  P->td = reinterpret_cast<const int*>(at[19]);
   HZ_HIP(hipMemcpyAsync(d, h.data(), tot, hipMemcpyHostToDevice, st));
   HZ_HIP(hipStreamSynchronize(st));   // h is local
   slot = std::move(P);
@@ -977,6 +1075,238 @@ k_mf_solve(CsJobs<T> jobs, int task0, long cstride) {
   }
 }
 
+// Orders a wave's LDS writes before its reads of other lanes' entries: a wave's LDS operations
+// complete in issue order, and the fences keep the compiler from moving them across.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Matrix entries a lane requests before it reads its front entries.
+constexpr int kMfSubPf = 8;
+
+// LDS extents of the bottom-subtree launch (largest over the subtrees): records, points, the
+// inverse-map (forward) or ring-index (backward) entries, the local vector per right-hand
+// side (points; backward also the root's ring) and the update storage.
+struct MfSubDims {
+  int nrec, np, nint, xs, ulds;
+};
+
+__host__ __device__ inline size_t mf_sub_vec_offset(const MfSubDims& d) {
+  return (32 + size_t(d.nrec) * sizeof(MfSubNode) + size_t(d.np + d.nint) * 4 + 15) / 16 * 16;
+}
+
+// The bottom subtrees (heights 0 .. T, every node small) in one launch per pass: workgroup
+// (subtree, job, right-hand-side group). The workgroup first copies the subtree's node
+// records, point indices and inverse maps (forward) or ring indices (backward) into LDS with
+// b (forward) or z (backward, y at the subtree's points and at the root's ring); then, one
+// height at a time with a barrier between heights, the four waves take the height's nodes in
+// turn, one wave per node, so that a node waits only for its own matrix rows.
+// Forward, heights ascending: lane r < s + m forms row r of [S; G^T] (as the small-node tasks
+// do) from f_r = (b at I_v, or 0) + child 0's u + child 1's u; the update vectors stay in LDS,
+// only the subtree root's goes to memory. Backward, heights descending: x_B from the local
+// vector; the rows of G x_B are split over 64 / RW lane groups (RW = 16, 32 or 64 >= s) that
+// each take a contiguous part of the m columns, then summed across the groups; x_I goes to the
+// local vector and to y.
+template <typename T, int NR, bool FWD>
+__global__ void __launch_bounds__(256)
+k_mf_sub(CsJobs<T> jobs, int TT, long cstride, MfSubDims dm) {
+  extern __shared__ __align__(16) char smem[];
+  int* lev = reinterpret_cast<int*>(smem);
+  MfSubNode* rl = reinterpret_cast<MfSubNode*>(smem + 32);
+  int* il = reinterpret_cast<int*>(rl + dm.nrec);
+  int* ml = il + dm.np;
+  V2<T>* vl = reinterpret_cast<V2<T>*>(smem + mf_sub_vec_offset(dm));
+  const CoarseJob<T>* job = &jobs.j[blockIdx.y];
+  const int hb = blockIdx.z * NR;
+  const int nr = min(NR, job->nrhs - hb);
+  if (nr <= 0) return;
+  const MfView mv = *job->mf;
+  const V2<T>* __restrict__ Fac = job->S;
+  const V2<T>* b = job->b + long(hb) * cstride;
+  V2<T>* y = job->y + long(hb) * cstride;
+  V2<T>* u = job->gbuf + long(hb) * job->ustride;
+  const long us = job->ustride;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const MfSubHdr hd = mv.sub_hdr[blockIdx.x];
+  const int xs = dm.xs;
+  V2<T>* ub = vl + NR * xs;                                   // forward: update vectors
+  V2<T>* fw = (FWD ? ub + NR * dm.ulds : ub) + wave * (NR * 64);   // the wave's f_I or x_B
+  // prologue
+  if (tid <= TT + 1) lev[tid] = mv.sub_lev[long(blockIdx.x) * (TT + 2) + tid] - hd.q0;
+  {
+    const long* src = reinterpret_cast<const long*>(mv.sub_node + hd.q0);
+    long* dst = reinterpret_cast<long*>(rl);
+    constexpr int W8 = int(sizeof(MfSubNode) / 8);
+    for (int t = tid; t < hd.nrec * W8; t += 256) dst[t] = src[t];
+  }
+  if (FWD) {
+    for (int t = tid; t < hd.ninv; t += 256) ml[t] = mv.inv[hd.inv0 + t];
+  } else {
+    for (int t = tid; t < hd.nbm; t += 256) ml[t] = mv.sub_bloc[hd.bl0 + t];
+  }
+  for (int t = tid; t < hd.np; t += 256) {
+    const int gi = mv.I[hd.i0 + t];
+    il[t] = gi;
+#pragma unroll
+    for (int h = 0; h < NR; ++h)
+      if (h < nr) vl[h * xs + t] = FWD ? b[h * cstride + gi] : y[h * cstride + gi];
+  }
+  if (!FWD) {
+    for (int t = tid; t < hd.mroot; t += 256) {
+      const int gb = mv.B[hd.b0 + hd.nbm - hd.mroot + t];
+#pragma unroll
+      for (int h = 0; h < NR; ++h)
+        if (h < nr) vl[h * xs + hd.np + t] = y[h * cstride + gb];
+    }
+  }
+  __syncthreads();
+  for (int step = 0; step <= TT; ++step) {
+    const int ht = FWD ? step : TT - step;
+    const int q1 = lev[ht + 1];
+    for (int q = lev[ht] + wave; q < q1; q += 4) {
+      const MfSubNode r = rl[q];
+      const int s = r.s, m = r.m, w = s + m;
+      if (FWD) {
+        const bool row = lane < w;
+        const V2<T>* col = lane < s ? Fac + r.so + lane : Fac + r.go + (lane - s);
+        const int ld = lane < s ? s : m;
+        V2<T> xr[kMfSubPf];
+#pragma unroll
+        for (int k = 0; k < kMfSubPf; ++k) xr[k] = (row && k < s) ? col[long(k) * ld] : czero<T>();
+        V2<T> fl[NR];
+#pragma unroll
+        for (int h = 0; h < NR; ++h) fl[h] = czero<T>();
+        if (row) {
+          const int j0 = r.lu0 >= 0 ? ml[r.pinv + 2 * lane] : -1;
+          const int j1 = r.lu1 >= 0 ? ml[r.pinv + 2 * lane + 1] : -1;
+#pragma unroll
+          for (int h = 0; h < NR; ++h) {
+            if (h >= nr) continue;
+            V2<T> v = lane < s ? vl[h * xs + r.pI + lane] : czero<T>();
+            if (j0 >= 0) {
+              const V2<T> a = ub[h * dm.ulds + r.lu0 + j0];
+              v.x += a.x;
+              v.y += a.y;
+            }
+            if (j1 >= 0) {
+              const V2<T> a = ub[h * dm.ulds + r.lu1 + j1];
+              v.x += a.x;
+              v.y += a.y;
+            }
+            fl[h] = v;
+            if (lane < s) fw[h * 64 + lane] = v;
+          }
+        }
+        wave_sync();
+        if (row) {
+          V2<T> acc[NR];
+#pragma unroll
+          for (int h = 0; h < NR; ++h) acc[h] = czero<T>();
+#pragma unroll
+          for (int k = 0; k < kMfSubPf; ++k)
+            if (k < s)
+#pragma unroll
+              for (int h = 0; h < NR; ++h)
+                if (h < nr) cfma(acc[h], xr[k], fw[h * 64 + k]);
+          for (int k = kMfSubPf; k < s; ++k) {
+            const V2<T> xv = col[long(k) * ld];
+#pragma unroll
+            for (int h = 0; h < NR; ++h)
+              if (h < nr) cfma(acc[h], xv, fw[h * 64 + k]);
+          }
+#pragma unroll
+          for (int h = 0; h < NR; ++h) {
+            if (h >= nr) continue;
+            if (lane < s) {
+              y[h * cstride + il[r.pI + lane]] = acc[h];
+            } else {
+              V2<T> o;
+              o.x = fl[h].x - acc[h].x;
+              o.y = fl[h].y - acc[h].y;
+              if (r.lu >= 0) ub[h * dm.ulds + r.lu + (lane - s)] = o;
+              else u[h * us + hd.uoff_root + (lane - s)] = o;
+            }
+          }
+        }
+        wave_sync();     // fw is the wave's next node's
+      } else {
+        if (m == 0) continue;
+        const int RW = s <= 16 ? 16 : (s <= 32 ? 32 : 64);
+        const int i = lane & (RW - 1), c = lane / RW;
+        const int kc = (m + 64 / RW - 1) / (64 / RW);
+        const int k0 = c * kc, k1 = min(m, k0 + kc);
+        const V2<T>* col = Fac + r.gto + i;              // G^T[k][i] = G[i][k]
+        const bool act = i < s;
+        V2<T> xr[kMfSubPf];
+#pragma unroll
+        for (int t = 0; t < kMfSubPf; ++t)
+          xr[t] = (act && k0 + t < k1) ? col[long(k0 + t) * s] : czero<T>();
+        if (lane < m) {
+          const int lb = ml[r.pB + lane];
+#pragma unroll
+          for (int h = 0; h < NR; ++h)
+            if (h < nr) fw[h * 64 + lane] = vl[h * xs + lb];
+        }
+        wave_sync();
+        V2<T> acc[NR];
+#pragma unroll
+        for (int h = 0; h < NR; ++h) acc[h] = czero<T>();
+        if (act) {
+#pragma unroll
+          for (int t = 0; t < kMfSubPf; ++t)
+            if (k0 + t < k1)
+#pragma unroll
+              for (int h = 0; h < NR; ++h)
+                if (h < nr) cfma(acc[h], xr[t], fw[h * 64 + k0 + t]);
+          for (int k = k0 + kMfSubPf; k < k1; ++k) {
+            const V2<T> xv = col[long(k) * s];
+#pragma unroll
+            for (int h = 0; h < NR; ++h)
+              if (h < nr) cfma(acc[h], xv, fw[h * 64 + k]);
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < NR; ++h)
+          for (int o = RW; o < 64; o <<= 1) {
+            acc[h].x += __shfl_xor(acc[h].x, o, 64);
+            acc[h].y += __shfl_xor(acc[h].y, o, 64);
+          }
+        if (act && c == 0)
+#pragma unroll
+          for (int h = 0; h < NR; ++h) {
+            if (h >= nr) continue;
+            V2<T> z = vl[h * xs + r.pI + i];
+            z.x -= acc[h].x;
+            z.y -= acc[h].y;
+            vl[h * xs + r.pI + i] = z;
+            y[h * cstride + il[r.pI + i]] = z;
+          }
+        wave_sync();
+      }
+    }
+    __syncthreads();
+  }
+}
+
+MfSubDims mf_sub_dims(const MfSym& sym, bool fwd) {
+  const MfSubHdr& mx = sym.sub_max;
+  MfSubDims d;
+  d.nrec = mx.nrec;
+  d.np = mx.np;
+  d.nint = fwd ? mx.ninv : mx.nbm;
+  d.xs = fwd ? mx.np : mx.np + mx.mroot;
+  d.ulds = sym.sub_lds;
+  return d;
+}
+
+size_t mf_sub_lds(const MfSym& sym, bool fwd, int NR, size_t item) {
+  const MfSubDims d = mf_sub_dims(sym, fwd);
+  return mf_sub_vec_offset(d) + size_t(NR) * (d.xs + (fwd ? d.ulds : 0) + 4 * 64) * item;
+}
+
 template <typename T, int NR>
 int mf_launch_all(const MfSym& sym, const CsJobs<T>& jj, int njobs, int maxr, long cstride,
                   hipStream_t st) {
@@ -989,7 +1319,13 @@ int mf_launch_all(const MfSym& sym, const CsJobs<T>& jj, int njobs, int maxr, lo
     const int mx = fwd ? sym.fmax[h] : sym.bmax[h];
     return std::max<size_t>(size_t(NR) * mx, 4 * size_t(NR) * 64) * item;
   };
-  for (int h = 0; h <= sym.H; ++h) {
+  const int nsub = int(sym.sub_hdr.size());
+  if (nsub > 0) {
+    k_mf_sub<T, NR, true><<<dim3(nsub, njobs, gz), 256, mf_sub_lds(sym, true, NR, item), st>>>(
+        jj, sym.T, cstride, mf_sub_dims(sym, true));
+    ++launches;
+  }
+  for (int h = sym.T + 1; h <= sym.H; ++h) {
     const int n = sym.fwd0[h + 1] - sym.fwd0[h];
     if (n > 0) {
       const dim3 g(n, njobs, gz);
@@ -998,7 +1334,7 @@ int mf_launch_all(const MfSym& sym, const CsJobs<T>& jj, int njobs, int maxr, lo
       ++launches;
     }
   }
-  for (int h = sym.H; h >= 0; --h) {
+  for (int h = sym.H; h > sym.T; --h) {
     const int n = sym.bwd0[h + 1] - sym.bwd0[h];
     if (n > 0) {
       const dim3 g(n, njobs, gz);
@@ -1006,6 +1342,11 @@ int mf_launch_all(const MfSym& sym, const CsJobs<T>& jj, int njobs, int maxr, lo
       else k_mf_solve<T, NR, false, 0><<<g, 256, lds_of(h, false), st>>>(jj, sym.bwd0[h], cstride);
       ++launches;
     }
+  }
+  if (nsub > 0) {
+    k_mf_sub<T, NR, false><<<dim3(nsub, njobs, gz), 256, mf_sub_lds(sym, false, NR, item), st>>>(
+        jj, sym.T, cstride, mf_sub_dims(sym, false));
+    ++launches;
   }
   HZ_HIP(hipGetLastError());
   return launches;
@@ -1024,6 +1365,10 @@ void mf_set_lds(size_t bytes) {
   HZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_solve<T, NR, true, kMfPf>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
   HZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_solve<T, NR, false, kMfPf>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+  HZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_sub<T, NR, true>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+  HZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_sub<T, NR, false>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
   done = bytes;
 }
@@ -1045,13 +1390,16 @@ int mf_solve_jobs(const MfSym& sym, const CoarseJob<T>* jobs, int njobs, long cs
     }
     // right-hand sides per workgroup: as many as the front vectors' LDS allows (<= 4)
     const size_t per = std::max<size_t>(sym.maxf, 4 * 64) * item;
+    auto need = [&](int nr) {
+      return std::max({size_t(nr) * per, mf_sub_lds(sym, true, nr, item), mf_sub_lds(sym, false, nr, item)});
+    };
     int NR = 4;
-    while (NR > 1 && size_t(NR) * per > 128 * 1024) NR /= 2;
-    if (size_t(NR) * per > 160 * 1024) throw std::runtime_error("multifrontal: front exceeds LDS");
+    while (NR > 1 && need(NR) > 128 * 1024) NR /= 2;
+    if (need(NR) > 160 * 1024) throw std::runtime_error("multifrontal: front exceeds LDS");
     if (maxr == 1) NR = 1;
-    if (NR == 4) { mf_set_lds<T, 4>(4 * per); launches += mf_launch_all<T, 4>(sym, jj, nj, maxr, cstride, st); }
-    else if (NR == 2) { mf_set_lds<T, 2>(2 * per); launches += mf_launch_all<T, 2>(sym, jj, nj, maxr, cstride, st); }
-    else { mf_set_lds<T, 1>(per); launches += mf_launch_all<T, 1>(sym, jj, nj, maxr, cstride, st); }
+    if (NR == 4) { mf_set_lds<T, 4>(need(4)); launches += mf_launch_all<T, 4>(sym, jj, nj, maxr, cstride, st); }
+    else if (NR == 2) { mf_set_lds<T, 2>(need(2)); launches += mf_launch_all<T, 2>(sym, jj, nj, maxr, cstride, st); }
+    else { mf_set_lds<T, 1>(need(1)); launches += mf_launch_all<T, 1>(sym, jj, nj, maxr, cstride, st); }
   }
   return launches;
 }

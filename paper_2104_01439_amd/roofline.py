@@ -18,6 +18,12 @@ STENCIL_BYTES_PER_DOF = {"a0_apply": 32, "jacobi_first": 32, "jacobi_sweep": 48,
                          "prolongation_add": 36}
 
 
+# Per-point operators (heterogeneous k), P1: the 7 stored couplings of the point (16 B each)
+# on top of the vectors of the constant-k pass, and the Jacobi multiplier per point.
+STENCIL_PN_BYTES_PER_DOF_P1 = {"a0_apply": 7 * 16 + 32, "jacobi_sweep": 7 * 16 + 64,
+                               "residual": 7 * 16 + 48}
+
+
 def coarse_solve_bytes(n, p, itemsize=16, nrhs=1):
     """One coarse block triangular solve launch for nrhs right-hand sides: every stored
     block inverse read twice (forward and backward sweep; the last block only once), plus

@@ -48,6 +48,19 @@ def shift_from_map(k, h, p, weights=None):
     return sigma, complex(1.0, k ** (sigma - 2.0))
 
 
+def cell_shifts(k_cell, h, p, policy="map", weights=None):
+    """Per-cell shift multipliers s_c = 1 + i eps_c / k_c^2 for a heterogeneous wavenumber
+    (Sec. 6 compares eps in {k, k^(3/2), k^2, k^sigma_p} with k the local wavenumber):
+    policy "k", "k1.5", "k2" (eps = k^e), or "map" (eps = k^sigma_p(k, ell), the map of Sec. 5
+    evaluated at each cell's k, ell = log2(1/h))."""
+    k = np.asarray(k_cell, float)
+    if policy == "map":
+        sigma = sigma_map(k, math.log2(1.0 / h), p, weights)
+    else:
+        sigma = {"k": 1.0, "k1.5": 1.5, "k2": 2.0}[policy]
+    return 1.0 + 1j * k ** (sigma - 2.0)
+
+
 def sample_weights(ells, ps):
     """w_{ell_i, p_i}^-2 per sample, w_{ell, p} = N_{ell, p} / |D|."""
     ells = np.asarray(ells)
