@@ -731,8 +731,17 @@ void vcycle_group(hz_problem* const* probs, const int* zp, int nb, const DevOp<T
       launch_prolong<T>(p, pr0->M, pr0->Mc, rw, sc.ec, z, false, nb, az, Addr(Nc), st);
       return;
     }
-    launch_prolong<T>(p, pr0->M, pr0->Mc, rw, sc.ec, cur, true, nb, Addr(N), Addr(Nc), st);
-    for (int sw = 0; sw < nu; ++sw) {
+    // the first post-sweep stages u + P e_c itself where the kernel provides it
+    int sw0 = 0;
+    if (launch_smooth_pc<T>(p, fine, cur, Addr(N), sc.ec, Addr(Nc), pr0->Mc, rw, f, af,
+                            nu == 1 ? z : nxt, nu == 1 ? az : Addr(N), nb, st)) {
+      if (nu == 1) return;
+      std::swap(cur, nxt);
+      sw0 = 1;
+    } else {
+      launch_prolong<T>(p, pr0->M, pr0->Mc, rw, sc.ec, cur, true, nb, Addr(N), Addr(Nc), st);
+    }
+    for (int sw = sw0; sw < nu; ++sw) {
       if (sw == nu - 1) {
         launch_stencil<T, T, T, T>(p, ST_SMOOTH, fine, cur, Addr(N), f, af, z, az, nb, st);
       } else {

@@ -15,6 +15,7 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 
 #include "hz_common.h"
 
@@ -26,18 +27,37 @@ constexpr int BX = 64;   // macro points per tile along x (one wavefront)
 
 __device__ __forceinline__ int region(int a, int M) { return a == 0 ? 0 : (a == M - 1 ? 2 : 1); }
 
+// Coarse-grid correction added while staging (ST_SMOOTH_PC): coarse vector, its batch
+// offsets, coarse lattice size and prolongation weights.
+template <typename T>
+struct Corr {
+  const V2<T>* ec = nullptr;
+  Addr ac;
+  int Mc = 0;
+  const T* rw = nullptr;
+};
+
 // A tile is BX x BYT macro points (each p x p lattice points) plus a p-halo, staged in LDS;
 // 256 threads = 64 columns x 4 rows, each thread BYT / 4 macro rows. XCD: the tiles are
 // renumbered so that workgroup b (dispatched round-robin over the 8 XCDs, each with its own
 // L2) takes the tiles of band b mod 8 in row order, so that the halo rows shared by
 // vertically adjacent tiles are read through the same L2.
+// ST_SMOOTH_PC first stages the coarse points whose prolongation reaches the tile (and the
+// weight table), then stages v = x + P ec in 2 x 2 fine blocks: per fine point the coarse
+// terms in ascending (B, A) order, as the prolongation kernel sums them, then the fine value
+// added.
 template <int P, typename T, typename TX, typename TF, typename TY, int MODE, int BYT, bool XCD>
 __global__ void __launch_bounds__(256)
 k_stencil(DevOp<T> op, const V2<TX>* __restrict__ x, Addr ax, const V2<TF>* __restrict__ f,
-          Addr af, V2<TY>* __restrict__ y, Addr ay) {
+          Addr af, V2<TY>* __restrict__ y, Addr ay, Corr<T> cr) {
   constexpr int W = 2 * P + 1, W2 = W * W;
   constexpr int LW = P * BX + 2 * P, LH = P * BYT + 2 * P;
+  constexpr bool PC = MODE == ST_SMOOTH_PC;
+  constexpr int WR = 4 * P + 1;
+  constexpr int CW = PC ? (LW + 4 * P + 3) / 2 + 1 : 1, CH = PC ? (LH + 4 * P + 3) / 2 + 1 : 1;
   __shared__ V2<T> tile[LH][LW];
+  __shared__ V2<T> ctile[CH][CW];
+  __shared__ T wl[PC && P > 1 ? P * P * WR * WR : 1];
   const int M = op.M;
   const int nmac = (M + P - 1) / P;
   const int ntx = (nmac + BX - 1) / BX, nty = (nmac + BYT - 1) / BYT;
@@ -55,16 +75,113 @@ k_stencil(DevOp<T> op, const V2<TX>* __restrict__ x, Addr ax, const V2<TF>* __re
   if (MODE != ST_APPLY) f += af.at(bz);
   const int I0 = (tnum % ntx) * BX, J0 = (tnum / ntx) * BYT;
   const int ax0 = P * I0 - P, by0 = P * J0 - P;
-  for (int idx = threadIdx.x; idx < LW * LH; idx += 256) {
-    const int ly = idx / LW, lx = idx - ly * LW;
-    const int a = ax0 + lx, b = by0 + ly;
-    V2<T> v = czero<T>();
-    if (a >= 0 && a < M && b >= 0 && b < M) {
-      v = cvt<T>(x[long(b) * M + a]);
-      if constexpr (MODE == ST_SMOOTH0)    // the first sweep from zero: u1 = wdinv f
-        v = cmul<T>(wdinv[((b % P) * P + (a % P)) * 9 + region(b, M) * 3 + region(a, M)], v);
+  const int CA0 = (ax0 - 2 * P) >> 1, CB0 = (by0 - 2 * P) >> 1;   // floor
+  if constexpr (PC) {
+    // 2 x 2 fine blocks (2 At + i, 2 Bt + j): the (2P+1)^2 coarse points around (At, Bt) are
+    // every coarse point whose prolongation reaches the block, and the weight offsets
+    // (dx, dy) = (i + 2P - 2 ja, j + 2P - 2 jb) are compile-time constants. Every global load
+    // of the staging (the coarse tile, the fine values) is issued before the one barrier.
+    constexpr int NB = 2 * P + 1;
+    constexpr int NBX = LW / 2 + 2, NBY = LH / 2 + 2;
+    constexpr int NCT = (CW * CH + 255) / 256, NBL = (NBX * NBY + 255) / 256;
+    const V2<T>* __restrict__ ec = cr.ec + cr.ac.at(bz);
+    const int Mc = cr.Mc;
+    const int bx0 = ax0 >> 1, by0c = by0 >> 1;
+    V2<T> cl[NCT];
+#pragma unroll
+    for (int q = 0; q < NCT; ++q) {
+      const int idx = threadIdx.x + 256 * q;
+      const int cy = idx / CW, cx = idx - cy * CW;
+      const int A = CA0 + cx, B = CB0 + cy;
+      cl[q] = (idx < CW * CH && A >= 0 && A < Mc && B >= 0 && B < Mc) ? ec[long(B) * Mc + A]
+                                                                      : czero<T>();
     }
-    tile[ly][lx] = v;
+    V2<T> xl[NBL][2][2];
+#pragma unroll
+    for (int q = 0; q < NBL; ++q) {
+      const int idx = threadIdx.x + 256 * q;
+      const int qy = idx / NBX, qx = idx - qy * NBX;
+      const int At = bx0 + qx, Bt = by0c + qy;
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int a = 2 * At + i, b = 2 * Bt + j;
+          const int lx = a - ax0, ly = b - by0;
+          const bool in = idx < NBX * NBY && lx >= 0 && lx < LW && ly >= 0 && ly < LH &&
+                          a >= 0 && a < M && b >= 0 && b < M;
+          xl[q][j][i] = in ? cvt<T>(x[long(b) * M + a]) : czero<T>();
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NCT; ++q) {
+      const int idx = threadIdx.x + 256 * q;
+      if (idx < CW * CH) ctile[idx / CW][idx % CW] = cl[q];
+    }
+    if (P > 1)
+      for (int idx = threadIdx.x; idx < P * P * WR * WR; idx += 256) wl[idx] = cr.rw[idx];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NBL; ++q) {
+      const int idx = threadIdx.x + 256 * q;
+      if (idx >= NBX * NBY) continue;
+      const int qy = idx / NBX, qx = idx - qy * NBX;
+      const int At = bx0 + qx, Bt = by0c + qy;
+      if (2 * At > ax0 + LW - 1 || 2 * Bt > by0 + LH - 1) continue;
+      V2<T> cv[NB][NB];
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+        for (int ja = 0; ja < NB; ++ja) cv[jb][ja] = ctile[Bt - P + jb - CB0][At - P + ja - CA0];
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int a = 2 * At + i, b = 2 * Bt + j;
+          const int lx = a - ax0, ly = b - by0;
+          if (lx < 0 || lx >= LW || ly < 0 || ly >= LH) continue;
+          V2<T> v = czero<T>();
+          if (a >= 0 && a < M && b >= 0 && b < M) {
+            V2<T> pe = czero<T>();
+            sfor<0, NB>([&](auto jb_) {
+              constexpr int jb = decltype(jb_)::value;
+              constexpr int dy0 = 2 * P - 2 * jb;           // dy = j + dy0
+              const int B = Bt - P + jb;
+              sfor<0, NB>([&](auto ja_) {
+                constexpr int ja = decltype(ja_)::value;
+                constexpr int dx0 = 2 * P - 2 * ja;
+                const int A = At - P + ja;
+                const int dy = j + dy0, dx = i + dx0;
+                if (dy >= -2 * P && dy <= 2 * P && dx >= -2 * P && dx <= 2 * P && B >= 0 &&
+                    B < Mc && A >= 0 && A < Mc) {
+                  // P = 1: one class, the weight index is a constant (a wave-uniform load)
+                  const int cls = P == 1 ? 0 : (B % P) * P + (A % P);
+                  const int wi = (cls * WR + dy + 2 * P) * WR + dx + 2 * P;
+                  const T wt = P == 1 ? cr.rw[wi] : wl[wi];
+                  if (wt != T(0)) {
+                    pe.x += wt * cv[jb][ja].x;
+                    pe.y += wt * cv[jb][ja].y;
+                  }
+                }
+              });
+            });
+            v = cadd<T>(pe, xl[q][j][i]);
+          }
+          tile[ly][lx] = v;
+        }
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < LW * LH; idx += 256) {
+      const int ly = idx / LW, lx = idx - ly * LW;
+      const int a = ax0 + lx, b = by0 + ly;
+      V2<T> v = czero<T>();
+      if (a >= 0 && a < M && b >= 0 && b < M) {
+        v = cvt<T>(x[long(b) * M + a]);
+        if constexpr (MODE == ST_SMOOTH0)    // the first sweep from zero: u1 = wdinv f
+          v = cmul<T>(wdinv[((b % P) * P + (a % P)) * 9 + region(b, M) * 3 + region(a, M)], v);
+      }
+      tile[ly][lx] = v;
+    }
   }
   __syncthreads();
   const int tx = threadIdx.x % BX;
@@ -131,7 +248,7 @@ k_stencil(DevOp<T> op, const V2<TX>* __restrict__ x, Addr ax, const V2<TF>* __re
       V2<T> out = acc[cb][ca];
       if constexpr (MODE == ST_RESID) {
         out = csub<T>(cvt<T>(f[gi]), out);
-      } else if constexpr (MODE == ST_SMOOTH || MODE == ST_SMOOTH0) {
+      } else if constexpr (MODE == ST_SMOOTH || MODE == ST_SMOOTH0 || PC) {
         const V2<T> d = wdinv[(cb * P + ca) * 9 + reg[cb][ca]];
         const V2<T> rr = csub<T>(cvt<T>(f[gi]), out);
         out = cadd<T>(tile[P * ty + P + cb][P * tx + P + ca], cmul<T>(d, rr));
@@ -336,22 +453,23 @@ constexpr StencilVariant kVariants[] = {{4, false}, {4, true}, {8, false}, {8, t
 
 template <int P, typename T, typename TX, typename TF, typename TY, int MODE, int BYT, bool XCD>
 void stencil_launch(const DevOp<T>& op, const V2<TX>* x, Addr xs, const V2<TF>* f, Addr fs,
-                    V2<TY>* y, Addr ys, int nbatch, hipStream_t st) {
+                    V2<TY>* y, Addr ys, int nbatch, hipStream_t st, const Corr<T>& cr) {
   const int nmac = (op.M + P - 1) / P;
   const int ntiles = ((nmac + BX - 1) / BX) * ((nmac + BYT - 1) / BYT);
   const int blocks = XCD ? 8 * ((ntiles + 7) / 8) : ntiles;
-  k_stencil<P, T, TX, TF, TY, MODE, BYT, XCD><<<dim3(blocks, nbatch), 256, 0, st>>>(op, x, xs, f, fs, y, ys);
+  k_stencil<P, T, TX, TF, TY, MODE, BYT, XCD><<<dim3(blocks, nbatch), 256, 0, st>>>(op, x, xs, f, fs, y, ys, cr);
 }
 
 template <int P, typename T, typename TX, typename TF, typename TY, int MODE>
 void stencil_variant(int v, const DevOp<T>& op, const V2<TX>* x, Addr xs, const V2<TF>* f,
-                     Addr fs, V2<TY>* y, Addr ys, int nbatch, hipStream_t st) {
+                     Addr fs, V2<TY>* y, Addr ys, int nbatch, hipStream_t st,
+                     const Corr<T>& cr = Corr<T>()) {
   // taller tiles only where their LDS stays small (P <= 2)
-  if (v == 1) stencil_launch<P, T, TX, TF, TY, MODE, 4, true>(op, x, xs, f, fs, y, ys, nbatch, st);
-  else if (v == 2 && P <= 2) stencil_launch<P, T, TX, TF, TY, MODE, (P <= 2 ? 8 : 4), false>(op, x, xs, f, fs, y, ys, nbatch, st);
-  else if (v == 3 && P <= 2) stencil_launch<P, T, TX, TF, TY, MODE, (P <= 2 ? 8 : 4), true>(op, x, xs, f, fs, y, ys, nbatch, st);
-  else if (v == 4 && P == 1) stencil_launch<P, T, TX, TF, TY, MODE, (P == 1 ? 16 : 4), true>(op, x, xs, f, fs, y, ys, nbatch, st);
-  else stencil_launch<P, T, TX, TF, TY, MODE, 4, false>(op, x, xs, f, fs, y, ys, nbatch, st);
+  if (v == 1) stencil_launch<P, T, TX, TF, TY, MODE, 4, true>(op, x, xs, f, fs, y, ys, nbatch, st, cr);
+  else if (v == 2 && P <= 2) stencil_launch<P, T, TX, TF, TY, MODE, (P <= 2 ? 8 : 4), false>(op, x, xs, f, fs, y, ys, nbatch, st, cr);
+  else if (v == 3 && P <= 2) stencil_launch<P, T, TX, TF, TY, MODE, (P <= 2 ? 8 : 4), true>(op, x, xs, f, fs, y, ys, nbatch, st, cr);
+  else if (v == 4 && P == 1) stencil_launch<P, T, TX, TF, TY, MODE, (P == 1 ? 16 : 4), true>(op, x, xs, f, fs, y, ys, nbatch, st, cr);
+  else stencil_launch<P, T, TX, TF, TY, MODE, 4, false>(op, x, xs, f, fs, y, ys, nbatch, st, cr);
 }
 
 // Autotuner: the first launch of a (kernel, lattice size, batch bucket) times every variant
@@ -419,14 +537,27 @@ int forced_variant() {
   return (e && *e) ? std::atoi(e) : -1;
 }
 
+// HZ_FUSE_PC=0: the coarse correction as its own prolongation-add pass (for comparison).
+bool smooth_pc_disabled() {
+  static const bool off = [] {
+    const char* e = std::getenv("HZ_FUSE_PC");
+    return e && e[0] == '0';
+  }();
+  return off;
+}
+
 template <int P, typename T, typename TX, typename TF, typename TY>
 void stencil_p(int mode, const DevOp<T>& op, const V2<TX>* x, Addr xs, const V2<TF>* f, Addr fs,
-               V2<TY>* y, Addr ys, int nbatch, hipStream_t st) {
+               V2<TY>* y, Addr ys, int nbatch, hipStream_t st, const Corr<T>& cr = Corr<T>()) {
   auto launch = [&](int v) {
     if (mode == ST_APPLY) stencil_variant<P, T, TX, TF, TY, ST_APPLY>(v, op, x, xs, f, fs, y, ys, nbatch, st);
     else if (mode == ST_RESID) stencil_variant<P, T, TX, TF, TY, ST_RESID>(v, op, x, xs, f, fs, y, ys, nbatch, st);
     else if (mode == ST_SMOOTH) stencil_variant<P, T, TX, TF, TY, ST_SMOOTH>(v, op, x, xs, f, fs, y, ys, nbatch, st);
-    else stencil_variant<P, T, TX, TF, TY, ST_SMOOTH0>(v, op, x, xs, f, fs, y, ys, nbatch, st);
+    else if (mode == ST_SMOOTH0) stencil_variant<P, T, TX, TF, TY, ST_SMOOTH0>(v, op, x, xs, f, fs, y, ys, nbatch, st);
+    else if constexpr (P <= 2 && std::is_same<T, TX>::value && std::is_same<T, TF>::value &&
+                       std::is_same<T, TY>::value)
+      stencil_variant<P, T, TX, TF, TY, ST_SMOOTH_PC>(v, op, x, xs, f, fs, y, ys, nbatch, st, cr);
+    else throw std::runtime_error("stencil: mode not provided for this order or type");
   };
   const int nvar = P == 1 ? 5 : P == 2 ? 4 : 2;
   const int fv = forced_variant();
@@ -458,6 +589,23 @@ void launch_stencil(int p, int mode, const DevOp<T>& op, const V2<TX>* x, Addr x
   else if (p == 2) stencil_p<2, T, TX, TF, TY>(mode, op, x, xs, f, fs, y, ys, nbatch, st);
   else stencil_p<3, T, TX, TF, TY>(mode, op, x, xs, f, fs, y, ys, nbatch, st);
   HZ_HIP(hipGetLastError());
+}
+
+template <typename T>
+bool launch_smooth_pc(int p, const DevOp<T>& op, const V2<T>* x, Addr ax, const V2<T>* ec,
+                      Addr ac, int Mc, const T* rw, const V2<T>* f, Addr af, V2<T>* y, Addr ay,
+                      int nbatch, hipStream_t st) {
+  if (op.pn || p > 2 || smooth_pc_disabled()) return false;
+  if (op.M != 2 * (Mc - 1) + 1) throw std::runtime_error("smooth_pc: lattice sizes");
+  Corr<T> cr;
+  cr.ec = ec;
+  cr.ac = ac;
+  cr.Mc = Mc;
+  cr.rw = rw;
+  if (p == 1) stencil_p<1, T, T, T, T>(ST_SMOOTH_PC, op, x, ax, f, af, y, ay, nbatch, st, cr);
+  else stencil_p<2, T, T, T, T>(ST_SMOOTH_PC, op, x, ax, f, af, y, ay, nbatch, st, cr);
+  HZ_HIP(hipGetLastError());
+  return true;
 }
 
 template <typename T, typename TF>
@@ -527,6 +675,10 @@ void launch_f2d(const float2* x, double2* y, long n, hipStream_t st) {
 }
 
 // Instantiations used by the driver.
+template bool launch_smooth_pc<double>(int, const DevOp<double>&, const double2*, Addr,
+    const double2*, Addr, int, const double*, const double2*, Addr, double2*, Addr, int, hipStream_t);
+template bool launch_smooth_pc<float>(int, const DevOp<float>&, const float2*, Addr,
+    const float2*, Addr, int, const float*, const float2*, Addr, float2*, Addr, int, hipStream_t);
 template void launch_stencil<double, double, double, double>(int, int, const DevOp<double>&,
     const double2*, Addr, const double2*, Addr, double2*, Addr, int, hipStream_t);
 template void launch_stencil<double, float, double, double>(int, int, const DevOp<double>&,

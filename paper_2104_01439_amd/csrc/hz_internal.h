@@ -119,7 +119,7 @@ struct CoarseLayout {
 // Launchers (hz_fine.hip, hz_coarse.hip, hz_krylov.hip)
 // ------------------------------------------------------------------------------------------
 
-enum StencilMode { ST_APPLY = 0, ST_RESID = 1, ST_SMOOTH = 2, ST_SMOOTH0 = 3 };
+enum StencilMode { ST_APPLY = 0, ST_RESID = 1, ST_SMOOTH = 2, ST_SMOOTH0 = 3, ST_SMOOTH_PC = 4 };
 
 // y = A x  |  y = f - A x  |  y = x + wdinv (f - A x)   on one level, lattice M x M;
 // ST_SMOOTH0: the first two Jacobi sweeps from a zero iterate in one pass, y = u1 + wdinv
@@ -129,6 +129,15 @@ enum StencilMode { ST_APPLY = 0, ST_RESID = 1, ST_SMOOTH = 2, ST_SMOOTH0 = 3 };
 template <typename T, typename TX, typename TF, typename TY>
 void launch_stencil(int p, int mode, const DevOp<T>& op, const V2<TX>* x, Addr ax,
                     const V2<TF>* f, Addr af, V2<TY>* y, Addr ay, int nbatch, hipStream_t st);
+// The first post-smoothing sweep with the coarse-grid correction (Alg. 1): y = v + wdinv
+// (f - A v) with v = x + P ec formed while staging (coarse vector ec at ec + ac.at(z), Mc x Mc
+// lattice, prolongation weights rw); bitwise the prolongation-add followed by an ST_SMOOTH
+// sweep. Returns false (launching nothing) where it is not provided: per-point operators and
+// p = 3, whose staged tiles would not leave room for the coarse tile.
+template <typename T>
+bool launch_smooth_pc(int p, const DevOp<T>& op, const V2<T>* x, Addr ax, const V2<T>* ec,
+                      Addr ac, int Mc, const T* rw, const V2<T>* f, Addr af, V2<T>* y, Addr ay,
+                      int nbatch, hipStream_t st);
 // The same for per-point operators (op.pn = 1); called by launch_stencil.
 template <typename T, typename TX, typename TF, typename TY>
 void launch_stencil_pn(int p, int mode, const DevOp<T>& op, const V2<TX>* x, Addr ax,
