@@ -115,7 +115,7 @@ struct Workspace {
   double2* Us = nullptr;    // [cap][N] staged solutions (batched calls)
   double2* Zd = nullptr;    // [cap][m][N] preconditioned vectors (FP64)
   float2* Zf = nullptr;     // [cap][m][N] preconditioned vectors (mixed precision)
-  double2* partial = nullptr;   // [cap][nblk][64]
+  double2* partial = nullptr;   // [cap][blocks][64]
   double2* hbuf = nullptr;      // [cap][192]: CGS2 pass 1, pass 2, |w|^2
   char* dreg = nullptr;         // device copies of the two upload regions
   void* gb = nullptr;           // [cap][Nc] coarse forward-sweep buffers (per solve)
@@ -1153,9 +1153,9 @@ struct Lockstep {
     launch_maxpy_mdot_b(ws->V, Addr(0, d_vb), N, round_nv, d.itab, ws->hbuf, 192, ws->RW,
                         Addr(0, d_w), N, ws->partial, na, st);
     launch_reduce_b(ws->partial, fused_blocks(N), 64, d.itab, ws->hbuf + 64, 192, na, st);
-    launch_maxpy_b(ws->V, Addr(0, d_vb), N, 64, d.itab, ws->hbuf + 64, 192, ws->RW, Addr(0, d_w), N,
-                   ws->partial, nblk, na, st);
-    launch_reduce_b(ws->partial, nblk, 1, nullptr, ws->hbuf + 128, 192, na, st);
+    launch_maxpy_b(ws->V, Addr(0, d_vb), N, round_nv, d.itab, ws->hbuf + 64, 192, ws->RW,
+                   Addr(0, d_w), N, ws->partial, na, st);
+    launch_reduce_b(ws->partial, fused_blocks(N), 1, nullptr, ws->hbuf + 128, 192, na, st);
     read_back(na, st);
   }
 

@@ -342,12 +342,13 @@ void set_stencil_tuning(bool on);
 
 // Krylov kernels. Vectors of length N; a basis V is row-major [nv][ldv].
 // Batched forms run nbatch independent instances: instance z uses V + av.at(z), w + aw.at(z),
-// its partial sums at partial + z nblk 64, its small vectors (h, y) at z hs, and its own
-// vector count nvt[z] when the table is given (0 = nothing to do), else nv.
-int mdot_blocks(long N);
-int fused_blocks(long N);     // blocks (partial sums) of launch_maxpy_mdot_b
-// w -= V h, then partial sums of V^H w (the new w) from the same read of V; nv bounds the
-// per-instance counts nvt (the kernel keeps up to 64 basis entries per element in registers).
+// its partial sums at partial + z nblk 64 (block b's sums at b 64), its small vectors (h, y)
+// at z hs, and its own vector count nvt[z] when the table is given (0 = nothing to do), else
+// nv. For launch_maxpy(_b) and launch_maxpy_mdot_b nv bounds the per-instance counts: they
+// keep up to nv (<= 64) basis entries per element in registers.
+int mdot_blocks(long N);      // blocks (partial sums) of launch_mdot(_b)
+int fused_blocks(long N);     // blocks (partial sums) of launch_maxpy(_b), launch_maxpy_mdot_b
+// w -= V h, then partial sums of V^H w (the new w) from the same read of V.
 void launch_maxpy_mdot_b(const double2* V, Addr av, long ldv, int nv, const int* nvt,
                          const double2* h, long hs, double2* w, Addr aw, long N,
                          double2* partial, int nbatch, hipStream_t st);
@@ -359,12 +360,13 @@ void launch_mdot_b(const double2* V, Addr av, long ldv, int nv, const int* nvt, 
 void launch_reduce(const double2* partial, int nblk, int nv, double2* out, hipStream_t st);
 void launch_reduce_b(const double2* partial, int nblk, int nv, const int* nvt, double2* out,
                      long hs, int nbatch, hipStream_t st);
-// w -= V h (h on device, nv entries); optionally accumulates |w|^2 partials (nv index 0).
+// w -= V h (h on device, nv entries); optionally |w|^2 partials (index 0 of fused_blocks(N)
+// blocks).
 void launch_maxpy(const double2* V, long ldv, int nv, const double2* h, double2* w, long N,
-                  double2* norm_partial, int nblk, hipStream_t st);
+                  double2* norm_partial, hipStream_t st);
 void launch_maxpy_b(const double2* V, Addr av, long ldv, int nv, const int* nvt, const double2* h,
-                    long hs, double2* w, Addr aw, long N, double2* norm_partial, int nblk,
-                    int nbatch, hipStream_t st);
+                    long hs, double2* w, Addr aw, long N, double2* norm_partial, int nbatch,
+                    hipStream_t st);
 // v = s[z] w (per-instance factor on the device)
 void launch_scale_b(const double2* w, Addr aw, const double* s_dev, double2* v, Addr av, long N,
                     int nbatch, hipStream_t st);

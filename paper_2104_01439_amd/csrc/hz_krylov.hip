@@ -55,17 +55,19 @@ k_mdot(const V2<TV>* __restrict__ V, Addr av, long ldv, int nv, const int* __res
   }
 }
 
-// out[i] = sum_b partial[b][i] in a fixed order; one workgroup per i.
-__global__ void __launch_bounds__(256)
+// out[i] = sum_b partial[b][i] in a fixed order; one workgroup of 1024 threads per i (few
+// workgroups: the loads in flight per workgroup set the speed).
+__global__ void __launch_bounds__(1024)
 k_reduce(const double2* __restrict__ partial, int nblk, const int* __restrict__ nvt,
          double2* __restrict__ out, long ostride) {
-  __shared__ double sx[256], sy[256];
+  __shared__ double sx[1024], sy[1024];
   const int i = blockIdx.x;
   const int bz = blockIdx.y;
   if (nvt && i >= nvt[bz]) return;
   partial += long(bz) * nblk * 64;
   double ax = 0, ay = 0;
-  for (int b = threadIdx.x; b < nblk; b += 256) {
+#pragma unroll 8
+  for (int b = threadIdx.x; b < nblk; b += 1024) {
     const double2 v = partial[long(b) * 64 + i];
     ax += v.x;
     ay += v.y;
@@ -73,7 +75,7 @@ k_reduce(const double2* __restrict__ partial, int nblk, const int* __restrict__ 
   sx[threadIdx.x] = ax;
   sy[threadIdx.x] = ay;
   __syncthreads();
-  for (int s = 128; s >= 1; s >>= 1) {
+  for (int s = 512; s >= 1; s >>= 1) {
     if (threadIdx.x < s) {
       sx[threadIdx.x] += sx[threadIdx.x + s];
       sy[threadIdx.x] += sy[threadIdx.x + s];
@@ -83,9 +85,12 @@ k_reduce(const double2* __restrict__ partial, int nblk, const int* __restrict__ 
   if (threadIdx.x == 0) out[bz * ostride + i] = make_double2(sx[0], sy[0]);
 }
 
-// w -= sum_i V[i] h[i]; optionally partial[blk][0] = sum |w_new|^2 over the chunk.
-template <bool NORM>
-__global__ void __launch_bounds__(256)
+// w -= sum_i V[i] h[i] (ascending i); optionally partial[b][0] = sum |w_new|^2 over the
+// workgroup. One element per thread with its column of V (up to NVB basis vectors, NVB a
+// multiple of 8 >= the largest basis size of the launch) in registers, every load issued
+// before the barrier that stages h.
+template <int NVB, bool NORM>
+__global__ void __launch_bounds__(256, 1)
 k_maxpy(const double2* __restrict__ V, Addr av, long ldv, int nv, const int* __restrict__ nvt,
         const double2* __restrict__ h, long hstride, double2* __restrict__ w, Addr aw, long N,
         double2* __restrict__ partial, int nblk) {
@@ -97,25 +102,25 @@ k_maxpy(const double2* __restrict__ V, Addr av, long ldv, int nv, const int* __r
   V += av.at(bz);
   w += aw.at(bz);
   h += bz * hstride;
+  const long k = long(blockIdx.x) * 256 + threadIdx.x;
+  const bool in = k < N;
+  double2 vv[NVB];
+#pragma unroll
+  for (int i = 0; i < NVB; ++i) vv[i] = (i < nv && in) ? V[i * ldv + k] : make_double2(0, 0);
+  double2 acc = in ? w[k] : make_double2(0, 0);
   if (threadIdx.x < nv) hs[threadIdx.x] = h[threadIdx.x];
   __syncthreads();
-  const long base = long(blockIdx.x) * CHUNK + threadIdx.x;
-  double nrm = 0;
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const long k = base + q * 256;
-    if (k >= N) continue;
-    double2 acc = w[k];
-    for (int i = 0; i < nv; ++i) {
-      const double2 v = V[i * ldv + k];
+  for (int i = 0; i < NVB; ++i) {
+    if (i < nv) {
       const double2 hh = hs[i];
-      acc.x -= v.x * hh.x - v.y * hh.y;
-      acc.y -= v.x * hh.y + v.y * hh.x;
+      acc.x -= vv[i].x * hh.x - vv[i].y * hh.y;
+      acc.y -= vv[i].x * hh.y + vv[i].y * hh.x;
     }
-    w[k] = acc;
-    if (NORM) nrm += acc.x * acc.x + acc.y * acc.y;
   }
+  if (in) w[k] = acc;
   if (NORM) {
+    double nrm = acc.x * acc.x + acc.y * acc.y;
     nrm = wave_sum(nrm);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
     __syncthreads();
@@ -240,6 +245,17 @@ __global__ void k_copy(const double2* __restrict__ x, Addr ax, double2* __restri
 int mdot_blocks(long N) { return int((N + CHUNK - 1) / CHUNK); }
 int fused_blocks(long N) { return int((N + 255) / 256); }
 
+// NVB bucket (a multiple of 8, at least nv) of a launch whose basis sizes are at most nv.
+#define HZ_NVB(MACRO)                \
+  if (nv <= 8) { MACRO(8); }         \
+  else if (nv <= 16) { MACRO(16); }  \
+  else if (nv <= 24) { MACRO(24); }  \
+  else if (nv <= 32) { MACRO(32); }  \
+  else if (nv <= 40) { MACRO(40); }  \
+  else if (nv <= 48) { MACRO(48); }  \
+  else if (nv <= 56) { MACRO(56); }  \
+  else { MACRO(64); }
+
 void launch_maxpy_mdot_b(const double2* V, Addr av, long ldv, int nv, const int* nvt,
                          const double2* h, long hs, double2* w, Addr aw, long N,
                          double2* partial, int nbatch, hipStream_t st) {
@@ -247,14 +263,7 @@ void launch_maxpy_mdot_b(const double2* V, Addr av, long ldv, int nv, const int*
   const dim3 g(unsigned(fused_blocks(N)), nbatch);
   const int nb = fused_blocks(N);
 #define HZ_MM(B) k_maxpy_mdot<B><<<g, 256, 0, st>>>(V, av, ldv, nv, nvt, h, hs, w, aw, N, partial, nb)
-  if (nv <= 8) HZ_MM(8);
-  else if (nv <= 16) HZ_MM(16);
-  else if (nv <= 24) HZ_MM(24);
-  else if (nv <= 32) HZ_MM(32);
-  else if (nv <= 40) HZ_MM(40);
-  else if (nv <= 48) HZ_MM(48);
-  else if (nv <= 56) HZ_MM(56);
-  else HZ_MM(64);
+  HZ_NVB(HZ_MM)
 #undef HZ_MM
   HZ_HIP(hipGetLastError());
 }
@@ -278,32 +287,35 @@ void launch_mdot_b(const double2* V, Addr av, long ldv, int nv, const int* nvt, 
 }
 
 void launch_reduce(const double2* partial, int nblk, int nv, double2* out, hipStream_t st) {
-  k_reduce<<<dim3(nv, 1), 256, 0, st>>>(partial, nblk, nullptr, out, 0);
+  k_reduce<<<dim3(nv, 1), 1024, 0, st>>>(partial, nblk, nullptr, out, 0);
   HZ_HIP(hipGetLastError());
 }
 
 void launch_reduce_b(const double2* partial, int nblk, int nv, const int* nvt, double2* out,
                      long hs, int nbatch, hipStream_t st) {
   if (nbatch <= 0 || nv <= 0) return;
-  k_reduce<<<dim3(nv, nbatch), 256, 0, st>>>(partial, nblk, nvt, out, hs);
+  k_reduce<<<dim3(nv, nbatch), 1024, 0, st>>>(partial, nblk, nvt, out, hs);
   HZ_HIP(hipGetLastError());
 }
 
 void launch_maxpy(const double2* V, long ldv, int nv, const double2* h, double2* w, long N,
-                  double2* norm_partial, int nblk, hipStream_t st) {
-  launch_maxpy_b(V, Addr(), ldv, nv, nullptr, h, 0, w, Addr(), N, norm_partial, nblk, 1, st);
+                  double2* norm_partial, hipStream_t st) {
+  launch_maxpy_b(V, Addr(), ldv, nv, nullptr, h, 0, w, Addr(), N, norm_partial, 1, st);
 }
 
 void launch_maxpy_b(const double2* V, Addr av, long ldv, int nv, const int* nvt, const double2* h,
-                    long hs, double2* w, Addr aw, long N, double2* norm_partial, int nblk,
-                    int nbatch, hipStream_t st) {
+                    long hs, double2* w, Addr aw, long N, double2* norm_partial, int nbatch,
+                    hipStream_t st) {
   if (nbatch <= 0) return;
-  if (norm_partial)
-    k_maxpy<true><<<dim3(nblk, nbatch), 256, 0, st>>>(V, av, ldv, nv, nvt, h, hs, w, aw, N,
-                                                       norm_partial, nblk);
-  else
-    k_maxpy<false><<<dim3(nblk, nbatch), 256, 0, st>>>(V, av, ldv, nv, nvt, h, hs, w, aw, N,
-                                                        nullptr, nblk);
+  const int nb = fused_blocks(N);
+  const dim3 g(unsigned(nb), nbatch);
+#define HZ_MX(B)                                                                                \
+  if (norm_partial)                                                                             \
+    k_maxpy<B, true><<<g, 256, 0, st>>>(V, av, ldv, nv, nvt, h, hs, w, aw, N, norm_partial, nb); \
+  else                                                                                          \
+    k_maxpy<B, false><<<g, 256, 0, st>>>(V, av, ldv, nv, nvt, h, hs, w, aw, N, nullptr, nb);
+  HZ_NVB(HZ_MX)
+#undef HZ_MX
   HZ_HIP(hipGetLastError());
 }
 

@@ -8,7 +8,9 @@ runs, each on torch's current stream:
   * `--stencils` applications of each other fine-level pass of the V-cycle (Jacobi sweep,
     residual + restriction, restriction, prolongation);
   * `--coarse-solves` coarse direct solves (multifrontal: every stored factor entry read
-    once; bytes per system from the problem's own counters).
+    once; bytes per system from the problem's own counters);
+  * `--vcycles` whole V-cycles (their fine passes include the post-smoothing sweep that
+    stages the coarse-grid correction itself).
 It prints the device time of each group from HIP events and the algorithmic bytes, so that
 counter totals can be set against them:
 
@@ -28,6 +30,7 @@ def main(argv=None):
     ap.add_argument("--applies", type=int, default=8)
     ap.add_argument("--coarse-solves", type=int, default=4)
     ap.add_argument("--stencils", type=int, default=0)
+    ap.add_argument("--vcycles", type=int, default=0)
     a = ap.parse_args(argv)
 
     import torch
@@ -76,6 +79,9 @@ def main(argv=None):
         for op, arg in (("JACOBI", x), ("RESID_RESTRICT", x), ("RESTRICT", x), ("PROLONG", xc)):
             ms = timed(lambda: pr.apply(op, arg, f, prec=a.prec), a.stencils)
             out[op] = {"ms": ms}
+    if a.vcycles:
+        ms = timed(lambda: pr.apply("VCYCLE", F, prec=a.prec), a.vcycles)
+        out["VCYCLE"] = {"ms": ms}
     if a.coarse_solves:
         rc = pr.apply("RESTRICT", F)
         pr.stats(reset=True)
