@@ -117,6 +117,7 @@ struct Workspace {
   float2* Zf = nullptr;     // [cap][m][N] preconditioned vectors (mixed precision)
   double2* partial = nullptr;   // [cap][blocks][64]
   double2* hbuf = nullptr;      // [cap][192]: CGS2 pass 1, pass 2, |w|^2
+  double2* red = nullptr;       // [cap][kReduceGroups][64] first-stage sums of the reductions
   char* dreg = nullptr;         // device copies of the two upload regions
   void* gb = nullptr;           // [cap][Nc] coarse forward-sweep buffers (per solve)
   Scratch<double> s64;
@@ -332,7 +333,8 @@ size_t workspace_bytes(long N, int nblk, int cap, int m, int prec, bool staged) 
   b += size_t(cap) * m * N * (prec == HZ_MIXED ? 8 : 16);       // Z
   b += 2 * size_t(cap) * N * 16;                                // r, w
   if (staged) b += 2 * size_t(cap) * N * 16;                    // F, u
-  b += size_t(cap) * (size_t(fused_blocks(N)) * 64 * 16 + 192 * 16 + 64 * 16 + 8);
+  b += size_t(cap) * (size_t(fused_blocks(N)) * 64 * 16 + size_t(kReduceGroups) * 64 * 16 +
+                      192 * 16 + 64 * 16 + 8);
   b += 2 * size_t(cap) * (Workspace::kTabs * 8 + 2 * 4 + 8 + 3 * 8 + 64 * 16) + 4096;
   return b;
 }
@@ -533,6 +535,7 @@ std::unique_ptr<Workspace> make_workspace(int cap, int m, int prec, long N, long
   else w->Zd = w->mem.alloc<double2>(size_t(cap) * m * N);
   w->partial = w->mem.alloc<double2>(size_t(cap) * fused_blocks(N) * 64);
   w->hbuf = w->mem.alloc<double2>(size_t(cap) * 192);
+  w->red = w->mem.alloc<double2>(size_t(cap) * kReduceGroups * 64);
   w->up_bytes = region_bytes(cap);
   // device mirror of the two upload regions
   w->dreg = w->mem.alloc<char>(2 * w->up_bytes);
@@ -885,7 +888,7 @@ struct Lockstep {
     upload(0, st);
     launch_mdot_b(Fb, Addr(0, d.tab), 0, 1, nullptr, Fb, Addr(0, d.tab), N, ws->partial,
                   ws->nblk, nq, st);
-    launch_reduce_b(ws->partial, ws->nblk, 1, nullptr, ws->hbuf, 192, nq, st);
+    launch_reduce_b(ws->partial, ws->nblk, 1, nullptr, ws->hbuf, 192, nq, ws->red, st);
     launch_fill_zero_b(Ub, Addr(0, d.tab + cap), N, nq, st);
     launch_copy_b(Fb, Addr(0, d.tab), ws->RW, Addr(0, d.tab + 2 * cap), N, nq, st);
     read_back(nq, st);
@@ -1149,13 +1152,13 @@ struct Lockstep {
     // CGS2: two passes of h = V^H w, w -= V h; then |w|^2
     // (the first pass's update and the second pass's projection share one read of V)
     launch_mdot_b(ws->V, Addr(0, d_vb), N, 64, d.itab, ws->RW, Addr(0, d_w), N, ws->partial, nblk, na, st);
-    launch_reduce_b(ws->partial, nblk, 64, d.itab, ws->hbuf, 192, na, st);
+    launch_reduce_b(ws->partial, nblk, 64, d.itab, ws->hbuf, 192, na, ws->red, st);
     launch_maxpy_mdot_b(ws->V, Addr(0, d_vb), N, round_nv, d.itab, ws->hbuf, 192, ws->RW,
                         Addr(0, d_w), N, ws->partial, na, st);
-    launch_reduce_b(ws->partial, fused_blocks(N), 64, d.itab, ws->hbuf + 64, 192, na, st);
+    launch_reduce_b(ws->partial, fused_blocks(N), 64, d.itab, ws->hbuf + 64, 192, na, ws->red, st);
     launch_maxpy_b(ws->V, Addr(0, d_vb), N, round_nv, d.itab, ws->hbuf + 64, 192, ws->RW,
                    Addr(0, d_w), N, ws->partial, na, st);
-    launch_reduce_b(ws->partial, fused_blocks(N), 1, nullptr, ws->hbuf + 128, 192, na, st);
+    launch_reduce_b(ws->partial, fused_blocks(N), 1, nullptr, ws->hbuf + 128, 192, na, ws->red, st);
     read_back(na, st);
   }
 
@@ -1254,7 +1257,7 @@ struct Lockstep {
     }
     launch_mdot_b(ws->RW, Addr(0, d2.tab + 3 * cap), 0, 1, nullptr, ws->RW, Addr(0, d2.tab + 3 * cap),
                   N, ws->partial, ws->nblk, ne, st);
-    launch_reduce_b(ws->partial, ws->nblk, 1, nullptr, ws->hbuf, 192, ne, st);
+    launch_reduce_b(ws->partial, ws->nblk, 1, nullptr, ws->hbuf, 192, ne, ws->red, st);
     read_back(ne, st);
     HZ_HIP(hipStreamSynchronize(st));
     after_sync();

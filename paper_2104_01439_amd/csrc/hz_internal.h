@@ -352,18 +352,15 @@ int fused_blocks(long N);     // blocks (partial sums) of launch_maxpy(_b), laun
 void launch_maxpy_mdot_b(const double2* V, Addr av, long ldv, int nv, const int* nvt,
                          const double2* h, long hs, double2* w, Addr aw, long N,
                          double2* partial, int nbatch, hipStream_t st);
-template <typename TV>
-void launch_mdot(const V2<TV>* V, long ldv, int nv, const double2* w, long N, double2* partial,
-                 int nblk, hipStream_t st);
 void launch_mdot_b(const double2* V, Addr av, long ldv, int nv, const int* nvt, const double2* w,
                    Addr aw, long N, double2* partial, int nblk, int nbatch, hipStream_t st);
-void launch_reduce(const double2* partial, int nblk, int nv, double2* out, hipStream_t st);
+// out[z hs + i] = sum over the nblk partial sums of vector i (i < nvt[z], else nv), in a fixed
+// order, through work [nbatch][kReduceGroups][64].
+constexpr int kReduceGroups = 128;
 void launch_reduce_b(const double2* partial, int nblk, int nv, const int* nvt, double2* out,
-                     long hs, int nbatch, hipStream_t st);
+                     long hs, int nbatch, double2* work, hipStream_t st);
 // w -= V h (h on device, nv entries); optionally |w|^2 partials (index 0 of fused_blocks(N)
 // blocks).
-void launch_maxpy(const double2* V, long ldv, int nv, const double2* h, double2* w, long N,
-                  double2* norm_partial, hipStream_t st);
 void launch_maxpy_b(const double2* V, Addr av, long ldv, int nv, const int* nvt, const double2* h,
                     long hs, double2* w, Addr aw, long N, double2* norm_partial, int nbatch,
                     hipStream_t st);

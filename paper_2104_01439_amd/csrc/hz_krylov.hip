@@ -55,34 +55,75 @@ k_mdot(const V2<TV>* __restrict__ V, Addr av, long ldv, int nv, const int* __res
   }
 }
 
-// out[i] = sum_b partial[b][i] in a fixed order; one workgroup of 1024 threads per i (few
-// workgroups: the loads in flight per workgroup set the speed).
+// out[i] = sum_b partial[b][i] in a fixed order, in two stages. First stage: workgroup g of
+// instance bz sums block rows [g per, (g + 1) per) of every vector i < nv (1024 threads:
+// vector t % 64, row lane t / 64 taking every 16th row in ascending order, so a row's
+// vectors are read together), then its 16 row lanes in order, into work[bz][g][i].
 __global__ void __launch_bounds__(1024)
-k_reduce(const double2* __restrict__ partial, int nblk, const int* __restrict__ nvt,
-         double2* __restrict__ out, long ostride) {
-  __shared__ double sx[1024], sy[1024];
-  const int i = blockIdx.x;
+k_reduce1(const double2* __restrict__ partial, int nblk, int nv, const int* __restrict__ nvt,
+          double2* __restrict__ work) {
+  __shared__ double sx[16][64], sy[16][64];
   const int bz = blockIdx.y;
-  if (nvt && i >= nvt[bz]) return;
-  partial += long(bz) * nblk * 64;
+  const int nvb = nvt ? nvt[bz] : nv;
+  if (nvb <= 0) return;
+  const int i = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const int per = (nblk + kReduceGroups - 1) / kReduceGroups;
+  const int b0 = blockIdx.x * per, b1 = min(nblk, b0 + per);
+  const double2* __restrict__ pp = partial + long(bz) * nblk * 64;
   double ax = 0, ay = 0;
-#pragma unroll 8
-  for (int b = threadIdx.x; b < nblk; b += 1024) {
-    const double2 v = partial[long(b) * 64 + i];
-    ax += v.x;
-    ay += v.y;
-  }
-  sx[threadIdx.x] = ax;
-  sy[threadIdx.x] = ay;
-  __syncthreads();
-  for (int s = 512; s >= 1; s >>= 1) {
-    if (threadIdx.x < s) {
-      sx[threadIdx.x] += sx[threadIdx.x + s];
-      sy[threadIdx.x] += sy[threadIdx.x + s];
+  if (i < nvb) {
+#pragma unroll 4
+    for (int b = b0 + rl; b < b1; b += 16) {
+      const double2 v = pp[long(b) * 64 + i];
+      ax += v.x;
+      ay += v.y;
     }
-    __syncthreads();
   }
-  if (threadIdx.x == 0) out[bz * ostride + i] = make_double2(sx[0], sy[0]);
+  sx[rl][i] = ax;
+  sy[rl][i] = ay;
+  __syncthreads();
+  if (threadIdx.x < 64 && i < nvb) {
+    double tx = 0, ty = 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      tx += sx[r][i];
+      ty += sy[r][i];
+    }
+    work[(long(bz) * kReduceGroups + blockIdx.x) * 64 + i] = make_double2(tx, ty);
+  }
+}
+
+// Second stage: out[i] = the kReduceGroups first-stage sums in a fixed order (16 row lanes of
+// kReduceGroups / 16 sums each, then the lanes in order).
+__global__ void __launch_bounds__(1024)
+k_reduce2(const double2* __restrict__ work, int nv, const int* __restrict__ nvt,
+          double2* __restrict__ out, long ostride) {
+  __shared__ double sx[16][64], sy[16][64];
+  const int bz = blockIdx.y;
+  const int nvb = nvt ? nvt[bz] : nv;
+  if (nvb <= 0) return;
+  const int i = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  double ax = 0, ay = 0;
+  if (i < nvb) {
+#pragma unroll
+    for (int g = rl; g < kReduceGroups; g += 16) {
+      const double2 v = work[(long(bz) * kReduceGroups + g) * 64 + i];
+      ax += v.x;
+      ay += v.y;
+    }
+  }
+  sx[rl][i] = ax;
+  sy[rl][i] = ay;
+  __syncthreads();
+  if (threadIdx.x < 64 && i < nvb) {
+    double tx = 0, ty = 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      tx += sx[r][i];
+      ty += sy[r][i];
+    }
+    out[bz * ostride + i] = make_double2(tx, ty);
+  }
 }
 
 // w -= sum_i V[i] h[i] (ascending i); optionally partial[b][0] = sum |w_new|^2 over the
@@ -268,17 +309,6 @@ void launch_maxpy_mdot_b(const double2* V, Addr av, long ldv, int nv, const int*
   HZ_HIP(hipGetLastError());
 }
 
-template <typename TV>
-void launch_mdot(const V2<TV>* V, long ldv, int nv, const double2* w, long N, double2* partial,
-                 int nblk, hipStream_t st) {
-  k_mdot<TV><<<dim3(nblk, 1), 256, 0, st>>>(V, Addr(), ldv, nv, nullptr, w, Addr(), N, partial, nblk);
-  HZ_HIP(hipGetLastError());
-}
-template void launch_mdot<double>(const double2*, long, int, const double2*, long, double2*, int,
-                                  hipStream_t);
-template void launch_mdot<float>(const float2*, long, int, const double2*, long, double2*, int,
-                                 hipStream_t);
-
 void launch_mdot_b(const double2* V, Addr av, long ldv, int nv, const int* nvt, const double2* w,
                    Addr aw, long N, double2* partial, int nblk, int nbatch, hipStream_t st) {
   if (nbatch <= 0) return;
@@ -286,21 +316,12 @@ void launch_mdot_b(const double2* V, Addr av, long ldv, int nv, const int* nvt, 
   HZ_HIP(hipGetLastError());
 }
 
-void launch_reduce(const double2* partial, int nblk, int nv, double2* out, hipStream_t st) {
-  k_reduce<<<dim3(nv, 1), 1024, 0, st>>>(partial, nblk, nullptr, out, 0);
-  HZ_HIP(hipGetLastError());
-}
-
 void launch_reduce_b(const double2* partial, int nblk, int nv, const int* nvt, double2* out,
-                     long hs, int nbatch, hipStream_t st) {
+                     long hs, int nbatch, double2* work, hipStream_t st) {
   if (nbatch <= 0 || nv <= 0) return;
-  k_reduce<<<dim3(nv, nbatch), 1024, 0, st>>>(partial, nblk, nvt, out, hs);
+  k_reduce1<<<dim3(kReduceGroups, nbatch), 1024, 0, st>>>(partial, nblk, nv, nvt, work);
+  k_reduce2<<<dim3(1, nbatch), 1024, 0, st>>>(work, nv, nvt, out, hs);
   HZ_HIP(hipGetLastError());
-}
-
-void launch_maxpy(const double2* V, long ldv, int nv, const double2* h, double2* w, long N,
-                  double2* norm_partial, hipStream_t st) {
-  launch_maxpy_b(V, Addr(), ldv, nv, nullptr, h, 0, w, Addr(), N, norm_partial, 1, st);
 }
 
 void launch_maxpy_b(const double2* V, Addr av, long ldv, int nv, const int* nvt, const double2* h,
