@@ -254,10 +254,10 @@ def run_gpu(cfg, steps, warmup, prec):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
-    # Dominant kernel: the multifrontal coarse solve (k_mf_solve, one launch per tree height
-    # and pass). Device time from HIP event pairs around every coarse solve on the solve
-    # stream during the timed steps; bytes are the algorithmic factor and vector traffic.
-    # Unit: one coarse system (its 2H+1 launches).
+    # Dominant kernel: the multifrontal coarse solve (k_mf_sub for the bottom subtrees and
+    # k_mf_solve for each higher tree height, per pass). Device time from HIP event pairs
+    # around every coarse solve on the solve stream during the timed steps; bytes are the
+    # algorithmic factor and vector traffic. Unit: one coarse system (all its launches).
     systems = sum(x["coarse_systems"] for x in stats)
     launches = sum(x["coarse_solves"] for x in stats)
     cs_ms = sum(x["coarse_solve_ms"] for x in stats) / max(systems, 1)
@@ -775,8 +775,9 @@ def main():
                    "shift": str(cfg["s"]), "tol": cfg["tol"], "restart": cfg["restart"],
                    "nu": cfg["nu"], "omega": cfg["omega"], "precision": a.prec,
                    "iterations": g["iterations"]},
-        "roofline": {"kernel": "multifrontal coarse solve (k_mf_solve, one launch per tree "
-                               "height and pass; unit: one coarse system)", "bound": "hbm",
+        "roofline": {"kernel": "multifrontal coarse solve (k_mf_sub for the bottom subtrees, "
+                               "k_mf_solve per higher tree height and pass; unit: one coarse "
+                               "system)", "bound": "hbm",
                      "achieved": cs_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": cs_gbs / HBM_PEAK_GBS,
                      "traffic": measured_traffic() if (cfg["name"] == "p1_k400_n2048" and

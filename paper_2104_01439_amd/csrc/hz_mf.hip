@@ -13,7 +13,8 @@
 // Solve: forward (heights ascending) f = [b_I; 0] + children's u, z_I = S_v f_I,
 // u_v = f_B - G_v^T f_I; backward (heights descending) x_I = z_I - G_v x_B.
 // The factor is explicit (inverses and products), so each pass is a set of independent
-// matrix-vector products per height: 2 H + 1 dependent launches per solve.
+// matrix-vector products per height: at most 2 H + 1 dependent launches per solve, fewer with
+// the bottom subtrees (heights 0 .. T) in one launch per pass.
 
 #include <algorithm>
 #include <cstring>
