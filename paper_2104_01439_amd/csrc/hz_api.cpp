@@ -701,8 +701,11 @@ void vcycle_group(hz_problem* const* probs, const int* zp, int nb, const DevOp<T
         launch_stencil<T, T, T, T>(p, ST_SMOOTH, fine, c, Addr(N), f, af, x, Addr(N), nb, st);
         std::swap(c, x);
       }
-      launch_stencil<T, T, T, T>(p, ST_RESID, fine, c, Addr(N), f, af, sc.rf, Addr(N), nb, st);
-      launch_restrict<T>(p, pr0->M, pr0->Mc, rw, sc.rf, sc.rc, nb, Addr(N), Addr(Nc), st);
+      if (!launch_resid_restrict<T>(p, fine, c, Addr(N), f, af, pr0->Mc, rw, sc.rc, Addr(Nc), nb,
+                                    st)) {
+        launch_stencil<T, T, T, T>(p, ST_RESID, fine, c, Addr(N), f, af, sc.rf, Addr(N), nb, st);
+        launch_restrict<T>(p, pr0->M, pr0->Mc, rw, sc.rf, sc.rc, nb, Addr(N), Addr(Nc), st);
+      }
     }
   }
   if (phases & VC_COARSE) {
@@ -1402,6 +1405,7 @@ void apply_impl(hz_problem* pr, int op, const double2* x, const double2* f, doub
       case HZ_OP_COARSE_SOLVE: timed_coarse_solve<double>(pr, lv, x, y, st, b.own); break;
       case HZ_OP_COARSE_A: launch_stencil<double, double, double, double>(p, ST_APPLY, lv.coarse, x, o, nullptr, o, y, o, 1, st); break;
       case HZ_OP_RESID_RESTRICT:
+        if (launch_resid_restrict<double>(p, lv.fine, x, o, f, o, pr->Mc, pr->rw, y, o, 1, st)) break;
         launch_stencil<double, double, double, double>(p, ST_RESID, lv.fine, x, o, f, o, b.s64.rf, o, 1, st);
         launch_restrict<double>(p, pr->M, pr->Mc, pr->rw, b.s64.rf, y, 1, o, o, st);
         break;
@@ -1432,6 +1436,8 @@ void apply_impl(hz_problem* pr, int op, const double2* x, const double2* f, doub
     case HZ_OP_COARSE_SOLVE: timed_coarse_solve<float>(pr, lv, xin, yout, st, b.own); break;
     case HZ_OP_COARSE_A: launch_stencil<float, float, float, float>(p, ST_APPLY, lv.coarse, xin, o, nullptr, o, yout, o, 1, st); break;
     case HZ_OP_RESID_RESTRICT:
+      if (launch_resid_restrict<float>(p, lv.fine, xin, o, b.af32, o, pr->Mc, pr->frw, yout, o, 1, st))
+        break;
       launch_stencil<float, float, float, float>(p, ST_RESID, lv.fine, xin, o, b.af32, o, b.s32.rf, o, 1, st);
       launch_restrict<float>(p, pr->M, pr->Mc, pr->frw, b.s32.rf, yout, 1, o, o, st);
       break;

@@ -318,6 +318,107 @@ k_restrict(int Mf, int Mc, const T* __restrict__ rw, const V2<T>* __restrict__ r
   yc[i] = acc;
 }
 
+// Residual and restriction in one pass, P1 (Alg. 1: restrict residual): r_c = P^T (f - A u).
+// A workgroup owns RCX x RCY coarse points. It stages u on the fine points that the residuals
+// of its restriction footprint read (the footprint, 2 fine points around the coarse tile's
+// fine image, plus a 1-point halo), forms those residuals in registers with the stencil
+// kernel's tap order (dy, then dx ascending; so bitwise its residual) and stores them over the
+// staged u, then each thread restricts one coarse point from them in the restriction
+// kernel's order. The residual never goes to
+// memory; neighbouring tiles recompute their 3 shared footprint lines. Tiles in XCD bands as
+// in the stencil kernel.
+constexpr int RCX = 32, RCY = 8;
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_resid_restrict1(DevOp<T> op, const V2<T>* __restrict__ x, Addr ax, const V2<T>* __restrict__ f,
+                  Addr af, int Mc, const T* __restrict__ rw, V2<T>* __restrict__ yc, Addr ac) {
+  constexpr int W2 = 9;
+  constexpr int RWD = 2 * RCX - 1 + 4, RHD = 2 * RCY - 1 + 4;   // residual region
+  constexpr int UWD = RWD + 2, UHD = RHD + 2;                   // staged u
+  __shared__ V2<T> ut[UHD][UWD];
+  V2<T>* rt = &ut[0][0];      // the residuals (RHD x RWD) replace u once every wave has read it
+  constexpr int NQ = (RWD * RHD + 255) / 256;
+  const int M = op.M;
+  const int ntx = (Mc + RCX - 1) / RCX, nty = (Mc + RCY - 1) / RCY;
+  const int per = (ntx * nty + 7) / 8;
+  const int tnum = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (tnum >= ntx * nty) return;               // whole workgroup, before any barrier
+  const int bz = blockIdx.y;
+  const V2<T>* __restrict__ coef = op.ctab ? op.ctab[bz] : op.coef;
+  x += ax.at(bz);
+  f += af.at(bz);
+  yc += ac.at(bz);
+  const int A0 = (tnum % ntx) * RCX, B0 = (tnum / ntx) * RCY;
+  const int ra0 = 2 * A0 - 2, rb0 = 2 * B0 - 2;       // residual region origin
+  const int ua0 = ra0 - 1, ub0 = rb0 - 1;             // staged u origin
+  V2<T> fq[NQ];               // f at this thread's residual points, requested with u
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int idx = threadIdx.x + 256 * q;
+    const int ly = idx / RWD, lx = idx - ly * RWD;
+    const int a = ra0 + lx, b = rb0 + ly;
+    fq[q] = (idx < RWD * RHD && a >= 0 && a < M && b >= 0 && b < M) ? f[long(b) * M + a]
+                                                                    : czero<T>();
+  }
+  for (int idx = threadIdx.x; idx < UWD * UHD; idx += 256) {
+    const int ly = idx / UWD, lx = idx - ly * UWD;
+    const int a = ua0 + lx, b = ub0 + ly;
+    ut[ly][lx] = (a >= 0 && a < M && b >= 0 && b < M) ? x[long(b) * M + a] : czero<T>();
+  }
+  __syncthreads();
+  V2<T> rq[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int idx = threadIdx.x + 256 * q;
+    const int ly = idx / RWD, lx = idx - ly * RWD;
+    const int a = ra0 + lx, b = rb0 + ly;
+    V2<T> r = czero<T>();
+    if (idx < RWD * RHD && a >= 0 && a < M && b >= 0 && b < M) {
+      const int reg = region(b, M) * 3 + region(a, M);
+      V2<T> acc = czero<T>();
+      sfor<-1, 2>([&](auto dy_) {
+        constexpr int dy = decltype(dy_)::value;
+        sfor<-1, 2>([&](auto dx_) {
+          constexpr int dx = decltype(dx_)::value;
+          if constexpr (couples(1, 0, 0, dx, dy)) {
+            constexpr int off = (dy + 1) * 3 + (dx + 1);
+            cfma(acc, coef[reg * W2 + off], ut[ly + 1 + dy][lx + 1 + dx]);
+          }
+        });
+      });
+      r = csub<T>(fq[q], acc);
+    }
+    rq[q] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int idx = threadIdx.x + 256 * q;
+    if (idx < RWD * RHD) rt[idx] = rq[q];
+  }
+  __syncthreads();
+  const int A = A0 + int(threadIdx.x) % RCX, B = B0 + int(threadIdx.x) / RCX;
+  if (A >= Mc || B >= Mc) return;
+  V2<T> acc = czero<T>();
+#pragma unroll
+  for (int dy = -2; dy <= 2; ++dy) {
+    const int b = 2 * B + dy;
+    if (b < 0 || b >= M) continue;
+#pragma unroll
+    for (int dx = -2; dx <= 2; ++dx) {
+      const int a = 2 * A + dx;
+      if (a < 0 || a >= M) continue;
+      const T wt = rw[(dy + 2) * 5 + dx + 2];
+      if (wt != T(0)) {
+        const V2<T> v = rt[(b - rb0) * RWD + (a - ra0)];
+        acc.x += wt * v.x;
+        acc.y += wt * v.y;
+      }
+    }
+  }
+  yc[long(B) * Mc + A] = acc;
+}
+
 // yf(a, b) (+)= sum over coarse (A, B) with |a - 2A|, |b - 2B| <= 2P of RW[cls(A,B)][.][.] xc.
 // One thread per coarse point (At, Bt) forms the 2 x 2 fine points (2 At + i, 2 Bt + j): their
 // coarse neighbourhoods are the same (2P+1)^2 points (held in registers for P <= 2), and a
@@ -537,6 +638,15 @@ int forced_variant() {
   return (e && *e) ? std::atoi(e) : -1;
 }
 
+// HZ_FUSE_RR=0: the residual and the restriction as two passes (for comparison).
+bool resid_restrict_disabled() {
+  static const bool off = [] {
+    const char* e = std::getenv("HZ_FUSE_RR");
+    return e && e[0] == '0';
+  }();
+  return off;
+}
+
 // HZ_FUSE_PC=0: the coarse correction as its own prolongation-add pass (for comparison).
 bool smooth_pc_disabled() {
   static const bool off = [] {
@@ -608,6 +718,19 @@ bool launch_smooth_pc(int p, const DevOp<T>& op, const V2<T>* x, Addr ax, const 
   return true;
 }
 
+template <typename T>
+bool launch_resid_restrict(int p, const DevOp<T>& op, const V2<T>* x, Addr ax, const V2<T>* f,
+                           Addr af, int Mc, const T* rw, V2<T>* yc, Addr ac, int nbatch,
+                           hipStream_t st) {
+  if (op.pn || p != 1 || resid_restrict_disabled()) return false;
+  if (op.M != 2 * (Mc - 1) + 1) throw std::runtime_error("resid_restrict: lattice sizes");
+  const int ntiles = ((Mc + RCX - 1) / RCX) * ((Mc + RCY - 1) / RCY);
+  k_resid_restrict1<T><<<dim3(8 * ((ntiles + 7) / 8), nbatch), 256, 0, st>>>(op, x, ax, f, af, Mc,
+                                                                             rw, yc, ac);
+  HZ_HIP(hipGetLastError());
+  return true;
+}
+
 template <typename T, typename TF>
 void launch_jacobi0(int p, const DevOp<T>& op, const V2<TF>* f, Addr fs, V2<T>* y, Addr ys,
                     int nbatch, hipStream_t st) {
@@ -675,6 +798,10 @@ void launch_f2d(const float2* x, double2* y, long n, hipStream_t st) {
 }
 
 // Instantiations used by the driver.
+template bool launch_resid_restrict<double>(int, const DevOp<double>&, const double2*, Addr,
+    const double2*, Addr, int, const double*, double2*, Addr, int, hipStream_t);
+template bool launch_resid_restrict<float>(int, const DevOp<float>&, const float2*, Addr,
+    const float2*, Addr, int, const float*, float2*, Addr, int, hipStream_t);
 template bool launch_smooth_pc<double>(int, const DevOp<double>&, const double2*, Addr,
     const double2*, Addr, int, const double*, const double2*, Addr, double2*, Addr, int, hipStream_t);
 template bool launch_smooth_pc<float>(int, const DevOp<float>&, const float2*, Addr,

@@ -138,6 +138,14 @@ template <typename T>
 bool launch_smooth_pc(int p, const DevOp<T>& op, const V2<T>* x, Addr ax, const V2<T>* ec,
                       Addr ac, int Mc, const T* rw, const V2<T>* f, Addr af, V2<T>* y, Addr ay,
                       int nbatch, hipStream_t st);
+// Residual and restriction in one pass (Alg. 1: restrict residual): yc = P^T (f - A x), fine
+// lattice op.M, coarse Mc, batch offsets as for launch_stencil; bitwise the ST_RESID pass
+// followed by launch_restrict. Returns false (launching nothing) where it is not provided:
+// per-point operators and p > 1.
+template <typename T>
+bool launch_resid_restrict(int p, const DevOp<T>& op, const V2<T>* x, Addr ax, const V2<T>* f,
+                           Addr af, int Mc, const T* rw, V2<T>* yc, Addr ac, int nbatch,
+                           hipStream_t st);
 // The same for per-point operators (op.pn = 1); called by launch_stencil.
 template <typename T, typename TX, typename TF, typename TY>
 void launch_stencil_pn(int p, int mode, const DevOp<T>& op, const V2<TX>* x, Addr ax,

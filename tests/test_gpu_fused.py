@@ -1,9 +1,12 @@
-"""The first post-smoothing sweep with the coarse-grid correction staged in the stencil tile
-(Alg. 1: add coarse grid correction, then postsmoothing) against the same V-cycle with the
-correction as its own prolongation-add pass (HZ_FUSE_PC=0, read once per process, so that
-side runs in a child process): bitwise equal in FP64 and with FP32 operators, for nu = 1,
-2, 3, ragged tiles, a batched solve, and the orders and operators that keep the two-pass
-form (P3, per-point operators). Both sides are also checked against the oracle's V-cycle."""
+"""The fused V-cycle passes against their two-pass forms: the first post-smoothing sweep with
+the coarse-grid correction staged in the stencil tile (Alg. 1: add coarse grid correction,
+then postsmoothing; P1, P2) and the residual with the restriction in one pass (Alg. 1:
+restrict residual; P1), against the same V-cycle with the correction as its own
+prolongation-add pass and the residual written then restricted (HZ_FUSE_PC=0, HZ_FUSE_RR=0,
+read once per process, so that side runs in a child process): bitwise equal in FP64 and
+with FP32 operators, for nu = 1, 2, 3, ragged tiles, a batched solve, and the orders and
+operators that keep the two-pass forms (P3, per-point operators). Both sides are also
+checked against the oracle's V-cycle and its residual restriction."""
 
 import json
 import os
@@ -35,8 +38,10 @@ for i, (k, n, p, s, nu) in enumerate(CASES):
     print("[unfused] case", i, flush=True)
     pr = hz.Problem(k, 1.0 / n, p, s, nu=nu)
     f = torch.from_numpy(inputs.random_complex(pr.N, seed=50 + i)).cuda()
+    x = torch.from_numpy(inputs.random_complex(pr.N, seed=60 + i)).cuda()
     for prec in ("fp64", "mixed"):
         out[f"v{i}_{prec}"] = pr.apply("VCYCLE", f, prec=prec).cpu().numpy()
+        out[f"r{i}_{prec}"] = pr.apply("RESID_RESTRICT", x, f, prec=prec).cpu().numpy()
     pr.close()
 print("[unfused] batched", flush=True)
 pr = hz.Problem(12.0, 1 / 64, 1, 1 + 0.5j)
@@ -59,7 +64,7 @@ print("RESULT ok", flush=True)
 def unfused(tmp_path_factory):
     out = str(tmp_path_factory.mktemp("fused") / "unfused.npz")
     code = f"ROOT = {ROOT!r}\nCASES = {CASES!r}\nOUT = {out!r}\n" + CHILD
-    env = dict(os.environ, HZ_FUSE_PC="0")
+    env = dict(os.environ, HZ_FUSE_PC="0", HZ_FUSE_RR="0")
     p = subprocess.run([sys.executable, "-u", "-c", code], env=env, capture_output=True,
                        text=True, timeout=240)
     print(p.stdout[-2000:], p.stderr[-2000:], flush=True)
@@ -83,14 +88,20 @@ def test_fused_vcycle_equals_two_pass(hz, unfused, i):
     print(f"[fused] case {i}: k={k} n={n} p={p} nu={nu}", flush=True)
     pr = hz.Problem(k, 1.0 / n, p, s, nu=nu)
     f = inputs.random_complex(pr.N, seed=50 + i)
-    fd = torch.from_numpy(f).cuda()
+    x = inputs.random_complex(pr.N, seed=60 + i)
+    fd, xd = torch.from_numpy(f).cuda(), torch.from_numpy(x).cuda()
     tg = TwoGrid(k, n, p, s, nu=nu, omega=0.6)
     ref = tg.vcycle(f)
-    for prec, tol in (("fp64", 1e-10), ("mixed", 2e-6)):
+    ref_rr = tg.P.T @ (f - tg.Aeps @ x)
+    for prec, tol, tol_rr in (("fp64", 1e-10, 1e-12), ("mixed", 2e-6, 2e-6)):
         z = pr.apply("VCYCLE", fd, prec=prec).cpu().numpy()
         assert np.array_equal(z, unfused[f"v{i}_{prec}"]), (i, prec)
         e = np.linalg.norm(z - ref) / np.linalg.norm(ref)
         assert e <= tol, (i, prec, e)
+        rc = pr.apply("RESID_RESTRICT", xd, fd, prec=prec).cpu().numpy()
+        assert np.array_equal(rc, unfused[f"r{i}_{prec}"]), (i, prec, "resid_restrict")
+        e = np.linalg.norm(rc - ref_rr) / np.linalg.norm(ref_rr)
+        assert e <= tol_rr, (i, prec, "resid_restrict", e)
     pr.close()
 
 
