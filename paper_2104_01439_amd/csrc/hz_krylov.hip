@@ -13,6 +13,7 @@ namespace {
 
 constexpr int EPT = 4;                 // elements per thread in the streaming kernels
 constexpr int CHUNK = 256 * EPT;       // elements per workgroup
+constexpr int MDOT_U = 2;              // basis vectors per step of k_mdot (4: no faster)
 
 template <typename TV>
 __global__ void __launch_bounds__(256)
@@ -33,17 +34,30 @@ k_mdot(const V2<TV>* __restrict__ V, Addr av, long ldv, int nv, const int* __res
     wv[q] = k < N ? w[k] : make_double2(0, 0);
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int i = 0; i < nv; ++i) {
-    const V2<TV>* vi = V + i * ldv;
-    double2 acc = make_double2(0, 0);
+  // MDOT_U basis vectors per step: their loads are in flight together
+  for (int i0 = 0; i0 < nv; i0 += MDOT_U) {
+    V2<TV> va[MDOT_U][EPT];
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const long k = base + q * 256;
-      if (k < N) cfma_conj(acc, cvt<double>(vi[k]), wv[q]);
+    for (int u = 0; u < MDOT_U; ++u)
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const long k = base + q * 256;
+        va[u][q] = (i0 + u < nv && k < N) ? V[(i0 + u) * ldv + k] : czero<TV>();
+      }
+#pragma unroll
+    for (int u = 0; u < MDOT_U; ++u) {
+      const int i = i0 + u;
+      if (i >= nv) break;
+      double2 acc = make_double2(0, 0);
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const long k = base + q * 256;
+        if (k < N) cfma_conj(acc, cvt<double>(va[u][q]), wv[q]);
+      }
+      acc.x = wave_sum(acc.x);
+      acc.y = wave_sum(acc.y);
+      if (lane == 0) { red[0][i][wave] = acc.x; red[1][i][wave] = acc.y; }
     }
-    acc.x = wave_sum(acc.x);
-    acc.y = wave_sum(acc.y);
-    if (lane == 0) { red[0][i][wave] = acc.x; red[1][i][wave] = acc.y; }
   }
   __syncthreads();
   if (threadIdx.x < nv) {
