@@ -101,8 +101,11 @@ def stencil_rates(cfg, prec, reps=20):
     passes = {
         "A0 apply": ("A0", x, None, yf, B["a0_apply"], 1),
         "Jacobi sweep": ("JACOBI", x, f, yf, B["jacobi_sweep"], 1),
-        "residual + restriction (2 kernels)": ("RESID_RESTRICT", x, f, yc,
-                                               B["residual"] + B["restriction"], 2),
+        # P1: one pass (the residual is never stored); otherwise the two passes
+        ("residual + restriction (one pass)" if p == 1 else "residual + restriction (2 kernels)"):
+            ("RESID_RESTRICT", x, f, yc,
+             B["resid_restrict_fused"] if p == 1 else B["residual"] + B["restriction"],
+             1 if p == 1 else 2),
         "restriction": ("RESTRICT", x, None, yc, B["restriction"], 1),
         "prolongation": ("PROLONG", xc, None, yf, B["prolongation"], 1),
     }

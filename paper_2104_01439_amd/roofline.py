@@ -13,9 +13,12 @@ FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix, published
 #   restriction      r read, r_c written (1/4)                   20
 #   prolongation     e_c read (1/4), P e_c written               20
 #   prolongation+add e_c read (1/4), u read, u + P e_c written   36
+#   residual + restriction in one pass (P1): u, f read, r_c written (1/4)           36
+#   sweep with the staged correction: u, f, e_c (1/4) read, u' written               52
 STENCIL_BYTES_PER_DOF = {"a0_apply": 32, "jacobi_first": 32, "jacobi_sweep": 48,
                          "residual": 48, "restriction": 20, "prolongation": 20,
-                         "prolongation_add": 36}
+                         "prolongation_add": 36, "resid_restrict_fused": 36,
+                         "sweep_staged_correction": 52}
 
 
 # Per-point operators (heterogeneous k), P1: the 7 stored couplings of the point (16 B each)
