@@ -910,6 +910,7 @@ k_mf_solve(CsJobs<T> jobs, int task0, long cstride) {
         const bool zr = r < s;
         const V2<T>* Xc = zr ? Fac + nd.Soff + r : Fac + nd.Goff + (r - s);
         const int ld = zr ? s : m;
+#pragma unroll 4
         for (int k = 0; k < s; ++k) {
           const V2<T> xv = Xc[long(k) * ld];
 #pragma unroll
@@ -952,6 +953,7 @@ k_mf_solve(CsJobs<T> jobs, int task0, long cstride) {
         }
         k0 = lane + 64 * PF;
       }
+#pragma unroll 4
       for (int k = k0; k < len; k += 64) {
         const V2<T> xv = xr[k];
 #pragma unroll
@@ -1019,6 +1021,7 @@ k_mf_solve(CsJobs<T> jobs, int task0, long cstride) {
       for (int h = 0; h < NR; ++h) acc[h] = czero<T>();
       if (lane < s) {
         const V2<T>* Sv = Fac + nd.Soff;     // symmetric: row k, entry lane = S[lane][k]
+#pragma unroll 4
         for (int k = 0; k < s; ++k) {
           const V2<T> xv = Sv[long(k) * s + lane];
 #pragma unroll
@@ -1031,6 +1034,7 @@ k_mf_solve(CsJobs<T> jobs, int task0, long cstride) {
       } else {
         const int rr = lane - s;
         const V2<T>* Gv = Fac + nd.Goff;     // (G^T f_I)[rr] = sum_i G[i][rr] f[i]
+#pragma unroll 4
         for (int i = 0; i < s; ++i) {
           const V2<T> xv = Gv[long(i) * m + rr];
 #pragma unroll
@@ -1057,6 +1061,7 @@ k_mf_solve(CsJobs<T> jobs, int task0, long cstride) {
 #pragma unroll
       for (int h = 0; h < NR; ++h) acc[h] = czero<T>();
       const V2<T>* GTv = Fac + nd.GToff;     // (G x_B)[lane] = sum_k G^T[k][lane] x_B[k]
+#pragma unroll 4
       for (int k = 0; k < m; ++k) {
         const V2<T> xv = GTv[long(k) * s + lane];
 #pragma unroll
