@@ -298,8 +298,7 @@ __device__ void sweep_invert(double2 (*Y)[SB][SB + 1], int w, double2* __restric
 
 // Before the first pass: the pivot row panel of tile 0 (workgroups 1..T) and the inverse of
 // the first pivot block (workgroup 0).
-__global__ void __launch_bounds__(256)
-k_sweep_first(SweepPass a) {
+__device__ __forceinline__ void sweep_first_body(const SweepPass& a) {
   __shared__ double2 Y[2][SB][SB + 1];
   const int tid = threadIdx.x;
   const int ld = a.T * SB;
@@ -327,8 +326,7 @@ k_sweep_first(SweepPass a) {
 
 // One pass of the sweep (pivot tile K). Workgroup 0 prepares the next pass's pivot inverse;
 // every other wave owns one upper tile (ti <= tj).
-__global__ void __launch_bounds__(256)
-k_sweep_pass(SweepPass a) {
+__device__ __forceinline__ void sweep_pass_body(const SweepPass& a) {
   __shared__ double2 Y[2][SB][SB + 1];
   const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
   const int wave = threadIdx.x >> 6;
@@ -409,8 +407,7 @@ k_sweep_pass(SweepPass a) {
 
 // Final pass: S = -X, the upper tiles negated in place and mirrored into the lower ones
 // (diagonal tiles from their upper triangle).
-__global__ void __launch_bounds__(256)
-k_sweep_last(double2* __restrict__ X, int n, int T) {
+__device__ __forceinline__ void sweep_last_body(double2* __restrict__ X, int n, int T) {
   __shared__ double2 L[SB][SB + 1];
   int u = blockIdx.x;
   int ti = 0;
@@ -450,6 +447,54 @@ k_sweep_last(double2* __restrict__ X, int n, int T) {
     const int row = tj * SB + r, col = ti * SB + c;
     if (row < n && col < n) X[size_t(row) * n + col] = L[c][r];
   }
+}
+
+// The sweep of one block: entry kernels over the bodies above.
+__global__ void __launch_bounds__(256) k_sweep_first(SweepPass a) { sweep_first_body(a); }
+__global__ void __launch_bounds__(256) k_sweep_pass(SweepPass a) { sweep_pass_body(a); }
+__global__ void __launch_bounds__(256) k_sweep_last(double2* __restrict__ X, int n, int T) {
+  sweep_last_body(X, n, T);
+}
+
+// The pass state of block z of a batch at pivot tile K: the block at base + xoff, its two
+// alternating pivot row panels at W + woff and pivot inverses at R + roff.
+__device__ __forceinline__ SweepPass sweep_pass_of(const SweepNode& z, double2* base, double2* W,
+                                                   double2* R, int K, int* flag) {
+  SweepPass a;
+  const size_t ld = size_t(z.T) * SB;
+  a.X = base + z.xoff;
+  a.n = z.n;
+  a.T = z.T;
+  a.K = K;
+  a.Rc = W + z.woff + size_t(K & 1) * SB * ld;
+  a.Rn = W + z.woff + size_t((K + 1) & 1) * SB * ld;
+  a.Pc = R + z.roff + size_t(K & 1) * SB * SB;
+  a.Pn = R + z.roff + size_t((K + 1) & 1) * SB * SB;
+  a.flag = flag;
+  return a;
+}
+
+// Several blocks swept together, block blockIdx.y of the batch; workgroups beyond a block's
+// own range (its pass count, tile count) leave at once.
+__global__ void __launch_bounds__(256)
+k_sweep_first_b(double2* base, double2* W, double2* R, const SweepNode* __restrict__ zs, int* flag) {
+  const SweepNode z = zs[blockIdx.y];
+  if (int(blockIdx.x) > z.T) return;
+  sweep_first_body(sweep_pass_of(z, base, W, R, -1, flag));
+}
+__global__ void __launch_bounds__(256)
+k_sweep_pass_b(double2* base, double2* W, double2* R, const SweepNode* __restrict__ zs, int K,
+               int* flag) {
+  const SweepNode z = zs[blockIdx.y];
+  if (K >= z.T) return;
+  if (blockIdx.x > 0 && int(blockIdx.x - 1) * 4 >= z.T * (z.T + 1) / 2) return;
+  sweep_pass_body(sweep_pass_of(z, base, W, R, K, flag));
+}
+__global__ void __launch_bounds__(256)
+k_sweep_last_b(double2* base, const SweepNode* __restrict__ zs) {
+  const SweepNode z = zs[blockIdx.y];
+  if (int(blockIdx.x) >= z.T * (z.T + 1) / 2) return;
+  sweep_last_body(base + z.xoff, z.n, z.T);
 }
 
 __global__ void k_factor_to_f32(const double2* __restrict__ S, float2* __restrict__ Sf, size_t n) {
@@ -1326,6 +1371,17 @@ void sweep_inverse(double2* D, int n, double2* W, double2* R, int* flag, hipStre
     k_sweep_pass<<<1 + (nu + 3) / 4, 256, 0, st>>>(a);
   }
   k_sweep_last<<<nu, 256, 0, st>>>(D, n, nt);
+}
+
+void sweep_inverse_batch(double2* base, const SweepNode* zs, int nz, int maxT, double2* W,
+                         double2* R, int* flag, hipStream_t st) {
+  if (nz <= 0) return;
+  const int maxnu = maxT * (maxT + 1) / 2;
+  k_sweep_first_b<<<dim3(maxT + 1, nz), 256, 0, st>>>(base, W, R, zs, flag);
+  for (int K = 0; K < maxT; ++K)
+    k_sweep_pass_b<<<dim3(1 + (maxnu + 3) / 4, nz), 256, 0, st>>>(base, W, R, zs, K, flag);
+  k_sweep_last_b<<<dim3(maxnu, nz), 256, 0, st>>>(base, zs);
+  HZ_HIP(hipGetLastError());
 }
 
 namespace {

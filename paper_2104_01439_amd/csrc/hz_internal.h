@@ -328,6 +328,15 @@ void launch_factor_to_f32(const double2* S, float2* Sf, size_t n, hipStream_t st
 // sweep (W: 2 sweep_panel_elems(n), R: 2 sweep_pinv_elems() elements of work); sets *flag on a
 // zero or non-finite pivot.
 void sweep_inverse(double2* X, int n, double2* W, double2* R, int* flag, hipStream_t st);
+// The same for nz blocks at once (one launch per pass for all): block z is the n x n matrix at
+// base + zs[z].xoff with T = ceil(n / 32) tiles, its panel work at W + zs[z].woff
+// (sweep_panel_elems(n) elements) and R + zs[z].roff (sweep_pinv_elems()); maxT the largest T.
+struct SweepNode {
+  long xoff, woff, roff;
+  int n, T;
+};
+void sweep_inverse_batch(double2* base, const SweepNode* zs, int nz, int maxT, double2* W,
+                         double2* R, int* flag, hipStream_t st);
 // Device copy of the symbolic data (and of the factorisation's launch tables) of a mesh
 // class on the current device, built on first use with stream st and kept until the process
 // ends; returns the view on the device and, in host_copy, the same view held on the host.

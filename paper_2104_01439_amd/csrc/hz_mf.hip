@@ -568,6 +568,8 @@ struct MfHeightLaunch {
   int smax;                     // largest separator of the small inversions
   std::vector<int> big;         // nodes inverted by the sweep
   std::vector<long> bigoff;     // their fronts' offsets in the arena
+  size_t z0 = 0, z1 = 0;        // their sweep descriptors
+  int maxT = 0;                 // largest tile count among them
 };
 struct MfPlan {
   MfView view;                  // device pointers
@@ -579,6 +581,8 @@ struct MfPlan {
   const int2 *rows = nullptr, *ext = nullptr;
   const int *gj = nullptr, *parent = nullptr, *td = nullptr;
   const GemmDesc* gd = nullptr;
+  const SweepNode* zn = nullptr;   // sweep descriptors of the large separators, by height
+  long zw = 0, zr = 0;             // panel and pivot-inverse work of the largest height's batch
 };
 
 std::mutex g_plan_mu;
@@ -632,6 +636,7 @@ const MfPlan& mf_plan(const MfSym& sym, hipStream_t st) {
   std::vector<int> gj, parent(sym.parent.begin(), sym.parent.end());
   std::vector<GemmDesc> gd;
   std::vector<int> td;
+  std::vector<SweepNode> zn;
   P->hl.assign(sym.H + 1, MfHeightLaunch());
   for (int h = 0; h <= sym.H; ++h) {
     MfHeightLaunch& L = P->hl[h];
@@ -661,6 +666,27 @@ const MfPlan& mf_plan(const MfSym& sym, hipStream_t st) {
       }
     }
     L.g1 = gj.size();
+    {
+      // the large separators of this height, swept together
+      L.z0 = zn.size();
+      long w = 0, r = 0;
+      for (int v : L.big) {
+        const MfNode& nd = sym.nodes[v];
+        SweepNode z;
+        z.xoff = nd.Soff;
+        z.woff = w;
+        z.roff = r;
+        z.n = nd.s;
+        z.T = (nd.s + 31) / 32;
+        w += long(sweep_panel_elems(size_t(nd.s)));
+        r += long(sweep_pinv_elems());
+        L.maxT = std::max(L.maxT, z.T);
+        zn.push_back(z);
+      }
+      L.z1 = zn.size();
+      P->zw = std::max(P->zw, w);
+      P->zr = std::max(P->zr, r);
+    }
     for (int phase = 0; phase < 2; ++phase) {
       L.d0[phase] = gd.size();
       L.t0[phase] = td.size();
@@ -702,7 +728,8 @@ const MfPlan& mf_plan(const MfSym& sym, hipStream_t st) {
       {nullptr, sizeof(MfView)},
       {fo.data(), fo.size() * 8}, {rows.data(), rows.size() * 8}, {ext.data(), ext.size() * 8},
       {gj.data(), gj.size() * 4}, {parent.data(), parent.size() * 4},
-      {gd.data(), gd.size() * sizeof(GemmDesc)}, {td.data(), td.size() * 4}};
+      {gd.data(), gd.size() * sizeof(GemmDesc)}, {td.data(), td.size() * 4},
+      {zn.data(), zn.size() * sizeof(SweepNode)}};
   size_t tot = 0;
   for (auto& q : parts) tot += al(q.second);
   char* d = nullptr;
@@ -737,6 +764,7 @@ const MfPlan& mf_plan(const MfSym& sym, hipStream_t st) {
   P->parent = reinterpret_cast<const int*>(at[17]);
   P->gd = reinterpret_cast<const GemmDesc*>(at[18]);
   P->td = reinterpret_cast<const int*>(at[19]);
+  P->zn = reinterpret_cast<const SweepNode*>(at[20]);
   HZ_HIP(hipMemcpyAsync(d, h.data(), tot, hipMemcpyHostToDevice, st));
   HZ_HIP(hipStreamSynchronize(st));   // h is local
   slot = std::move(P);
@@ -757,11 +785,11 @@ hz_status mf_factor(const MfSym& sym, const DevOp<double>& cop, double2* Fac, in
   const MfView& mv = P.view;
   double2* ws = nullptr;
   HZ_HIP(hipMallocAsync(reinterpret_cast<void**>(&ws), size_t(std::max<long>(P.arena, 1)) * 16, st));
-  // sweep work for the large inversions
+  // sweep work for the large inversions of one height (all swept together)
   double2 *W = nullptr, *R = nullptr;
-  if (P.maxbig > 0) {
-    HZ_HIP(hipMallocAsync(reinterpret_cast<void**>(&W), 2 * sweep_panel_elems(P.maxbig) * 16, st));
-    HZ_HIP(hipMallocAsync(reinterpret_cast<void**>(&R), 2 * sweep_pinv_elems() * 16, st));
+  if (P.zw > 0) {
+    HZ_HIP(hipMallocAsync(reinterpret_cast<void**>(&W), size_t(P.zw) * 16, st));
+    HZ_HIP(hipMallocAsync(reinterpret_cast<void**>(&R), size_t(P.zr) * 16, st));
   }
   HZ_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
   const int p = sym.p, Mc = sym.Mc;
@@ -793,8 +821,9 @@ hz_status mf_factor(const MfSym& sym, const DevOp<double>& cop, double2* Fac, in
       const long n2 = long(nd.s) * nd.s;
       k_mf_copy_ii<<<unsigned((n2 + 255) / 256), 256, 0, st>>>(ws + L.bigoff[q], nd.s,
                                                               nd.s + nd.m, Fac + nd.Soff);
-      sweep_inverse(Fac + nd.Soff, nd.s, W, R, flag, st);
     }
+    if (L.z1 > L.z0)
+      sweep_inverse_batch(Fac, P.zn + L.z0, int(L.z1 - L.z0), L.maxT, W, R, flag, st);
     for (int phase = 0; phase < 2; ++phase) {
       const int nt = int(L.t1[phase] - L.t0[phase]);
       if (nt > 0) k_mf_gemm<<<nt, 256, 0, st>>>(P.gd + L.d0[phase], P.td + L.t0[phase], Fac, ws);
